@@ -1,0 +1,259 @@
+/*
+ * spotlight.h -- C ABI of libspotlight.so, an MI355X (gfx950) implementation of
+ * the data-parallel hot path of the SPOTLIGHT real-time transient search:
+ * brute-force incoherent dedispersion of 8-bit multibeam filterbank blocks over
+ * a grid of trial DMs, the single-pulse search (boxcar matched filters of
+ * several widths, mean/sigma normalisation, S/N threshold, best width) and peak
+ * filtering into a candidate list (beam, DM, time, width, S/N).
+ *
+ * The problem statement follows the paper's "Dedispersion", "Single pulse
+ * search" and "Candidate optimisation" sections and Eq. (1).
+ *
+ * Conventions shared by every call
+ *  - Every function returns spl_status (SPL_OK = 0) and never throws; on error
+ *    a message for the calling thread is available from spl_last_error().
+ *  - Handles (spl_plan, spl_batch, spl_ranker) are opaque host objects.  They
+ *    are not thread-safe: use one handle from one thread (and one stream) at a
+ *    time.  Plans may be shared read-only by several batches.
+ *  - Ownership: the caller owns every device buffer (input blocks, workspace,
+ *    candidate buffer, run statistics, snippets, scores) and every stream.  The
+ *    library allocates host memory only, plus pinned host staging buffers; it
+ *    never calls hipMalloc.  Calls that take a stream only enqueue work on it;
+ *    device pointers must stay valid until the stream has passed that work.
+ *  - Device pointers are plain addresses from hipMalloc (or a caching allocator
+ *    on top of it) on the current HIP device.
+ */
+#ifndef SPOTLIGHT_H_
+#define SPOTLIGHT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+typedef int32_t spl_status;
+#define SPL_OK 0
+#define SPL_E_INVALID_ARG 1  /* an argument is out of range or inconsistent   */
+#define SPL_E_HIP 2          /* a HIP runtime call failed                      */
+#define SPL_E_OOM 3          /* host allocation failed or workspace too small  */
+#define SPL_E_CAPACITY 4     /* a result exceeded the capacity given           */
+#define SPL_E_UNSUPPORTED 5  /* valid input this build cannot process exactly  */
+#define SPL_E_NO_WEIGHTS 6   /* the ranker has no weights: use the plain path  */
+#define SPL_E_INTERNAL 7
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *spl_last_error(void);
+/* Library ABI version (major*10000 + minor*100 + patch). */
+int32_t spl_version(void);
+
+/* ------------------------------------------------------------------- plans */
+/*
+ * Observation band of one beam.
+ *   nchans      channels per block row; channel c has centre frequency
+ *               fch1_mhz + c*foff_mhz.  The reference frequency of Eq. (1) is
+ *               the highest channel centre (usually channel 0: the paper's
+ *               pipeline flips bands so that the highest frequency comes first;
+ *               either sign of foff_mhz is accepted).
+ *   tsamp_s     sampling interval in seconds.
+ *   n_out       samples owned by one block: candidates are searched at times
+ *               t in [0, n_out).  The block itself must carry n_in samples per
+ *               channel (spl_plan_info.n_in): the owned samples plus the
+ *               overlap tail of w_max - 1 + s_max samples needed to complete
+ *               every boxcar and every dispersion sweep (the paper reads blocks
+ *               with an overlap for the same reason).
+ *   norm_window length L of the segments over which mean and sigma of each DM
+ *               row are measured (0 means n_out).  Segment k covers owned
+ *               samples [k*L, min((k+1)*L, n_out)).
+ */
+typedef struct spl_band {
+    int32_t nchans;
+    int32_t n_out;
+    int32_t norm_window;
+    int32_t reserved0;
+    double fch1_mhz;
+    double foff_mhz;
+    double tsamp_s;
+} spl_band;
+
+/* A sub-range of the DM plan: trials dm_start + k*dm_step, k < n_trials
+ * (pc cm^-3).  Sub-ranges are concatenated in the order given. */
+typedef struct spl_dm_range {
+    double dm_start;
+    double dm_step;
+    int32_t n_trials;
+    int32_t reserved0;
+} spl_dm_range;
+
+#define SPL_MAX_STENCILS 4
+/* Peak filters applied in order (the paper uses a 3x3 then an 11x11 window in
+ * the DM-time plane).  Filter k keeps a point when no other surviving point
+ * within |dDM index| <= rd[k] and |dt| <= rt[k] has a larger key
+ * (S/N, -DM index, -t).  Passing NULL selects {(1,1), (5,5)}. */
+typedef struct spl_search_opts {
+    int32_t n_stencils;
+    int32_t stencil_rd[SPL_MAX_STENCILS];
+    int32_t stencil_rt[SPL_MAX_STENCILS];
+} spl_search_opts;
+
+typedef struct spl_plan spl_plan;
+
+typedef struct spl_plan_info {
+    int32_t nchans;
+    int32_t ndm;          /* DM trials, all sub-ranges */
+    int32_t n_out;
+    int32_t n_dd;         /* dedispersed samples per DM row: n_out + w_max - 1 */
+    int32_t n_in;         /* input samples per channel a block must carry: n_dd + s_max */
+    int32_t s_max;        /* largest delay in the table (samples) */
+    int32_t n_widths;
+    int32_t w_max;
+    int32_t norm_window;
+    int32_t n_segments;
+    int32_t n_stencils;
+    int32_t reserved0;
+    double threshold;     /* S/N threshold in sigma */
+} spl_plan_info;
+
+/*
+ * Build a plan: DM trials from the sub-ranges, the integer delay table
+ *   delay[d][c] = round-half-away( ((D * DM_d) * (1/f_c^2 - 1/f_ref^2)) / tsamp )
+ * of Eq. (1) with D = 4148.8064239 MHz^2 pc^-1 cm^3 s evaluated in binary64 in
+ * exactly this order, boxcar widths (strictly ascending, 1 <= w <= n_out) and
+ * the S/N threshold (> 0).  Each 8-bit sample sum must fit int32:
+ * nchans * 255 * w_max < 2^31, else SPL_E_UNSUPPORTED.  *out receives a new
+ * plan owned by the caller (spl_plan_destroy).
+ */
+spl_status spl_plan_create(const spl_band *band, const spl_dm_range *ranges, int32_t n_ranges,
+                           const int32_t *widths, int32_t n_widths, double threshold,
+                           const spl_search_opts *opts, spl_plan **out);
+
+/*
+ * As spl_plan_create, with an explicit host delay table delays[ndm][nchans]
+ * (non-negative int32, row-major by DM trial) and the DM value of each row
+ * (host, ndm doubles, used only for reporting).  Intended for tests.
+ */
+spl_status spl_plan_create_from_delays(const spl_band *band, const int32_t *delays,
+                                       const double *dms, int32_t ndm, const int32_t *widths,
+                                       int32_t n_widths, double threshold,
+                                       const spl_search_opts *opts, spl_plan **out);
+
+spl_status spl_plan_query(const spl_plan *plan, spl_plan_info *info);
+/* Copy the plan's delay table into host memory delays[ndm][nchans] (int32). */
+spl_status spl_plan_delays(const spl_plan *plan, int32_t *host_out);
+/* Copy the plan's DM values into host memory (ndm doubles). */
+spl_status spl_plan_dms(const spl_plan *plan, double *host_out);
+void spl_plan_destroy(spl_plan *plan);
+
+/* ----------------------------------------------------------------- batches */
+#define SPL_MODE_PLAIN_PER_BEAM 0   /* one launch sequence per beam, no graph     */
+#define SPL_MODE_PERSISTENT_GRAPH 1 /* all beams in one persistent launch, the    */
+                                    /* whole sequence captured once in a hipGraph */
+
+typedef struct spl_batch_opts {
+    int32_t mode;
+    int32_t reserved0;
+    int64_t hit_capacity;  /* boxcar hits held between search and peak filter; 0: default */
+} spl_batch_opts;
+
+/*
+ * Candidate record (32 bytes).  dm_index counts rows of the beam's plan; dm is
+ * that row's DM as float; snr is the binary64 S/N rounded to float; flags is 0
+ * from the search (the plain optimisation path and the ranker use it).
+ */
+typedef struct spl_candidate {
+    int32_t beam;
+    int32_t dm_index;
+    int32_t t_sample;
+    int32_t width;
+    int32_t boxcar_sum;
+    float snr;
+    float dm;
+    uint32_t flags;
+} spl_candidate;
+
+/* Written to device memory by every run. */
+typedef struct spl_run_stats {
+    int64_t n_hits;                          /* boxcar hits above threshold (true count) */
+    int64_t n_candidates;                    /* candidates after the peak filters (true count) */
+    int64_t n_after_stencil[SPL_MAX_STENCILS];
+    int32_t hit_overflow;                    /* 1: n_hits exceeded the hit capacity */
+    int32_t cand_overflow;                   /* 1: n_candidates exceeded the caller's capacity */
+} spl_run_stats;
+
+typedef struct spl_batch spl_batch;
+
+/*
+ * A batch searches n_beams beams per run, beam b with plans[b] (plans may
+ * differ in every parameter).  The plans must outlive the batch.
+ */
+spl_status spl_batch_create(const spl_plan *const *plans, int32_t n_beams,
+                            const spl_batch_opts *opts, spl_batch **out);
+/* Device workspace bytes the batch needs (plan tables + scratch). */
+spl_status spl_batch_workspace_size(const spl_batch *batch, size_t *bytes);
+/*
+ * Attach a caller-owned device workspace of at least the size above (256-byte
+ * aligned) and upload the plan tables into it (synchronous).  Must be called
+ * before the first run and again after spl_batch_set_tiles / spl_autotune
+ * changed the tiling.
+ */
+spl_status spl_batch_set_workspace(spl_batch *batch, void *d_ws, size_t bytes);
+
+/*
+ * Enqueue one search of one block per beam on `stream`.
+ *   d_blocks[b]  device pointer to beam b's block, uint8 [nchans][pitch],
+ *                channel-major, 16-byte aligned, holding at least n_in valid
+ *                samples per row.
+ *   pitches[b]   row pitch in bytes, a multiple of 16, >= n_in.
+ *   d_cands      device buffer of `capacity` records; receives the candidates
+ *                of all beams sorted by (beam, dm_index, t_sample).  If there
+ *                are more than `capacity`, the first `capacity` in that order
+ *                are written and d_stats->cand_overflow is set.
+ *   d_stats      device spl_run_stats, written by the run.
+ * Host arrays d_blocks/pitches are read before the call returns.  Results are
+ * complete when the stream reaches the end of the enqueued work; a run with
+ * d_stats->hit_overflow set is incomplete (raise the hit capacity).
+ */
+spl_status spl_batch_run(spl_batch *batch, const uint8_t *const *d_blocks, const int64_t *pitches,
+                         spl_candidate *d_cands, int64_t capacity, spl_run_stats *d_stats,
+                         hipStream_t stream);
+
+/* Read-only device views of the last run's intermediate results of one beam:
+ * the DM transform int32 [ndm][pitch_elems] (valid columns 0..n_dd-1) and the
+ * segment moments int64 S1[ndm][n_segments], S2[ndm][n_segments]. */
+spl_status spl_batch_dm_transform(const spl_batch *batch, int32_t beam, const int32_t **d_X,
+                                  int64_t *pitch_elems);
+spl_status spl_batch_moments(const spl_batch *batch, int32_t beam, const int64_t **d_S1,
+                             const int64_t **d_S2);
+
+/* Dedispersion tiling of one beam: dm_per_wave DM trials per wavefront (4 wavefronts
+ * per workgroup), time_groups groups of 256 samples per workgroup, chan_chunk channels
+ * staged in LDS per step (<= 256). */
+typedef struct spl_tiles {
+    int32_t dm_per_wave;
+    int32_t time_groups;
+    int32_t chan_chunk;
+    int32_t reserved0;
+} spl_tiles;
+spl_status spl_batch_get_tiles(const spl_batch *batch, int32_t beam, spl_tiles *tiles);
+/* Set the tiling of every beam sharing beam's plan; SPL_E_UNSUPPORTED if the shape is
+ * not compiled in or does not fit the LDS.  Call spl_batch_set_workspace afterwards. */
+spl_status spl_batch_set_tiles(spl_batch *batch, int32_t beam, const spl_tiles *tiles);
+
+void spl_batch_destroy(spl_batch *batch);
+
+/* ------------------------------------------------------------- test hooks */
+/* The normaliser of the search on device, for parity tests: for i < count,
+ * mu[i] = S1/n and sigma[i] = sqrt(n*S2 - S1^2)/n (exact 128-bit difference,
+ * rounded once to binary64; sigma = 0 when the difference is 0), from int64 device
+ * arrays n, s1, s2 (n > 0, s1 >= 0, s2 >= 0) into double device arrays. */
+spl_status spl_debug_mu_sigma(const int64_t *d_n, const int64_t *d_s1, const int64_t *d_s2, int64_t count,
+                              double *d_mu, double *d_sigma, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPOTLIGHT_H_ */

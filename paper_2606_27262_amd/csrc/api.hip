@@ -1,0 +1,823 @@
+// Host runtime and C ABI of libspotlight: plans (the library's own binary64 delay
+// table of Eq. (1)), batch layout in a caller-owned workspace, the launch sequence of
+// a search run, and its capture into a hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "spl_internal.h"
+#include "spotlight.h"
+
+#pragma STDC FP_CONTRACT OFF
+
+using namespace spl;
+
+// -------------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+static spl_status fail(spl_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e__ = (expr);                                                              \
+        if (e__ != hipSuccess)                                                                \
+            return fail(SPL_E_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e__),    \
+                        __FILE__, __LINE__);                                                  \
+    } while (0)
+
+extern "C" const char *spl_last_error(void) { return g_err.c_str(); }
+extern "C" int32_t spl_version(void) { return 100; }
+
+// --------------------------------------------------------------------- plans
+static constexpr double kDispersionConstant = 4148.8064239;  // MHz^2 pc^-1 cm^3 s
+
+struct spl_plan {
+    spl_band band;
+    std::vector<double> dms;
+    std::vector<int32_t> delays;   // [ndm][nch]
+    std::vector<int32_t> widths;
+    double theta = 0;
+    int nst = 2;
+    int rd[kMaxStencils] = {1, 5, 0, 0};
+    int rt[kMaxStencils] = {1, 5, 0, 0};
+    int nch = 0, ndm = 0, n_out = 0, n_dd = 0, n_in = 0, s_max = 0, w_max = 0, L = 0, nseg = 0;
+};
+
+static spl_status check_common(const spl_band *band, const int32_t *widths, int32_t n_widths, double threshold,
+                               const spl_search_opts *opts, spl_plan *p) {
+    if (!band) return fail(SPL_E_INVALID_ARG, "band is NULL");
+    if (band->nchans < 1) return fail(SPL_E_INVALID_ARG, "nchans must be >= 1 (got %d)", band->nchans);
+    if (band->n_out < 1) return fail(SPL_E_INVALID_ARG, "n_out must be >= 1 (got %d)", band->n_out);
+    if (!(band->tsamp_s > 0.0) || !std::isfinite(band->tsamp_s))
+        return fail(SPL_E_INVALID_ARG, "tsamp_s must be finite and > 0");
+    if (!std::isfinite(band->fch1_mhz) || !std::isfinite(band->foff_mhz))
+        return fail(SPL_E_INVALID_ARG, "frequencies must be finite");
+    const int L = band->norm_window ? band->norm_window : band->n_out;
+    if (L < 1 || L > band->n_out) return fail(SPL_E_INVALID_ARG, "norm_window must be in [0, n_out]");
+    if (!widths || n_widths < 1) return fail(SPL_E_INVALID_ARG, "at least one boxcar width is required");
+    if (n_widths > kMaxWidths) return fail(SPL_E_UNSUPPORTED, "at most %d widths are supported", kMaxWidths);
+    for (int i = 0; i < n_widths; ++i) {
+        if (widths[i] < 1 || widths[i] > band->n_out)
+            return fail(SPL_E_INVALID_ARG, "width %d out of [1, n_out]", widths[i]);
+        if (i && widths[i] <= widths[i - 1]) return fail(SPL_E_INVALID_ARG, "widths must be strictly ascending");
+    }
+    const int w_max = widths[n_widths - 1];
+    if (w_max > kMaxWmax) return fail(SPL_E_UNSUPPORTED, "w_max above %d is not supported", kMaxWmax);
+    if (!(threshold > 0.0) || !std::isfinite(threshold)) return fail(SPL_E_INVALID_ARG, "threshold must be > 0");
+    if ((int64_t)band->nchans * 255 * w_max >= ((int64_t)1 << 31))
+        return fail(SPL_E_UNSUPPORTED, "nchans*255*w_max must be below 2^31 for exact int32 boxcars");
+    const double xmax = (double)band->nchans * 255.0;
+    if ((double)L * xmax * xmax >= 9.0e18)
+        return fail(SPL_E_UNSUPPORTED, "segment sums of squares would overflow int64");
+    for (int c = 0; c < band->nchans; ++c) {
+        double f = band->fch1_mhz + (double)c * band->foff_mhz;
+        if (!(f > 0.0)) return fail(SPL_E_INVALID_ARG, "channel %d has a non-positive frequency", c);
+    }
+    if (opts) {
+        if (opts->n_stencils < 0 || opts->n_stencils > kMaxStencils)
+            return fail(SPL_E_INVALID_ARG, "n_stencils must be in [0, %d]", kMaxStencils);
+        p->nst = opts->n_stencils;
+        for (int k = 0; k < p->nst; ++k) {
+            if (opts->stencil_rd[k] < 0 || opts->stencil_rt[k] < 0 || opts->stencil_rd[k] > 1024 ||
+                opts->stencil_rt[k] > 1024)
+                return fail(SPL_E_INVALID_ARG, "stencil half-sizes must be in [0, 1024]");
+            p->rd[k] = opts->stencil_rd[k];
+            p->rt[k] = opts->stencil_rt[k];
+        }
+    }
+    p->band = *band;
+    p->band.norm_window = L;
+    p->widths.assign(widths, widths + n_widths);
+    p->theta = threshold;
+    p->nch = band->nchans;
+    p->n_out = band->n_out;
+    p->w_max = w_max;
+    p->L = L;
+    p->nseg = (band->n_out + L - 1) / L;
+    p->n_dd = band->n_out + w_max - 1;
+    return SPL_OK;
+}
+
+static spl_status finish_plan(spl_plan *p) {
+    int64_t smax = 0;
+    for (int32_t v : p->delays) smax = std::max<int64_t>(smax, v);
+    if ((int64_t)p->n_dd + smax > INT32_MAX / 2) return fail(SPL_E_UNSUPPORTED, "block length too large");
+    p->s_max = (int)smax;
+    p->n_in = p->n_dd + p->s_max;
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_plan_create(const spl_band *band, const spl_dm_range *ranges, int32_t n_ranges,
+                                      const int32_t *widths, int32_t n_widths, double threshold,
+                                      const spl_search_opts *opts, spl_plan **out) {
+    if (!out) return fail(SPL_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!ranges || n_ranges < 1) return fail(SPL_E_INVALID_ARG, "at least one DM range is required");
+    spl_plan *p = new (std::nothrow) spl_plan();
+    if (!p) return fail(SPL_E_OOM, "host allocation failed");
+    spl_status st = check_common(band, widths, n_widths, threshold, opts, p);
+    if (st != SPL_OK) { delete p; return st; }
+    for (int k = 0; k < n_ranges; ++k) {
+        const spl_dm_range &r = ranges[k];
+        if (r.n_trials < 1 || !(r.dm_start >= 0.0) || !(r.dm_step >= 0.0) || !std::isfinite(r.dm_start) ||
+            !std::isfinite(r.dm_step)) {
+            delete p;
+            return fail(SPL_E_INVALID_ARG, "DM range %d is invalid", k);
+        }
+        for (int d = 0; d < r.n_trials; ++d) p->dms.push_back(r.dm_start + (double)d * r.dm_step);
+    }
+    p->ndm = (int)p->dms.size();
+    if ((int64_t)p->ndm * p->nch > ((int64_t)1 << 31)) { delete p; return fail(SPL_E_UNSUPPORTED, "plan too large"); }
+    // Eq. (1): delay relative to the highest channel centre, rounded to the nearest
+    // sample (half-way cases away from zero), evaluated in binary64 in this order.
+    double fref = band->fch1_mhz;
+    for (int c = 0; c < p->nch; ++c) fref = std::max(fref, band->fch1_mhz + (double)c * band->foff_mhz);
+    p->delays.resize((size_t)p->ndm * p->nch);
+    for (int d = 0; d < p->ndm; ++d) {
+        for (int c = 0; c < p->nch; ++c) {
+            const double f = band->fch1_mhz + (double)c * band->foff_mhz;
+            const double v =
+                ((kDispersionConstant * p->dms[d]) * ((1.0 / (f * f)) - (1.0 / (fref * fref)))) / band->tsamp_s;
+            if (!(v < 1.0e9)) { delete p; return fail(SPL_E_UNSUPPORTED, "delay out of range"); }
+            p->delays[(size_t)d * p->nch + c] = (int32_t)std::llround(v);
+        }
+    }
+    st = finish_plan(p);
+    if (st != SPL_OK) { delete p; return st; }
+    *out = p;
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_plan_create_from_delays(const spl_band *band, const int32_t *delays, const double *dms,
+                                                  int32_t ndm, const int32_t *widths, int32_t n_widths,
+                                                  double threshold, const spl_search_opts *opts, spl_plan **out) {
+    if (!out) return fail(SPL_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!delays || ndm < 1) return fail(SPL_E_INVALID_ARG, "a delay table with ndm >= 1 is required");
+    spl_plan *p = new (std::nothrow) spl_plan();
+    if (!p) return fail(SPL_E_OOM, "host allocation failed");
+    spl_status st = check_common(band, widths, n_widths, threshold, opts, p);
+    if (st != SPL_OK) { delete p; return st; }
+    p->ndm = ndm;
+    p->delays.assign(delays, delays + (size_t)ndm * p->nch);
+    for (int32_t v : p->delays)
+        if (v < 0) { delete p; return fail(SPL_E_INVALID_ARG, "delays must be non-negative"); }
+    p->dms.resize(ndm);
+    for (int d = 0; d < ndm; ++d) p->dms[d] = dms ? dms[d] : (double)d;
+    st = finish_plan(p);
+    if (st != SPL_OK) { delete p; return st; }
+    *out = p;
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_plan_query(const spl_plan *p, spl_plan_info *info) {
+    if (!p || !info) return fail(SPL_E_INVALID_ARG, "NULL argument");
+    info->nchans = p->nch;
+    info->ndm = p->ndm;
+    info->n_out = p->n_out;
+    info->n_dd = p->n_dd;
+    info->n_in = p->n_in;
+    info->s_max = p->s_max;
+    info->n_widths = (int32_t)p->widths.size();
+    info->w_max = p->w_max;
+    info->norm_window = p->L;
+    info->n_segments = p->nseg;
+    info->n_stencils = p->nst;
+    info->reserved0 = 0;
+    info->threshold = p->theta;
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_plan_delays(const spl_plan *p, int32_t *host_out) {
+    if (!p || !host_out) return fail(SPL_E_INVALID_ARG, "NULL argument");
+    std::memcpy(host_out, p->delays.data(), p->delays.size() * sizeof(int32_t));
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_plan_dms(const spl_plan *p, double *host_out) {
+    if (!p || !host_out) return fail(SPL_E_INVALID_ARG, "NULL argument");
+    std::memcpy(host_out, p->dms.data(), p->dms.size() * sizeof(double));
+    return SPL_OK;
+}
+
+extern "C" void spl_plan_destroy(spl_plan *p) { delete p; }
+
+// ------------------------------------------------------------------- batches
+namespace {
+
+struct Tiles {
+    int dw = 8, j = 2, cc = 64;
+};
+
+// Everything that depends on one plan and its tiling.
+struct PlanLayout {
+    const spl_plan *plan = nullptr;
+    Tiles tiles;
+    int td = 0, ndm_pad = 0, ntile_d = 0, ntile_t = 0;
+    std::vector<int32_t> dcm;        // [nch][ndm_pad]
+    std::vector<int32_t> tile_base;  // [ntile_d][nch]
+    std::vector<int32_t> row_bytes;  // [ntile_d]
+    size_t off_dcm = 0, off_base = 0, off_dms = 0;
+};
+
+struct Region {
+    size_t off = 0, bytes = 0;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct spl_batch {
+    std::vector<const spl_plan *> plans;  // per beam
+    int nb = 0;
+    int mode = SPL_MODE_PLAIN_PER_BEAM;
+    int64_t hit_cap = 0;
+    std::vector<PlanLayout> layouts;       // unique plans
+    std::vector<int> layout_of_beam;
+    // global indexing
+    std::vector<int> row_base, chunk_base, item_base;   // [nb + 1]
+    int n_rows = 0, n_chunks = 0, n_items = 0;
+    int max_nst = 0, w_max = 0;
+    std::vector<DedispItem> items;
+    // shape groups for the persistent launch
+    struct Group { int dw, j; int item_lo, item_hi; size_t lds; int occ; };
+    std::vector<Group> groups;
+    std::vector<size_t> beam_lds;          // per beam (plain per-beam launches)
+    // workspace
+    size_t ws_bytes = 0;
+    char *ws = nullptr;
+    size_t off_beams = 0, off_items = 0;
+    std::vector<size_t> off_X, off_S, off_mu, off_sigma, off_T;   // per beam
+    size_t off_S_all = 0, bytes_S_all = 0;
+    size_t off_counts = 0, off_chunk_off = 0, off_block_sums = 0, off_row_start = 0;
+    size_t off_hits = 0, off_alive0 = 0, off_alive1 = 0, off_pos = 0, off_run = 0;
+    int n_block_sums = 0;
+    std::vector<int> xpitch;
+    std::vector<DevBeam> host_beams;
+    DevBeam *staging = nullptr;            // pinned copy of host_beams for async upload
+    hipEvent_t staging_done = nullptr;
+    bool staging_pending = false;
+    std::vector<const uint8_t *> cur_x;
+    std::vector<int64_t> cur_pitch;
+    // graph cache
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    const void *g_cands = nullptr, *g_stats = nullptr;
+    int64_t g_cap = -1;
+    bool tables_uploaded = false;
+};
+
+static spl_status layout_plan(PlanLayout &L) {
+    const spl_plan &p = *L.plan;
+    if (!dedisp_shape_supported(L.tiles.dw, L.tiles.j))
+        return fail(SPL_E_UNSUPPORTED, "dedispersion tile shape (%d, %d) is not compiled in", L.tiles.dw, L.tiles.j);
+    if (L.tiles.cc < 0 || L.tiles.cc > 256) return fail(SPL_E_UNSUPPORTED, "chan_chunk must be in [0, 256]");
+    L.td = 4 * L.tiles.dw;
+    L.ndm_pad = (p.ndm + L.td - 1) / L.td * L.td;
+    L.ntile_d = L.ndm_pad / L.td;
+    const int TT = 256 * L.tiles.j;
+    L.ntile_t = (p.n_dd + TT - 1) / TT;
+    L.dcm.assign((size_t)p.nch * L.ndm_pad, 0);
+    for (int c = 0; c < p.nch; ++c)
+        for (int d = 0; d < L.ndm_pad; ++d) {
+            const int ds = std::min(d, p.ndm - 1);   // pad by repeating the last trial
+            L.dcm[(size_t)c * L.ndm_pad + d] = p.delays[(size_t)ds * p.nch + c];
+        }
+    L.tile_base.assign((size_t)L.ntile_d * p.nch, 0);
+    L.row_bytes.assign(L.ntile_d, 0);
+    for (int k = 0; k < L.ntile_d; ++k) {
+        int span = 0;
+        for (int c = 0; c < p.nch; ++c) {
+            int lo = INT32_MAX, hi = 0;
+            for (int d = k * L.td; d < (k + 1) * L.td; ++d) {
+                const int v = L.dcm[(size_t)c * L.ndm_pad + d];
+                lo = std::min(lo, v);
+                hi = std::max(hi, v);
+            }
+            L.tile_base[(size_t)k * p.nch + c] = lo;
+            span = std::max(span, hi - lo);
+        }
+        L.row_bytes[k] = TT + 32 + (int)align_up((size_t)span, 16);
+    }
+    return SPL_OK;
+}
+
+static Tiles default_tiles(const spl_plan &p) {
+    Tiles t;
+    // enough work items to fill 256 compute units several times over
+    const int ttiles = (p.n_dd + 511) / 512;
+    t.dw = 8;
+    t.j = 2;
+    if ((int64_t)((p.ndm + 31) / 32) * ttiles < 1024) t.dw = 4;
+    if ((int64_t)((p.ndm + 15) / 16) * ((p.n_dd + 255) / 256) < 2048 && t.dw == 4) t.j = 1;
+    t.cc = 0;   // chosen from the LDS budget
+    return t;
+}
+
+static void choose_chunk(PlanLayout &L, size_t lds_budget) {
+    if (L.tiles.cc > 0) return;
+    const int rmax = *std::max_element(L.row_bytes.begin(), L.row_bytes.end());
+    int cc = (int)(lds_budget / (size_t)rmax);
+    cc = std::max(4, std::min(256, cc));
+    cc = cc / 4 * 4;
+    L.tiles.cc = cc;
+}
+
+static spl_status build_layout(spl_batch *B) {
+    // per-plan tables
+    for (auto &L : B->layouts) {
+        spl_status st = layout_plan(L);
+        if (st != SPL_OK) return st;
+        choose_chunk(L, 40 * 1024);
+    }
+    const int nb = B->nb;
+    B->row_base.assign(nb + 1, 0);
+    B->chunk_base.assign(nb + 1, 0);
+    B->item_base.assign(nb + 1, 0);
+    B->items.clear();
+    B->beam_lds.assign(nb, 0);
+    B->max_nst = 0;
+    B->w_max = 0;
+    // group beams by tile shape; items ordered by group, then beam, time tile, DM tile
+    B->groups.clear();
+    for (int b = 0; b < nb; ++b) {
+        const Tiles &t = B->layouts[B->layout_of_beam[b]].tiles;
+        int g = -1;
+        for (size_t k = 0; k < B->groups.size(); ++k)
+            if (B->groups[k].dw == t.dw && B->groups[k].j == t.j) g = (int)k;
+        if (g < 0) {
+            if ((int)B->groups.size() >= kMaxShapeGroups)
+                return fail(SPL_E_UNSUPPORTED, "at most %d distinct tile shapes per batch", kMaxShapeGroups);
+            B->groups.push_back({t.dw, t.j, 0, 0, 0, 0});
+        }
+    }
+    std::vector<std::vector<DedispItem>> per_beam(nb);
+    for (int b = 0; b < nb; ++b) {
+        const PlanLayout &L = B->layouts[B->layout_of_beam[b]];
+        const spl_plan &p = *L.plan;
+        const int TT = 256 * L.tiles.j;
+        for (int tt = 0; tt < L.ntile_t; ++tt)
+            for (int k = 0; k < L.ntile_d; ++k)
+                per_beam[b].push_back({b, k * L.td, tt * TT, L.row_bytes[k]});
+        const int rmax = *std::max_element(L.row_bytes.begin(), L.row_bytes.end());
+        B->beam_lds[b] = (size_t)L.tiles.cc * rmax;
+        B->max_nst = std::max(B->max_nst, p.nst);
+        B->w_max = std::max(B->w_max, p.w_max);
+    }
+    // rows / chunks in beam order; items grouped by shape
+    for (int b = 0; b < nb; ++b) {
+        const spl_plan &p = *B->plans[b];
+        B->row_base[b + 1] = B->row_base[b] + p.ndm;
+        B->chunk_base[b + 1] = B->chunk_base[b] + p.ndm * ((p.n_out + kBoxTile - 1) / kBoxTile);
+    }
+    B->n_rows = B->row_base[nb];
+    B->n_chunks = B->chunk_base[nb];
+    // items of beam b occupy [item_base[b], item_base[b] + its item count), in group order
+    for (auto &g : B->groups) {
+        g.item_lo = (int)B->items.size();
+        size_t lds = 0;
+        for (int b = 0; b < nb; ++b) {
+            const Tiles &t = B->layouts[B->layout_of_beam[b]].tiles;
+            if (t.dw != g.dw || t.j != g.j) continue;
+            B->item_base[b] = (int)B->items.size();
+            B->items.insert(B->items.end(), per_beam[b].begin(), per_beam[b].end());
+            lds = std::max(lds, B->beam_lds[b]);
+        }
+        g.item_hi = (int)B->items.size();
+        g.lds = lds;
+    }
+    B->n_items = (int)B->items.size();
+    if ((int64_t)B->n_chunks >= INT32_MAX / 2 || (int64_t)B->n_items >= INT32_MAX / 2)
+        return fail(SPL_E_UNSUPPORTED, "batch too large");
+
+    // workspace layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = align_up(off, 256);
+        size_t o = off;
+        off += bytes;
+        return o;
+    };
+    B->off_beams = take(sizeof(DevBeam) * nb);
+    B->off_items = take(sizeof(DedispItem) * std::max(1, B->n_items));
+    for (auto &L : B->layouts) {
+        const spl_plan &p = *L.plan;
+        L.off_dcm = take(L.dcm.size() * sizeof(int32_t));
+        L.off_base = take(L.tile_base.size() * sizeof(int32_t));
+        L.off_dms = take((size_t)p.ndm * sizeof(double));
+    }
+    B->off_X.assign(nb, 0);
+    B->off_S.assign(nb, 0);
+    B->off_mu.assign(nb, 0);
+    B->off_sigma.assign(nb, 0);
+    B->off_T.assign(nb, 0);
+    B->xpitch.assign(nb, 0);
+    size_t s_total = 0;
+    for (int b = 0; b < nb; ++b) s_total += (size_t)B->plans[b]->ndm * B->plans[b]->nseg * 2;
+    B->off_S_all = take(s_total * sizeof(int64_t));
+    B->bytes_S_all = s_total * sizeof(int64_t);
+    size_t s_off = B->off_S_all;
+    for (int b = 0; b < nb; ++b) {
+        const spl_plan &p = *B->plans[b];
+        B->xpitch[b] = (int)align_up((size_t)p.n_dd, 64);
+        B->off_X[b] = take((size_t)p.ndm * B->xpitch[b] * sizeof(int32_t));
+        B->off_S[b] = s_off;
+        s_off += (size_t)p.ndm * p.nseg * 2 * sizeof(int64_t);
+        B->off_mu[b] = take((size_t)p.ndm * p.nseg * sizeof(double));
+        B->off_sigma[b] = take((size_t)p.ndm * p.nseg * sizeof(double));
+        B->off_T[b] = take((size_t)p.ndm * p.nseg * p.widths.size() * sizeof(int32_t));
+    }
+    B->off_counts = take((size_t)B->n_chunks * sizeof(int32_t));
+    B->off_chunk_off = take((size_t)B->n_chunks * sizeof(int64_t));
+    B->n_block_sums = std::max(scan_blocks(B->n_chunks), scan_blocks(B->hit_cap)) + 1;
+    B->off_block_sums = take((size_t)B->n_block_sums * sizeof(int64_t));
+    B->off_row_start = take((size_t)(B->n_rows + 1) * sizeof(int64_t));
+    B->off_hits = take((size_t)B->hit_cap * sizeof(Hit));
+    B->off_alive0 = take((size_t)B->hit_cap);
+    B->off_alive1 = take((size_t)B->hit_cap);
+    B->off_pos = take((size_t)B->hit_cap * sizeof(int64_t));
+    B->off_run = take(sizeof(DevRun));
+    B->ws_bytes = align_up(off, 256);
+    B->tables_uploaded = false;
+    if (B->graph_exec) {
+        (void)hipGraphExecDestroy(B->graph_exec);
+        B->graph_exec = nullptr;
+    }
+    if (B->graph) {
+        (void)hipGraphDestroy(B->graph);
+        B->graph = nullptr;
+    }
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_batch_create(const spl_plan *const *plans, int32_t n_beams, const spl_batch_opts *opts,
+                                       spl_batch **out) {
+    if (!out) return fail(SPL_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!plans || n_beams < 1) return fail(SPL_E_INVALID_ARG, "at least one beam is required");
+    for (int b = 0; b < n_beams; ++b)
+        if (!plans[b]) return fail(SPL_E_INVALID_ARG, "plan of beam %d is NULL", b);
+    spl_batch *B = new (std::nothrow) spl_batch();
+    if (!B) return fail(SPL_E_OOM, "host allocation failed");
+    B->nb = n_beams;
+    B->plans.assign(plans, plans + n_beams);
+    B->mode = opts ? opts->mode : SPL_MODE_PLAIN_PER_BEAM;
+    if (B->mode != SPL_MODE_PLAIN_PER_BEAM && B->mode != SPL_MODE_PERSISTENT_GRAPH) {
+        delete B;
+        return fail(SPL_E_INVALID_ARG, "unknown mode %d", opts->mode);
+    }
+    B->hit_cap = (opts && opts->hit_capacity > 0) ? opts->hit_capacity : ((int64_t)1 << 24);
+    if (B->hit_cap > ((int64_t)1 << 31)) {
+        delete B;
+        return fail(SPL_E_UNSUPPORTED, "hit capacity above 2^31");
+    }
+    B->layout_of_beam.assign(n_beams, -1);
+    for (int b = 0; b < n_beams; ++b) {
+        int found = -1;
+        for (size_t k = 0; k < B->layouts.size(); ++k)
+            if (B->layouts[k].plan == plans[b]) found = (int)k;
+        if (found < 0) {
+            PlanLayout L;
+            L.plan = plans[b];
+            const Tiles t = default_tiles(*plans[b]);
+            L.tiles = t;
+            B->layouts.push_back(L);
+            found = (int)B->layouts.size() - 1;
+        }
+        B->layout_of_beam[b] = found;
+    }
+    spl_status st = build_layout(B);
+    if (st != SPL_OK) { delete B; return st; }
+    B->cur_x.assign(n_beams, nullptr);
+    B->cur_pitch.assign(n_beams, 0);
+    *out = B;
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_batch_workspace_size(const spl_batch *B, size_t *bytes) {
+    if (!B || !bytes) return fail(SPL_E_INVALID_ARG, "NULL argument");
+    *bytes = B->ws_bytes;
+    return SPL_OK;
+}
+
+static void fill_host_beams(spl_batch *B) {
+    B->host_beams.assign(B->nb, DevBeam{});
+    for (int b = 0; b < B->nb; ++b) {
+        const PlanLayout &L = B->layouts[B->layout_of_beam[b]];
+        const spl_plan &p = *B->plans[b];
+        DevBeam &d = B->host_beams[b];
+        std::memset(&d, 0, sizeof d);
+        d.x = B->cur_x[b];
+        d.pitch = B->cur_pitch[b];
+        d.dcm = (const int32_t *)(B->ws + L.off_dcm);
+        d.tile_base = (const int32_t *)(B->ws + L.off_base);
+        d.X = (int32_t *)(B->ws + B->off_X[b]);
+        d.S1 = (int64_t *)(B->ws + B->off_S[b]);
+        d.S2 = d.S1 + (size_t)p.ndm * p.nseg;
+        d.mu = (double *)(B->ws + B->off_mu[b]);
+        d.sigma = (double *)(B->ws + B->off_sigma[b]);
+        d.T = (int32_t *)(B->ws + B->off_T[b]);
+        d.dms = (const double *)(B->ws + L.off_dms);
+        d.theta = p.theta;
+        d.nch = p.nch;
+        d.ndm = p.ndm;
+        d.ndm_pad = L.ndm_pad;
+        d.n_dd = p.n_dd;
+        d.n_out = p.n_out;
+        d.L = p.L;
+        d.nseg = p.nseg;
+        d.nw = (int)p.widths.size();
+        d.xpitch = B->xpitch[b];
+        d.row_base = B->row_base[b];
+        d.chunk_base = B->chunk_base[b];
+        d.nchunk_t = (p.n_out + kBoxTile - 1) / kBoxTile;
+        d.chan_chunk = L.tiles.cc;
+        d.tile_dm = L.td;
+        d.beam = b;
+        d.w_max = p.w_max;
+        d.nst = p.nst;
+        for (int k = 0; k < kMaxStencils; ++k) {
+            d.rd[k] = p.rd[k];
+            d.rt[k] = p.rt[k];
+        }
+        for (size_t k = 0; k < p.widths.size(); ++k) d.widths[k] = p.widths[k];
+    }
+}
+
+extern "C" spl_status spl_batch_set_workspace(spl_batch *B, void *d_ws, size_t bytes) {
+    if (!B || !d_ws) return fail(SPL_E_INVALID_ARG, "NULL argument");
+    if (bytes < B->ws_bytes) return fail(SPL_E_OOM, "workspace too small: %zu < %zu bytes", bytes, B->ws_bytes);
+    if (((uintptr_t)d_ws & 255) != 0) return fail(SPL_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (B->staging_pending) {
+        HIP_TRY(hipEventSynchronize(B->staging_done));
+        B->staging_pending = false;
+    }
+    if (!B->staging) {
+        HIP_TRY(hipHostMalloc((void **)&B->staging, sizeof(DevBeam) * B->nb, hipHostMallocDefault));
+        HIP_TRY(hipEventCreateWithFlags(&B->staging_done, hipEventDisableTiming));
+    }
+    B->ws = (char *)d_ws;
+    for (auto &L : B->layouts) {
+        HIP_TRY(hipMemcpy(B->ws + L.off_dcm, L.dcm.data(), L.dcm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(B->ws + L.off_base, L.tile_base.data(), L.tile_base.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(B->ws + L.off_dms, L.plan->dms.data(), L.plan->dms.size() * sizeof(double),
+                          hipMemcpyHostToDevice));
+    }
+    if (B->n_items)
+        HIP_TRY(hipMemcpy(B->ws + B->off_items, B->items.data(), B->items.size() * sizeof(DedispItem),
+                          hipMemcpyHostToDevice));
+    fill_host_beams(B);
+    HIP_TRY(hipMemcpy(B->ws + B->off_beams, B->host_beams.data(), sizeof(DevBeam) * B->nb, hipMemcpyHostToDevice));
+    for (auto &g : B->groups) {
+        int occ = 0;
+        HIP_TRY(prepare_dedisp(g.dw, g.j, g.lds, &occ));
+        g.occ = std::max(1, occ);
+    }
+    for (int b = 0; b < B->nb; ++b) {
+        const Tiles &t = B->layouts[B->layout_of_beam[b]].tiles;
+        int occ = 0;
+        HIP_TRY(prepare_dedisp(t.dw, t.j, B->beam_lds[b], &occ));
+    }
+    if (B->graph_exec) {
+        (void)hipGraphExecDestroy(B->graph_exec);
+        B->graph_exec = nullptr;
+    }
+    if (B->graph) {
+        (void)hipGraphDestroy(B->graph);
+        B->graph = nullptr;
+    }
+    B->tables_uploaded = true;
+    return SPL_OK;
+}
+
+// The launch sequence of one beam range [b_lo, b_hi).
+static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persistent, spl_candidate *cands,
+                                int64_t cand_cap, spl_run_stats *stats, hipStream_t s) {
+    const DevBeam *beams = (const DevBeam *)(B->ws + B->off_beams);
+    const DedispItem *items = (const DedispItem *)(B->ws + B->off_items);
+    DevRun *run = (DevRun *)(B->ws + B->off_run);
+    const int row_lo = B->row_base[b_lo], row_hi = B->row_base[b_hi];
+    const int chunk_lo = B->chunk_base[b_lo], chunk_hi = B->chunk_base[b_hi];
+    int32_t *counts = (int32_t *)(B->ws + B->off_counts) + chunk_lo;
+    int64_t *chunk_off = (int64_t *)(B->ws + B->off_chunk_off) + chunk_lo;
+    int64_t *block_sums = (int64_t *)(B->ws + B->off_block_sums);
+    int64_t *row_start = (int64_t *)(B->ws + B->off_row_start) + row_lo;
+    Hit *hits = (Hit *)(B->ws + B->off_hits);
+    uint8_t *alive[2] = {(uint8_t *)(B->ws + B->off_alive0), (uint8_t *)(B->ws + B->off_alive1)};
+    int64_t *pos = (int64_t *)(B->ws + B->off_pos);
+    const int64_t cap = B->hit_cap;
+
+    // 1. dedispersion (+ moments)
+    if (persistent) {
+        for (size_t g = 0; g < B->groups.size(); ++g) {
+            const auto &G = B->groups[g];
+            const int n = G.item_hi - G.item_lo;
+            if (n <= 0) continue;
+            const int grid = std::min(n, G.occ * 256);
+            HIP_TRY(launch_dedisp(G.dw, G.j, beams, items, G.item_lo, G.item_hi, &run->queue[g], grid, G.lds, s));
+        }
+    } else {
+        for (int b = b_lo; b < b_hi; ++b) {
+            const Tiles &t = B->layouts[B->layout_of_beam[b]].tiles;
+            const int lo = B->item_base[b];
+            const PlanLayout &L = B->layouts[B->layout_of_beam[b]];
+            const int hi = lo + L.ntile_d * L.ntile_t;
+            HIP_TRY(launch_dedisp(t.dw, t.j, beams, items, lo, hi, nullptr, hi - lo, B->beam_lds[b], s));
+        }
+    }
+    // 2. normaliser and integer thresholds
+    HIP_TRY(launch_thresholds(beams, b_lo, b_hi, row_lo, row_hi, s));
+    // 3. boxcar hits: count, scan, emit in (row, t) order
+    int w_max = 1;
+    int max_nst = 0;
+    for (int b = b_lo; b < b_hi; ++b) {
+        w_max = std::max(w_max, B->plans[b]->w_max);
+        max_nst = std::max(max_nst, B->plans[b]->nst);
+    }
+    HIP_TRY(launch_boxcar(false, beams, b_lo, b_hi, chunk_lo, chunk_hi, w_max, counts, nullptr, nullptr, 0, s));
+    HIP_TRY(launch_scan_i32(counts, nullptr, chunk_hi - chunk_lo, block_sums, chunk_off, &run->n_hits, s));
+    HIP_TRY(launch_row_start(beams, b_lo, b_hi, row_lo, row_hi, chunk_lo, chunk_off, &run->n_hits, cap, row_start,
+                             s));
+    HIP_TRY(launch_boxcar(true, beams, b_lo, b_hi, chunk_lo, chunk_hi, w_max, nullptr, chunk_off, hits, cap, s));
+    // 4. peak filters, then ordered compaction into candidate records
+    const uint8_t *in = nullptr;
+    for (int k = 0; k < max_nst; ++k) {
+        uint8_t *o = alive[k & 1];
+        HIP_TRY(launch_nms(beams, b_lo, b_hi, row_lo, hits, &run->n_hits, cap, row_start, k, in, o,
+                           &run->n_alive[k], s));
+        in = o;
+    }
+    if (max_nst) {
+        HIP_TRY(launch_scan_u8(in, &run->n_hits, cap, block_sums, pos, &run->n_cand_beam, s));
+        HIP_TRY(launch_scatter(beams, b_lo, b_hi, hits, &run->n_hits, cap, in, pos, &run->n_cand_total, cands,
+                               cand_cap, s));
+    } else {
+        HIP_TRY(launch_scatter(beams, b_lo, b_hi, hits, &run->n_hits, cap, nullptr, nullptr, &run->n_cand_total,
+                               cands, cand_cap, s));
+    }
+    HIP_TRY(launch_pass_end(run, stats, cap, max_nst, s));
+    return SPL_OK;
+}
+
+static spl_status enqueue_all(spl_batch *B, spl_candidate *cands, int64_t cap, spl_run_stats *stats,
+                              hipStream_t s) {
+    DevRun *run = (DevRun *)(B->ws + B->off_run);
+    HIP_TRY(launch_fill_u64((uint64_t *)run, (int64_t)(sizeof(DevRun) / 8), 0, s));
+    HIP_TRY(launch_fill_u64((uint64_t *)stats, (int64_t)(sizeof(spl_run_stats) / 8), 0, s));
+    if (B->mode == SPL_MODE_PERSISTENT_GRAPH) {
+        spl_status st = enqueue_range(B, 0, B->nb, true, cands, cap, stats, s);
+        if (st != SPL_OK) return st;
+    } else {
+        for (int b = 0; b < B->nb; ++b) {
+            spl_status st = enqueue_range(B, b, b + 1, false, cands, cap, stats, s);
+            if (st != SPL_OK) return st;
+        }
+    }
+    HIP_TRY(launch_finalize(run, stats, cap, s));
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_batch_run(spl_batch *B, const uint8_t *const *d_blocks, const int64_t *pitches,
+                                    spl_candidate *d_cands, int64_t capacity, spl_run_stats *d_stats,
+                                    hipStream_t stream) {
+    static_assert(sizeof(spl_run_stats) % 8 == 0, "stats are cleared in 8-byte words");
+    static_assert(sizeof(DevRun) % 8 == 0, "run state is cleared in 8-byte words");
+    if (!B || !d_blocks || !pitches || !d_stats) return fail(SPL_E_INVALID_ARG, "NULL argument");
+    if (!B->tables_uploaded) return fail(SPL_E_INVALID_ARG, "spl_batch_set_workspace was not called");
+    if (capacity < 0 || (capacity > 0 && !d_cands)) return fail(SPL_E_INVALID_ARG, "bad candidate buffer");
+    if (((uintptr_t)d_stats & 7) != 0) return fail(SPL_E_INVALID_ARG, "d_stats must be 8-byte aligned");
+    bool changed = false;
+    for (int b = 0; b < B->nb; ++b) {
+        const spl_plan &p = *B->plans[b];
+        if (!d_blocks[b]) return fail(SPL_E_INVALID_ARG, "block of beam %d is NULL", b);
+        if (((uintptr_t)d_blocks[b] & 15) != 0) return fail(SPL_E_INVALID_ARG, "block of beam %d is not 16-byte aligned", b);
+        if (pitches[b] < p.n_in || (pitches[b] & 15) != 0)
+            return fail(SPL_E_INVALID_ARG, "pitch of beam %d must be a multiple of 16 and >= n_in = %d", b, p.n_in);
+        if (d_blocks[b] != B->cur_x[b] || pitches[b] != B->cur_pitch[b]) changed = true;
+    }
+    if (changed) {
+        if (B->staging_pending) HIP_TRY(hipEventSynchronize(B->staging_done));
+        for (int b = 0; b < B->nb; ++b) {
+            B->cur_x[b] = d_blocks[b];
+            B->cur_pitch[b] = pitches[b];
+            B->host_beams[b].x = d_blocks[b];
+            B->host_beams[b].pitch = pitches[b];
+        }
+        std::memcpy(B->staging, B->host_beams.data(), sizeof(DevBeam) * B->nb);
+        HIP_TRY(hipMemcpyAsync(B->ws + B->off_beams, B->staging, sizeof(DevBeam) * B->nb, hipMemcpyHostToDevice,
+                               stream));
+        HIP_TRY(hipEventRecord(B->staging_done, stream));
+        B->staging_pending = true;
+    }
+    if (B->mode == SPL_MODE_PERSISTENT_GRAPH) {
+        if (stream == nullptr) return fail(SPL_E_INVALID_ARG, "graph mode needs a non-default stream");
+        if (!B->graph_exec || B->g_cands != d_cands || B->g_stats != d_stats || B->g_cap != capacity) {
+            if (B->graph_exec) { (void)hipGraphExecDestroy(B->graph_exec); B->graph_exec = nullptr; }
+            if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
+            HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            spl_status st = enqueue_all(B, d_cands, capacity, d_stats, stream);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(stream, &g);
+            if (st != SPL_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+            if (e != hipSuccess) return fail(SPL_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            B->graph = g;
+            HIP_TRY(hipGraphInstantiate(&B->graph_exec, B->graph, nullptr, nullptr, 0));
+            B->g_cands = d_cands;
+            B->g_stats = d_stats;
+            B->g_cap = capacity;
+        }
+        HIP_TRY(hipGraphLaunch(B->graph_exec, stream));
+        return SPL_OK;
+    }
+    return enqueue_all(B, d_cands, capacity, d_stats, stream);
+}
+
+extern "C" spl_status spl_batch_dm_transform(const spl_batch *B, int32_t beam, const int32_t **d_X,
+                                             int64_t *pitch_elems) {
+    if (!B || !d_X || !pitch_elems || beam < 0 || beam >= B->nb) return fail(SPL_E_INVALID_ARG, "bad argument");
+    if (!B->ws) return fail(SPL_E_INVALID_ARG, "no workspace attached");
+    *d_X = (const int32_t *)(B->ws + B->off_X[beam]);
+    *pitch_elems = B->xpitch[beam];
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_batch_moments(const spl_batch *B, int32_t beam, const int64_t **d_S1,
+                                        const int64_t **d_S2) {
+    if (!B || !d_S1 || !d_S2 || beam < 0 || beam >= B->nb) return fail(SPL_E_INVALID_ARG, "bad argument");
+    if (!B->ws) return fail(SPL_E_INVALID_ARG, "no workspace attached");
+    const spl_plan &p = *B->plans[beam];
+    *d_S1 = (const int64_t *)(B->ws + B->off_S[beam]);
+    *d_S2 = *d_S1 + (size_t)p.ndm * p.nseg;
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_batch_get_tiles(const spl_batch *B, int32_t beam, spl_tiles *tiles) {
+    if (!B || !tiles || beam < 0 || beam >= B->nb) return fail(SPL_E_INVALID_ARG, "bad argument");
+    const Tiles &t = B->layouts[B->layout_of_beam[beam]].tiles;
+    tiles->dm_per_wave = t.dw;
+    tiles->time_groups = t.j;
+    tiles->chan_chunk = t.cc;
+    tiles->reserved0 = 0;
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_batch_set_tiles(spl_batch *B, int32_t beam, const spl_tiles *tiles) {
+    if (!B || !tiles || beam < 0 || beam >= B->nb) return fail(SPL_E_INVALID_ARG, "bad argument");
+    if (!dedisp_shape_supported(tiles->dm_per_wave, tiles->time_groups))
+        return fail(SPL_E_UNSUPPORTED, "tile shape (%d, %d) is not compiled in", tiles->dm_per_wave,
+                    tiles->time_groups);
+    if (tiles->chan_chunk < 0 || tiles->chan_chunk > 256)
+        return fail(SPL_E_UNSUPPORTED, "chan_chunk must be in [0, 256] (0: from the LDS budget)");
+    PlanLayout &L = B->layouts[B->layout_of_beam[beam]];
+    const Tiles old = L.tiles;
+    L.tiles.dw = tiles->dm_per_wave;
+    L.tiles.j = tiles->time_groups;
+    L.tiles.cc = tiles->chan_chunk;
+    spl_status st = build_layout(B);
+    if (st == SPL_OK) {
+        const int rmax = *std::max_element(L.row_bytes.begin(), L.row_bytes.end());
+        if ((size_t)L.tiles.cc * rmax > 160 * 1024 - 256) st = fail(SPL_E_UNSUPPORTED, "tile does not fit the LDS");
+    }
+    if (st != SPL_OK) {
+        L.tiles = old;
+        (void)build_layout(B);
+        return st;
+    }
+    return SPL_OK;
+}
+
+extern "C" void spl_batch_destroy(spl_batch *B) {
+    if (!B) return;
+    if (B->staging_pending) (void)hipEventSynchronize(B->staging_done);
+    if (B->graph_exec) (void)hipGraphExecDestroy(B->graph_exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    if (B->staging_done) (void)hipEventDestroy(B->staging_done);
+    if (B->staging) (void)hipHostFree(B->staging);
+    delete B;
+}
+
+// ------------------------------------------------------------- test hook
+extern "C" spl_status spl_debug_mu_sigma(const int64_t *d_n, const int64_t *d_s1, const int64_t *d_s2,
+                                         int64_t count, double *d_mu, double *d_sigma, hipStream_t stream) {
+    if (count < 0 || (count > 0 && (!d_n || !d_s1 || !d_s2 || !d_mu || !d_sigma)))
+        return fail(SPL_E_INVALID_ARG, "bad argument");
+    HIP_TRY(launch_mu_sigma(d_n, d_s1, d_s2, count, d_mu, d_sigma, stream));
+    return SPL_OK;
+}

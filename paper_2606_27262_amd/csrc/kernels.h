@@ -1,0 +1,39 @@
+// Launchers of the HIP kernels (kernels.hip); every call enqueues on stream `s` and
+// returns the launch status.
+#pragma once
+
+#include "spl_internal.h"
+#include "spotlight.h"
+
+namespace spl {
+
+bool dedisp_shape_supported(int dw, int j);
+hipError_t prepare_dedisp(int dw, int j, size_t lds_bytes, int *blocks_per_cu);
+hipError_t launch_dedisp(int dw, int j, const DevBeam *beams, const DedispItem *items, int item_lo, int item_hi,
+                         int *queue, int grid, size_t lds_bytes, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_thresholds(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, int row_hi,
+                             hipStream_t s);
+hipError_t launch_boxcar(bool emit, const DevBeam *beams, int beam_lo, int beam_hi, int chunk_lo, int chunk_hi,
+                         int w_max, int32_t *counts, const int64_t *offsets, Hit *hits, int64_t cap,
+                         hipStream_t s);
+int scan_blocks(int64_t n_max);
+hipError_t launch_scan_i32(const int32_t *in, const int64_t *n_dev, int64_t n_max, int64_t *block_sums,
+                           int64_t *out, int64_t *total, hipStream_t s);
+hipError_t launch_scan_u8(const uint8_t *in, const int64_t *n_dev, int64_t n_max, int64_t *block_sums,
+                          int64_t *out, int64_t *total, hipStream_t s);
+hipError_t launch_row_start(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, int row_hi, int chunk_lo,
+                            const int64_t *chunk_off, const int64_t *n_hits, int64_t cap, int64_t *row_start,
+                            hipStream_t s);
+hipError_t launch_nms(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, const Hit *hits,
+                      const int64_t *n_hits, int64_t cap, const int64_t *row_start, int stencil,
+                      const uint8_t *alive_in, uint8_t *alive_out, int64_t *n_alive, hipStream_t s);
+hipError_t launch_scatter(const DevBeam *beams, int beam_lo, int beam_hi, const Hit *hits, const int64_t *n_hits,
+                          int64_t cap, const uint8_t *alive, const int64_t *pos, const int64_t *base,
+                          spl_candidate *cands, int64_t cand_cap, hipStream_t s);
+hipError_t launch_pass_end(DevRun *run, spl_run_stats *stats, int64_t hit_cap, int nst, hipStream_t s);
+hipError_t launch_finalize(DevRun *run, spl_run_stats *stats, int64_t cand_cap, hipStream_t s);
+hipError_t launch_mu_sigma(const int64_t *n, const int64_t *s1, const int64_t *s2, int64_t count, double *mu,
+                           double *sigma, hipStream_t s);
+
+}  // namespace spl

@@ -1,0 +1,778 @@
+// HIP kernels (gfx950) of the single-pulse search hot path.
+//
+//  k_dedisp      brute-force incoherent dedispersion (dedispersion section, Eq. (1)
+//                delays) into the int32 DM transform
+//  k_thresholds  exact moments, mean / sigma per (DM row, segment) and the smallest
+//                boxcar sum reaching the S/N threshold per width (single pulse search)
+//  k_boxcar      boxcar filters via wrapping 32-bit prefix sums, threshold test, best
+//                width; counts hits per tile, then emits them in (row, t) order
+//  k_nms         peak filter over the sorted hit list (3x3, then 11x11 windows)
+//  k_scan_*      device-wide exclusive scans used for ordered compaction
+//  k_scatter     candidate records from the peak-filter survivors
+//
+// All integer work is exact; binary64 is evaluated with contraction disabled so
+// every rounding is the one written in the expression.
+#include <hip/hip_runtime.h>
+#include <limits.h>
+
+#include "kernels.h"
+#include "spl_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace spl {
+
+// --------------------------------------------------------------------- helpers
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Read-only tables (delays) are read through the constant address space so that
+// wave-uniform indices become scalar loads.
+typedef __attribute__((address_space(4))) const int32_t cint32;
+__device__ __forceinline__ const cint32 *as_const(const int32_t *p) { return (const cint32 *)p; }
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Correctly rounded (nearest-even) conversion of the unsigned 128-bit integer hi:lo.
+__device__ double u128_to_f64(uint64_t hi, uint64_t lo) {
+    if (hi == 0) return (double)lo;
+    const int lz = __clzll((long long)hi);
+    uint64_t m = lz ? ((hi << lz) | (lo >> (64 - lz))) : hi;
+    const uint64_t rest = lz ? (lo << lz) : lo;
+    m |= (rest != 0) ? 1ull : 0ull;   // sticky bit below the rounding position
+    return ldexp((double)m, 64 - lz);
+}
+
+// mean and sigma of a segment from exact moments: V = n*S2 - S1^2 (128-bit),
+// mu = S1/n, sigma = sqrt(V)/n, sigma = 0 for V = 0.
+__device__ void mu_sigma(int64_t n, int64_t S1, int64_t S2, double &mu, double &sigma) {
+    const uint64_t un = (uint64_t)n, u2 = (uint64_t)S2, u1 = (uint64_t)S1;
+    const uint64_t a_lo = un * u2, a_hi = __umul64hi(un, u2);
+    const uint64_t b_lo = u1 * u1, b_hi = __umul64hi(u1, u1);
+    const uint64_t v_lo = a_lo - b_lo;
+    const uint64_t v_hi = a_hi - b_hi - (a_lo < b_lo ? 1ull : 0ull);
+    mu = (double)S1 / (double)n;
+    sigma = (v_hi == 0 && v_lo == 0) ? 0.0 : sqrt(u128_to_f64(v_hi, v_lo)) / (double)n;
+}
+
+__device__ __forceinline__ double snr_of(int64_t B, int w, double mu, double sigma) {
+    return ((double)B - (double)w * mu) / (sigma * sqrt((double)w));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Exclusive scan over the 256 threads of a workgroup; *total gets the sum.
+template <typename T>
+__device__ T block_exclusive_scan(T v, T *total, T *sh) {
+    const int lane = lane_id(), wave = wave_id();
+    T x = wave_inclusive_scan(v);
+    if (lane == 63) sh[wave] = x;
+    __syncthreads();
+    T pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        T s = sh[w];
+        if (w < wave) pre += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
+}
+
+__device__ __forceinline__ int beam_of_chunk(const DevBeam *beams, int lo, int hi, int g) {
+    int b = lo;
+    while (b + 1 < hi && beams[b + 1].chunk_base <= g) ++b;
+    return b;
+}
+__device__ __forceinline__ int beam_of_row(const DevBeam *beams, int lo, int hi, int r) {
+    int a = lo, z = hi - 1;   // largest b with row_base <= r
+    while (a < z) {
+        int m = (a + z + 1) >> 1;
+        if (beams[m].row_base <= r) a = m; else z = m - 1;
+    }
+    return a;
+}
+
+// ------------------------------------------------------------------- fill
+__global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------- dedispersion
+// Workgroup = 4 wavefronts; item = (beam, DM tile of 4*DW trials, time tile of 256*J
+// samples).  Wavefront w owns DM trials d0 + w*DW ... + DW-1; lane l owns samples
+// t0 + 256 j + 4 l + {0,1,2,3}, j < J.  Channels are staged chan_chunk at a time:
+// row r of the LDS holds x[c][ws_c, ws_c + row_bytes) with ws_c the 16-aligned start
+// of the tile's smallest delay for that channel, so every trial of the tile reads its
+// shifted samples from the same staged row.  A trial's delay is wave-uniform: it is
+// loaded through the scalar unit and turned into one LDS address add and two byte-
+// select masks.  v_perm_b32 extracts bytes (t, t+2) and (t+1, t+3) into 16-bit fields,
+// accumulated exactly for up to 256 channels and then widened to int32.
+template <int DW, int J>
+__global__ __launch_bounds__(kThreads) void k_dedisp(const DevBeam *__restrict__ beams,
+                                                     const DedispItem *__restrict__ items,
+                                                     int item_lo, int item_hi, int *queue) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ int s_item;
+    constexpr int TT = 256 * J;
+    const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+
+    int it = item_lo + blockIdx.x;
+    for (;;) {
+        if (queue) {
+            __syncthreads();
+            if (tid == 0) s_item = item_lo + atomicAdd(queue, 1);
+            __syncthreads();
+            it = __builtin_amdgcn_readfirstlane(s_item);
+        }
+        if (it >= item_hi) break;
+
+        const DedispItem item = items[it];
+        const DevBeam &B = beams[item.beam];
+        const int nch = B.nch, ndm_pad = B.ndm_pad, R = item.row_bytes;
+        const int t0 = item.t0, d0 = item.d0;
+        const int dw0 = d0 + wave * DW;
+        const int32_t *__restrict__ dcm = B.dcm;
+        const int32_t *__restrict__ base = B.tile_base + (size_t)(d0 / B.tile_dm) * nch;
+        const int64_t pitch = B.pitch;
+        const uint8_t *__restrict__ x = B.x;
+        const int cchunk = B.chan_chunk;
+
+        int32_t acc[DW][4 * J];
+#pragma unroll
+        for (int i = 0; i < DW; ++i)
+#pragma unroll
+            for (int k = 0; k < 4 * J; ++k) acc[i][k] = 0;
+
+        for (int c0 = 0; c0 < nch; c0 += cchunk) {
+            const int cc = min(cchunk, nch - c0);
+            __syncthreads();
+            // stage: wavefront w copies rows w, w+4, ... ; lanes stride over 16-byte vectors
+            const int nvec = R >> 4;
+            for (int r = wave; r < cc; r += kThreads / 64) {
+                const int c = c0 + r;
+                const int64_t ws = (int64_t)((t0 + as_const(base)[c]) & ~15);
+                const uint8_t *src = x + (size_t)c * pitch;
+                uint4 *dst = (uint4 *)(lds + r * R);
+                for (int k = lane; k < nvec; k += 64) {
+                    const int64_t off = ws + 16 * (int64_t)k;
+                    uint4 v = make_uint4(0, 0, 0, 0);
+                    if (off + 16 <= pitch) v = *(const uint4 *)(src + off);
+                    dst[k] = v;
+                }
+            }
+            __syncthreads();
+
+            uint32_t ae[DW][J], ao[DW][J];
+#pragma unroll
+            for (int i = 0; i < DW; ++i)
+#pragma unroll
+                for (int j = 0; j < J; ++j) ae[i][j] = ao[i][j] = 0u;
+
+            const uint32_t *lds32 = (const uint32_t *)lds;
+            // delays of the next channel are fetched one channel ahead
+            int32_t nd[DW];
+            int32_t nb;
+            {
+                const cint32 *drow = as_const(dcm + (size_t)c0 * ndm_pad + dw0);
+#pragma unroll
+                for (int i = 0; i < DW; ++i) nd[i] = drow[i];
+                nb = as_const(base)[c0];
+            }
+            for (int r = 0; r < cc; ++r) {
+                int32_t cd[DW];
+#pragma unroll
+                for (int i = 0; i < DW; ++i) cd[i] = nd[i];
+                const int cb = nb;
+                if (r + 1 < cc) {
+                    const cint32 *drow = as_const(dcm + (size_t)(c0 + r + 1) * ndm_pad + dw0);
+#pragma unroll
+                    for (int i = 0; i < DW; ++i) nd[i] = drow[i];
+                    nb = as_const(base)[c0 + r + 1];
+                }
+                const int ws = (t0 + cb) & ~15;
+                const int rowoff = r * R + t0 - ws;   // LDS byte of sample t0 + s is rowoff + s
+#pragma unroll
+                for (int i = 0; i < DW; ++i) {
+                    const int o = rowoff + cd[i];
+                    const uint32_t a = (uint32_t)(o & 3);
+                    const uint32_t sel_e = 0x0C000C00u | a | ((a + 2u) << 16);
+                    const uint32_t sel_o = sel_e + 0x00010001u;
+                    const uint32_t *p = lds32 + (o >> 2) + lane;
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        const uint32_t lo = p[64 * j], hi = p[64 * j + 1];
+                        ae[i][j] += __builtin_amdgcn_perm(hi, lo, sel_e);
+                        ao[i][j] += __builtin_amdgcn_perm(hi, lo, sel_o);
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < DW; ++i)
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    acc[i][4 * j + 0] += (int32_t)(ae[i][j] & 0xFFFFu);
+                    acc[i][4 * j + 2] += (int32_t)(ae[i][j] >> 16);
+                    acc[i][4 * j + 1] += (int32_t)(ao[i][j] & 0xFFFFu);
+                    acc[i][4 * j + 3] += (int32_t)(ao[i][j] >> 16);
+                }
+        }
+
+        // write the DM transform
+        const int ndm = B.ndm, n_dd = B.n_dd;
+#pragma unroll
+        for (int i = 0; i < DW; ++i) {
+            const int d = dw0 + i;
+            if (d >= ndm) continue;
+            int32_t *Xr = B.X + (size_t)d * B.xpitch;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int t = t0 + 256 * j + 4 * lane;
+                if (t + 3 < n_dd) {
+                    *(int4 *)(Xr + t) = make_int4(acc[i][4 * j], acc[i][4 * j + 1],
+                                                  acc[i][4 * j + 2], acc[i][4 * j + 3]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (t + e < n_dd) Xr[t + e] = acc[i][4 * j + e];
+                }
+            }
+        }
+        if (!queue) break;
+    }
+}
+
+// ------------------------------------------------------- moments + thresholds
+// One workgroup per DM row: exact moments n, S1 = sum X, S2 = sum X^2 of every
+// segment of the owned samples, then mu, sigma and, for every width w, the smallest
+// integer boxcar sum T with snr(T, w) >= theta.  snr is non-decreasing in the sum,
+// so "sum >= T" is exactly "snr >= theta".
+__global__ __launch_bounds__(kThreads) void k_thresholds(const DevBeam *__restrict__ beams, int beam_lo,
+                                                         int beam_hi, int row_lo) {
+    __shared__ int64_t sh[kThreads / 64];
+    const int r = row_lo + blockIdx.x;
+    const DevBeam &B = beams[beam_of_row(beams, beam_lo, beam_hi, r)];
+    const int d = r - B.row_base;
+    const int32_t *Xr = B.X + (size_t)d * B.xpitch;
+    for (int sg = 0; sg < B.nseg; ++sg) {
+        const int lo = sg * B.L, hi = min((sg + 1) * B.L, B.n_out);
+        int64_t s1 = 0, s2 = 0;
+        for (int t = lo + (int)threadIdx.x; t < hi; t += kThreads) {
+            const int64_t v = Xr[t];
+            s1 += v;
+            s2 += v * v;
+        }
+        int64_t t1, t2;
+        (void)block_exclusive_scan<int64_t>(s1, &t1, sh);
+        (void)block_exclusive_scan<int64_t>(s2, &t2, sh);
+        const size_t idx = (size_t)d * B.nseg + sg;
+        if (threadIdx.x == 0) {
+            B.S1[idx] = t1;
+            B.S2[idx] = t2;
+            double mu, sigma;
+            mu_sigma(hi - lo, t1, t2, mu, sigma);
+            B.mu[idx] = mu;
+            B.sigma[idx] = sigma;
+        }
+        if ((int)threadIdx.x < B.nw) {
+            double mu, sigma;
+            mu_sigma(hi - lo, t1, t2, mu, sigma);
+            const int j = threadIdx.x;
+            const int w = B.widths[j];
+            int32_t T = INT_MAX;
+            if (sigma > 0.0) {
+                const int64_t bmax = (int64_t)w * B.nch * 255;
+                const double est = ceil((double)w * mu + B.theta * sigma * sqrt((double)w));
+                int64_t b = est < 0.0 ? 0 : (est > (double)(bmax + 1) ? bmax + 1 : (int64_t)est);
+                while (b > 0 && snr_of(b - 1, w, mu, sigma) >= B.theta) --b;
+                while (b <= bmax && snr_of(b, w, mu, sigma) < B.theta) ++b;
+                T = b > bmax ? INT_MAX : (int32_t)b;
+            }
+            B.T[idx * B.nw + j] = T;
+        }
+    }
+}
+
+// ------------------------------------------------------------------- boxcars
+// Workgroup = one row chunk of kBoxTile owned samples.  P[i] = X[t0] + ... + X[t0+i-1]
+// in wrapping uint32; a window sum P[i+w] - P[i] is exact because every true sum is
+// below 2^31.  Thread k evaluates samples t0 + 4k .. t0 + 4k + 3 so that hits come out
+// in t order.  EMIT = false counts hits per chunk; EMIT = true writes them at the
+// chunk's offset from the exclusive scan of the counts.
+template <bool EMIT>
+__global__ __launch_bounds__(kThreads) void k_boxcar(const DevBeam *__restrict__ beams, int beam_lo,
+                                                     int beam_hi, int chunk_lo, int32_t *counts,
+                                                     const int64_t *offsets, Hit *hits, int64_t cap) {
+    extern __shared__ uint32_t P[];
+    __shared__ uint32_t sh32[kThreads / 64];
+    __shared__ int64_t sh64[kThreads / 64];
+    const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+    const int g = chunk_lo + blockIdx.x;
+    const DevBeam &B = beams[beam_of_chunk(beams, beam_lo, beam_hi, g)];
+    const int local = g - B.chunk_base;
+    const int d = local / B.nchunk_t;
+    const int t0 = (local - d * B.nchunk_t) * kBoxTile;
+    const int M = kBoxTile + B.w_max - 1;
+    const int32_t *Xr = B.X + (size_t)d * B.xpitch;
+
+    if (tid == 0) P[0] = 0u;
+    uint32_t carry = 0;
+    for (int base = 0; base < M; base += kThreads) {
+        const int i = base + tid;
+        const uint32_t v = (i < M && t0 + i < B.n_dd) ? (uint32_t)Xr[t0 + i] : 0u;
+        const uint32_t x = wave_inclusive_scan(v);
+        if (lane == 63) sh32[wave] = x;
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) {
+            if (w < wave) pre += sh32[w];
+            tot += sh32[w];
+        }
+        if (i < M) P[i + 1] = carry + pre + x;
+        carry += tot;
+        __syncthreads();
+    }
+
+    int cnt = 0;
+    int hw[4], hB[4], ht[4];
+    double hs[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int li = 4 * tid + e, t = t0 + li;
+        hw[e] = 0;
+        if (t >= B.n_out) continue;
+        const int sg = t / B.L;
+        const size_t idx = (size_t)d * B.nseg + sg;
+        const double mu = B.mu[idx], sigma = B.sigma[idx];
+        const int32_t *Tp = B.T + idx * B.nw;
+        double best = 0.0;
+        for (int j = 0; j < B.nw; ++j) {
+            const int w = B.widths[j];
+            const int32_t Bw = (int32_t)(P[li + w] - P[li]);
+            if (Bw >= Tp[j]) {
+                const double s = snr_of(Bw, w, mu, sigma);
+                if (hw[e] == 0 || s > best) {
+                    best = s;
+                    hw[e] = w;
+                    hB[e] = Bw;
+                }
+            }
+        }
+        if (hw[e]) {
+            hs[e] = best;
+            ht[e] = t;
+            ++cnt;
+        }
+    }
+    if (!EMIT) {
+        int64_t tot;
+        (void)block_exclusive_scan<int64_t>(cnt, &tot, sh64);
+        if (tid == 0) counts[blockIdx.x] = (int32_t)tot;
+    } else {
+        int64_t tot;
+        int64_t pos = offsets[blockIdx.x] + block_exclusive_scan<int64_t>(cnt, &tot, sh64);
+        const int row = B.row_base + d;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (!hw[e]) continue;
+            if (pos < cap) {
+                Hit h;
+                h.row = row;
+                h.t = ht[e];
+                h.w = hw[e];
+                h.B = hB[e];
+                h.snr = hs[e];
+                hits[pos] = h;
+            }
+            ++pos;
+        }
+    }
+}
+
+// ------------------------------------------------------------------- scans
+// Exclusive scan of n elements (n read from *n_dev when given, else n_static) in
+// blocks of kScanPerBlock: per-block sums, one-workgroup scan of the sums, then the
+// per-block scan with its offset.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const T *in, const int64_t *n_dev, int64_t n_static,
+                                                          int64_t *block_sums) {
+    __shared__ int64_t sh[kThreads / 64];
+    const int64_t n = n_dev ? min(*n_dev, n_static) : n_static;
+    const int64_t b0 = (int64_t)blockIdx.x * kScanPerBlock;
+    int64_t s = 0;
+    if (b0 < n) {
+        for (int k = 0; k < kScanPerBlock / kThreads; ++k) {
+            const int64_t i = b0 + (int64_t)k * kThreads + threadIdx.x;
+            if (i < n) s += (int64_t)in[i];
+        }
+    }
+    int64_t tot;
+    (void)block_exclusive_scan<int64_t>(s, &tot, sh);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t *block_sums, int nblocks, int64_t *total_out) {
+    __shared__ int64_t sh[16];
+    __shared__ int64_t s_carry;
+    const int tid = threadIdx.x, lane = lane_id(), wave = threadIdx.x >> 6;
+    if (tid == 0) s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nblocks; base += 1024) {
+        const int i = base + tid;
+        const int64_t v = i < nblocks ? block_sums[i] : 0;
+        const int64_t x = wave_inclusive_scan(v);
+        if (lane == 63) sh[wave] = x;
+        __syncthreads();
+        int64_t pre = 0, tot = 0;
+        for (int w = 0; w < 16; ++w) {
+            if (w < wave) pre += sh[w];
+            tot += sh[w];
+        }
+        const int64_t c = s_carry;
+        if (i < nblocks) block_sums[i] = c + pre + x - v;
+        __syncthreads();
+        if (tid == 0) s_carry = c + tot;
+        __syncthreads();
+    }
+    if (tid == 0 && total_out) *total_out = s_carry;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scan_down(const T *in, const int64_t *n_dev, int64_t n_static,
+                                                        const int64_t *block_offsets, int64_t *out) {
+    __shared__ int64_t sh[kThreads / 64];
+    const int64_t n = n_dev ? min(*n_dev, n_static) : n_static;
+    const int64_t b0 = (int64_t)blockIdx.x * kScanPerBlock;
+    if (b0 >= n) return;
+    int64_t carry = block_offsets[blockIdx.x];
+    for (int k = 0; k < kScanPerBlock / kThreads; ++k) {
+        const int64_t i = b0 + (int64_t)k * kThreads + threadIdx.x;
+        const int64_t v = i < n ? (int64_t)in[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_exclusive_scan<int64_t>(v, &tot, sh);
+        if (i < n) out[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+// First hit of every row (clamped to the stored hits) from the chunk offsets.
+__global__ void k_row_start(const DevBeam *__restrict__ beams, int beam_lo, int beam_hi, int row_lo,
+                            int row_hi, int chunk_lo, const int64_t *chunk_off, const int64_t *n_hits,
+                            int64_t cap, int64_t *row_start) {
+    const int r = row_lo + blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stored = min(*n_hits, cap);
+    if (r < row_hi) {
+        const DevBeam &B = beams[beam_of_row(beams, beam_lo, beam_hi, r)];
+        const int chunk = B.chunk_base + (r - B.row_base) * B.nchunk_t;
+        row_start[r - row_lo] = min(chunk_off[chunk - chunk_lo], stored);
+    }
+    if (r == row_hi) row_start[r - row_lo] = stored;
+}
+
+// ---------------------------------------------------------------- peak filter
+// q beats p when (snr_q, -d_q, -t_q) > (snr_p, -d_p, -t_p).  p survives when no other
+// alive hit of its beam within |dd| <= rd, |dt| <= rt beats it.  Rows of a beam are
+// contiguous in the hit list and sorted by t, so each neighbour row is searched by
+// bisection.
+__global__ __launch_bounds__(kThreads) void k_nms(const DevBeam *__restrict__ beams, int beam_lo, int beam_hi,
+                                                  int row_lo, const Hit *__restrict__ hits,
+                                                  const int64_t *n_hits, int64_t cap,
+                                                  const int64_t *__restrict__ row_start, int stencil,
+                                                  const uint8_t *alive_in, uint8_t *alive_out,
+                                                  int64_t *n_alive) {
+    __shared__ int64_t sh[kThreads / 64];
+    const int64_t n = min(*n_hits, cap);
+    int64_t kept = 0;
+    for (int64_t p = blockIdx.x * (int64_t)kThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kThreads) {
+        if (alive_in && !alive_in[p]) {
+            alive_out[p] = 0;
+            continue;
+        }
+        const Hit h = hits[p];
+        const DevBeam &B = beams[beam_of_row(beams, beam_lo, beam_hi, h.row)];
+        if (stencil >= B.nst) {   // this beam's plan has fewer filters: pass through
+            alive_out[p] = 1;
+            ++kept;
+            continue;
+        }
+        const int rd = B.rd[stencil], rt = B.rt[stencil];
+        const int d = h.row - B.row_base;
+        bool keep = true;
+        for (int dd = -rd; dd <= rd && keep; ++dd) {
+            const int d2 = d + dd;
+            if (d2 < 0 || d2 >= B.ndm) continue;
+            const int r2 = B.row_base + d2 - row_lo;
+            int64_t lo = row_start[r2], hi = row_start[r2 + 1];
+            const int tmin = h.t - rt;
+            while (lo < hi) {   // first index with t >= tmin
+                const int64_t m = (lo + hi) >> 1;
+                if (hits[m].t < tmin) lo = m + 1; else hi = m;
+            }
+            const int64_t end = row_start[r2 + 1];
+            for (int64_t q = lo; q < end; ++q) {
+                const Hit g = hits[q];
+                if (g.t > h.t + rt) break;
+                if (q == p || (alive_in && !alive_in[q])) continue;
+                const bool beats = g.snr != h.snr ? g.snr > h.snr : (d2 != d ? d2 < d : g.t < h.t);
+                if (beats) {
+                    keep = false;
+                    break;
+                }
+            }
+        }
+        alive_out[p] = keep ? 1 : 0;
+        kept += keep ? 1 : 0;
+    }
+    int64_t tot;
+    (void)block_exclusive_scan<int64_t>(kept, &tot, sh);
+    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)n_alive, (unsigned long long)tot);
+}
+
+// Candidate records of the survivors, in hit order, after `*base` earlier records.
+__global__ __launch_bounds__(kThreads) void k_scatter(const DevBeam *__restrict__ beams, int beam_lo, int beam_hi,
+                                                      const Hit *__restrict__ hits, const int64_t *n_hits,
+                                                      int64_t cap, const uint8_t *alive, const int64_t *pos,
+                                                      const int64_t *base, spl_candidate *cands,
+                                                      int64_t cand_cap) {
+    const int64_t n = min(*n_hits, cap);
+    const int64_t b0 = *base;
+    for (int64_t p = blockIdx.x * (int64_t)kThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kThreads) {
+        if (alive && !alive[p]) continue;
+        const int64_t o = b0 + (pos ? pos[p] : p);
+        if (o >= cand_cap) continue;
+        const Hit h = hits[p];
+        const DevBeam &B = beams[beam_of_row(beams, beam_lo, beam_hi, h.row)];
+        spl_candidate c;
+        c.beam = B.beam;
+        c.dm_index = h.row - B.row_base;
+        c.t_sample = h.t;
+        c.width = h.w;
+        c.boxcar_sum = h.B;
+        c.snr = (float)h.snr;
+        c.dm = (float)B.dms[c.dm_index];
+        c.flags = 0u;
+        cands[o] = c;
+    }
+}
+
+// End of the launch sequence of a beam range: fold the range's counts into the run
+// statistics; the next range's candidates go after this one's.
+__global__ void k_pass_end(DevRun *run, spl_run_stats *stats, int64_t hit_cap, int nst) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    stats->n_hits += run->n_hits;
+    if (run->n_hits > hit_cap) stats->hit_overflow = 1;
+    for (int k = 0; k < nst; ++k) {
+        stats->n_after_stencil[k] += run->n_alive[k];
+        run->n_alive[k] = 0;
+    }
+    run->n_cand_total += nst ? run->n_cand_beam : min(run->n_hits, hit_cap);
+}
+
+__global__ void k_finalize(DevRun *run, spl_run_stats *stats, int64_t cand_cap) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    stats->n_candidates = run->n_cand_total;
+    stats->cand_overflow = run->n_cand_total > cand_cap ? 1 : 0;
+}
+
+// Normaliser test hook: mu and sigma from exact moments, as the search computes them.
+__global__ void k_mu_sigma(const int64_t *n, const int64_t *s1, const int64_t *s2, int64_t count,
+                           double *mu, double *sigma) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < count) mu_sigma(n[i], s1[i], s2[i], mu[i], sigma[i]);
+}
+
+// ---------------------------------------------------------------- launchers
+#define SPL_HIP_LAUNCH_CHECK() \
+    do { hipError_t e__ = hipGetLastError(); if (e__ != hipSuccess) return e__; } while (0)
+
+template <int DW, int J>
+static hipError_t prepare_dedisp_t(size_t lds_bytes, int *blocks_per_cu) {
+    if (lds_bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_dedisp<DW, J>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_dedisp<DW, J>, kThreads, lds_bytes);
+}
+
+template <int DW, int J>
+static hipError_t launch_dedisp_t(const DevBeam *beams, const DedispItem *items, int item_lo, int item_hi,
+                                  int *queue, int grid, size_t lds_bytes, hipStream_t s) {
+    hipLaunchKernelGGL((k_dedisp<DW, J>), dim3(grid), dim3(kThreads), lds_bytes, s, beams, items, item_lo,
+                       item_hi, queue);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+bool dedisp_shape_supported(int dw, int j) {
+    switch (dw * 16 + j) {
+        case 4 * 16 + 1: case 4 * 16 + 2: case 4 * 16 + 4: case 8 * 16 + 1: case 8 * 16 + 2:
+        case 16 * 16 + 1: case 2 * 16 + 2: case 2 * 16 + 4:
+            return true;
+        default:
+            return false;
+    }
+}
+
+hipError_t prepare_dedisp(int dw, int j, size_t lds_bytes, int *blocks_per_cu) {
+    switch (dw * 16 + j) {
+        case 2 * 16 + 2: return prepare_dedisp_t<2, 2>(lds_bytes, blocks_per_cu);
+        case 2 * 16 + 4: return prepare_dedisp_t<2, 4>(lds_bytes, blocks_per_cu);
+        case 4 * 16 + 1: return prepare_dedisp_t<4, 1>(lds_bytes, blocks_per_cu);
+        case 4 * 16 + 2: return prepare_dedisp_t<4, 2>(lds_bytes, blocks_per_cu);
+        case 4 * 16 + 4: return prepare_dedisp_t<4, 4>(lds_bytes, blocks_per_cu);
+        case 8 * 16 + 1: return prepare_dedisp_t<8, 1>(lds_bytes, blocks_per_cu);
+        case 8 * 16 + 2: return prepare_dedisp_t<8, 2>(lds_bytes, blocks_per_cu);
+        case 16 * 16 + 1: return prepare_dedisp_t<16, 1>(lds_bytes, blocks_per_cu);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_dedisp(int dw, int j, const DevBeam *beams, const DedispItem *items, int item_lo,
+                         int item_hi, int *queue, int grid, size_t lds_bytes, hipStream_t s) {
+    switch (dw * 16 + j) {
+        case 2 * 16 + 2: return launch_dedisp_t<2, 2>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
+        case 2 * 16 + 4: return launch_dedisp_t<2, 4>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
+        case 4 * 16 + 1: return launch_dedisp_t<4, 1>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
+        case 4 * 16 + 2: return launch_dedisp_t<4, 2>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
+        case 4 * 16 + 4: return launch_dedisp_t<4, 4>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
+        case 8 * 16 + 1: return launch_dedisp_t<8, 1>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
+        case 8 * 16 + 2: return launch_dedisp_t<8, 2>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
+        case 16 * 16 + 1: return launch_dedisp_t<16, 1>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + kThreads - 1) / kThreads;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(kThreads), 0, s, p, n, v);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_thresholds(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, int row_hi, hipStream_t s) {
+    const int n = row_hi - row_lo;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_thresholds, dim3(n), dim3(kThreads), 0, s, beams, beam_lo, beam_hi, row_lo);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_boxcar(bool emit, const DevBeam *beams, int beam_lo, int beam_hi, int chunk_lo, int chunk_hi,
+                         int w_max, int32_t *counts, const int64_t *offsets, Hit *hits, int64_t cap,
+                         hipStream_t s) {
+    const int n = chunk_hi - chunk_lo;
+    if (n <= 0) return hipSuccess;
+    const size_t lds = (size_t)(kBoxTile + w_max + 1) * sizeof(uint32_t);
+    if (emit)
+        hipLaunchKernelGGL(k_boxcar<true>, dim3(n), dim3(kThreads), lds, s, beams, beam_lo, beam_hi, chunk_lo,
+                           counts, offsets, hits, cap);
+    else
+        hipLaunchKernelGGL(k_boxcar<false>, dim3(n), dim3(kThreads), lds, s, beams, beam_lo, beam_hi, chunk_lo,
+                           counts, offsets, hits, cap);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+int scan_blocks(int64_t n_max) { return (int)((n_max + kScanPerBlock - 1) / kScanPerBlock); }
+
+template <typename T>
+static hipError_t launch_scan_t(const T *in, const int64_t *n_dev, int64_t n_max, int64_t *block_sums,
+                                int64_t *out, int64_t *total, hipStream_t s) {
+    const int nb = scan_blocks(n_max);
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_reduce<T>, dim3(nb), dim3(kThreads), 0, s, in, n_dev, n_max, block_sums);
+    SPL_HIP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, block_sums, nb, total);
+    SPL_HIP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_down<T>, dim3(nb), dim3(kThreads), 0, s, in, n_dev, n_max, block_sums, out);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_scan_i32(const int32_t *in, const int64_t *n_dev, int64_t n_max, int64_t *block_sums,
+                           int64_t *out, int64_t *total, hipStream_t s) {
+    return launch_scan_t<int32_t>(in, n_dev, n_max, block_sums, out, total, s);
+}
+hipError_t launch_scan_u8(const uint8_t *in, const int64_t *n_dev, int64_t n_max, int64_t *block_sums,
+                          int64_t *out, int64_t *total, hipStream_t s) {
+    return launch_scan_t<uint8_t>(in, n_dev, n_max, block_sums, out, total, s);
+}
+
+hipError_t launch_row_start(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, int row_hi, int chunk_lo,
+                            const int64_t *chunk_off, const int64_t *n_hits, int64_t cap, int64_t *row_start,
+                            hipStream_t s) {
+    const int n = row_hi - row_lo + 1;
+    hipLaunchKernelGGL(k_row_start, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, beams, beam_lo,
+                       beam_hi, row_lo, row_hi, chunk_lo, chunk_off, n_hits, cap, row_start);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+static int grid_for(int64_t cap) {
+    int64_t g = (cap + kThreads - 1) / kThreads;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_nms(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, const Hit *hits,
+                      const int64_t *n_hits, int64_t cap, const int64_t *row_start, int stencil,
+                      const uint8_t *alive_in, uint8_t *alive_out, int64_t *n_alive, hipStream_t s) {
+    hipLaunchKernelGGL(k_nms, dim3(grid_for(cap)), dim3(kThreads), 0, s, beams, beam_lo, beam_hi, row_lo, hits,
+                       n_hits, cap, row_start, stencil, alive_in, alive_out, n_alive);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_scatter(const DevBeam *beams, int beam_lo, int beam_hi, const Hit *hits, const int64_t *n_hits,
+                          int64_t cap, const uint8_t *alive, const int64_t *pos, const int64_t *base,
+                          spl_candidate *cands, int64_t cand_cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(cap)), dim3(kThreads), 0, s, beams, beam_lo, beam_hi, hits,
+                       n_hits, cap, alive, pos, base, cands, cand_cap);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_pass_end(DevRun *run, spl_run_stats *stats, int64_t hit_cap, int nst, hipStream_t s) {
+    hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(64), 0, s, run, stats, hit_cap, nst);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_finalize(DevRun *run, spl_run_stats *stats, int64_t cand_cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, run, stats, cand_cap);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_mu_sigma(const int64_t *n, const int64_t *s1, const int64_t *s2, int64_t count, double *mu,
+                           double *sigma, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mu_sigma, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, n, s1, s2, count, mu,
+                       sigma);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+}  // namespace spl

@@ -1,0 +1,72 @@
+// Internal layout shared by the host runtime and the HIP kernels of libspotlight.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spl {
+
+constexpr int kMaxWidths = 16;
+constexpr int kMaxStencils = 4;
+constexpr int kBoxTile = 1024;        // owned samples per boxcar workgroup
+constexpr int kThreads = 256;         // threads per workgroup of every kernel
+constexpr int kScanPerBlock = 4096;   // elements per block of the device-wide scan
+constexpr int kMaxWmax = 8192;
+constexpr int kMaxShapeGroups = 4;  // distinct dedispersion tile shapes per batch
+
+// One beam of a batch, resident in the workspace.
+struct DevBeam {
+    const uint8_t *x;        // block [nch][pitch]
+    int64_t pitch;           // bytes
+    const int32_t *dcm;      // delays, channel-major [nch][ndm_pad]
+    const int32_t *tile_base;// min delay over each DM tile [ndm_tiles][nch]
+    int32_t *X;              // DM transform [ndm][xpitch]
+    int64_t *S1, *S2;        // [ndm][nseg]
+    double *mu, *sigma;      // [ndm][nseg]
+    int32_t *T;              // integer thresholds [ndm][nseg][nw]
+    const double *dms;       // [ndm]
+    double theta;
+    int32_t nch, ndm, ndm_pad, n_dd, n_out, L, nseg, nw;
+    int32_t xpitch;          // int32 elements per DM row
+    int32_t row_base;        // global row index of (beam, d = 0)
+    int32_t chunk_base;      // global boxcar chunk of (d = 0, k = 0)
+    int32_t nchunk_t;        // boxcar chunks per row
+    int32_t chan_chunk;      // channels staged in LDS per step
+    int32_t tile_dm;         // DM trials per dedispersion tile
+    int32_t beam;
+    int32_t w_max;
+    int32_t nst;             // peak filters of this beam's plan
+    int32_t rd[kMaxStencils], rt[kMaxStencils];
+    int32_t widths[kMaxWidths];
+};
+
+// One dedispersion work item: a DM tile x time tile of one beam.
+struct DedispItem {
+    int32_t beam;
+    int32_t d0;        // first DM trial of the tile
+    int32_t t0;        // first output sample of the tile
+    int32_t row_bytes; // LDS bytes per staged channel row (multiple of 16)
+};
+
+// A boxcar hit: one (row, t) above threshold with its best width.
+struct Hit {
+    int32_t row;   // global row (beam's row_base + DM index)
+    int32_t t;
+    int32_t w;
+    int32_t B;
+    double snr;
+};
+static_assert(sizeof(Hit) == 24, "Hit layout");
+
+// Per-run device state kept in the scratch part of the workspace.
+struct DevRun {
+    int64_t n_hits;        // true hit count of the beams in flight
+    int64_t n_cand_total;  // candidates written so far (all beams)
+    int64_t n_cand_beam;   // candidates of the beams in flight
+    int64_t n_alive[kMaxStencils];
+    int32_t hit_overflow;
+    int32_t queue[kMaxShapeGroups];  // persistent-kernel work counters
+    int32_t pad;
+};
+
+}  // namespace spl

@@ -1,0 +1,318 @@
+"""ctypes binding of libspotlight.so (argument marshalling only).
+
+Device memory and streams come from PyTorch; every step of the search runs in
+the library's HIP kernels.  Importing this module fails if the library is not
+built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspotlight.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2606_27262_amd.build.build() "
+                      "(or __graft_entry__.build()) before using the search")
+_lib = ctypes.CDLL(LIB_PATH)
+
+SPL_OK, SPL_E_INVALID_ARG, SPL_E_HIP, SPL_E_OOM, SPL_E_CAPACITY, SPL_E_UNSUPPORTED, \
+    SPL_E_NO_WEIGHTS, SPL_E_INTERNAL = range(8)
+MODE_PLAIN_PER_BEAM, MODE_PERSISTENT_GRAPH = 0, 1
+MAX_STENCILS = 4
+
+CAND_DTYPE = np.dtype([("beam", "<i4"), ("dm_index", "<i4"), ("t_sample", "<i4"),
+                       ("width", "<i4"), ("boxcar_sum", "<i4"), ("snr", "<f4"),
+                       ("dm", "<f4"), ("flags", "<u4")])
+
+
+class SplError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"spotlight error {status}: {msg}")
+        self.status = status
+
+
+class _Band(ctypes.Structure):
+    _fields_ = [("nchans", ctypes.c_int32), ("n_out", ctypes.c_int32),
+                ("norm_window", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("fch1_mhz", ctypes.c_double), ("foff_mhz", ctypes.c_double),
+                ("tsamp_s", ctypes.c_double)]
+
+
+class _DMRange(ctypes.Structure):
+    _fields_ = [("dm_start", ctypes.c_double), ("dm_step", ctypes.c_double),
+                ("n_trials", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+
+
+class _SearchOpts(ctypes.Structure):
+    _fields_ = [("n_stencils", ctypes.c_int32), ("stencil_rd", ctypes.c_int32 * MAX_STENCILS),
+                ("stencil_rt", ctypes.c_int32 * MAX_STENCILS)]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in ("nchans", "ndm", "n_out", "n_dd", "n_in", "s_max",
+                                               "n_widths", "w_max", "norm_window", "n_segments",
+                                               "n_stencils", "reserved0")] + [("threshold", ctypes.c_double)]
+
+
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("hit_capacity", ctypes.c_int64)]
+
+
+class _Tiles(ctypes.Structure):
+    _fields_ = [("dm_per_wave", ctypes.c_int32), ("time_groups", ctypes.c_int32),
+                ("chan_chunk", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+
+
+STATS_FIELDS = ("n_hits", "n_candidates", "n_after_stencil0", "n_after_stencil1",
+                "n_after_stencil2", "n_after_stencil3", "overflow")
+STATS_WORDS = 7   # int64 words of spl_run_stats
+
+_P = ctypes.c_void_p
+_I32, _I64, _F64, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+
+
+def _sig(name, args, res=ctypes.c_int32):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_sig("spl_last_error", [], ctypes.c_char_p)
+_sig("spl_version", [], ctypes.c_int32)
+_sig("spl_plan_create", [ctypes.POINTER(_Band), ctypes.POINTER(_DMRange), _I32, _P, _I32, _F64,
+                         ctypes.POINTER(_SearchOpts), ctypes.POINTER(_P)])
+_sig("spl_plan_create_from_delays", [ctypes.POINTER(_Band), _P, _P, _I32, _P, _I32, _F64,
+                                     ctypes.POINTER(_SearchOpts), ctypes.POINTER(_P)])
+_sig("spl_plan_query", [_P, ctypes.POINTER(_PlanInfo)])
+_sig("spl_plan_delays", [_P, _P])
+_sig("spl_plan_dms", [_P, _P])
+_sig("spl_plan_destroy", [_P], None)
+_sig("spl_batch_create", [ctypes.POINTER(_P), _I32, ctypes.POINTER(_BatchOpts), ctypes.POINTER(_P)])
+_sig("spl_batch_workspace_size", [_P, ctypes.POINTER(_SZ)])
+_sig("spl_batch_set_workspace", [_P, _P, _SZ])
+_sig("spl_batch_run", [_P, ctypes.POINTER(_P), ctypes.POINTER(_I64), _P, _I64, _P, _P])
+_sig("spl_batch_dm_transform", [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_I64)])
+_sig("spl_batch_moments", [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_P)])
+_sig("spl_batch_get_tiles", [_P, _I32, ctypes.POINTER(_Tiles)])
+_sig("spl_batch_set_tiles", [_P, _I32, ctypes.POINTER(_Tiles)])
+_sig("spl_batch_destroy", [_P], None)
+_sig("spl_debug_mu_sigma", [_P, _P, _P, _I64, _P, _P, _P])
+
+
+def _check(st):
+    if st != SPL_OK:
+        raise SplError(st, _lib.spl_last_error().decode())
+
+
+def version() -> int:
+    return int(_lib.spl_version())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """Search plan of one beam (see spl_plan_create)."""
+
+    def __init__(self, nchans, fch1, foff, tsamp, n_out, dm_ranges=None, widths=(1,), threshold=6.0,
+                 norm_window=0, stencils=((1, 1), (5, 5)), delays=None, dms=None):
+        band = _Band(int(nchans), int(n_out), int(norm_window), 0, float(fch1), float(foff), float(tsamp))
+        w = np.ascontiguousarray(widths, np.int32)
+        opts = _SearchOpts()
+        opts.n_stencils = len(stencils)
+        for k, (rd, rt) in enumerate(stencils):
+            opts.stencil_rd[k] = int(rd)
+            opts.stencil_rt[k] = int(rt)
+        h = _P()
+        if delays is None:
+            rr = (_DMRange * len(dm_ranges))(*[_DMRange(float(a), float(b), int(n), 0) for a, b, n in dm_ranges])
+            _check(_lib.spl_plan_create(ctypes.byref(band), rr, len(dm_ranges), w.ctypes.data, w.size,
+                                        float(threshold), ctypes.byref(opts), ctypes.byref(h)))
+        else:
+            dl = np.ascontiguousarray(delays, np.int32)
+            dv = None if dms is None else np.ascontiguousarray(dms, np.float64)
+            _check(_lib.spl_plan_create_from_delays(ctypes.byref(band), dl.ctypes.data,
+                                                    None if dv is None else dv.ctypes.data, dl.shape[0],
+                                                    w.ctypes.data, w.size, float(threshold), ctypes.byref(opts),
+                                                    ctypes.byref(h)))
+        self._h = h
+        self.tsamp = float(tsamp)
+        self.info = self.query()
+
+    @classmethod
+    def from_dict(cls, p, **kw):
+        return cls(p["nchans"], p["fch1"], p["foff"], p["tsamp"], p["n_out"], p["dm_ranges"], p["widths"],
+                   p["threshold"], norm_window=p.get("norm_window", 0), **kw)
+
+    def query(self) -> dict:
+        i = _PlanInfo()
+        _check(_lib.spl_plan_query(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in _PlanInfo._fields_}
+
+    def delays(self) -> np.ndarray:
+        out = np.empty((self.info["ndm"], self.info["nchans"]), np.int32)
+        _check(_lib.spl_plan_delays(self._h, out.ctypes.data))
+        return out
+
+    def dms(self) -> np.ndarray:
+        out = np.empty(self.info["ndm"], np.float64)
+        _check(_lib.spl_plan_dms(self._h, out.ctypes.data))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.spl_plan_destroy(self._h)
+            self._h = None
+
+
+class Batch:
+    """A batch of beams searched per run.  Device memory (workspace, candidates,
+    statistics) is allocated here with torch and owned by this object."""
+
+    def __init__(self, plans, mode=MODE_PLAIN_PER_BEAM, hit_capacity=0, device="cuda"):
+        self.plans = list(plans)
+        arr = (_P * len(self.plans))(*[p._h for p in self.plans])
+        opts = _BatchOpts(int(mode), 0, int(hit_capacity))
+        h = _P()
+        _check(_lib.spl_batch_create(arr, len(self.plans), ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self.mode = mode
+        self.device = device
+        self.ws = None
+        self._stream = None
+
+    def workspace_bytes(self) -> int:
+        n = _SZ()
+        _check(_lib.spl_batch_workspace_size(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def tiles(self, beam=0) -> dict:
+        t = _Tiles()
+        _check(_lib.spl_batch_get_tiles(self._h, beam, ctypes.byref(t)))
+        return {"dm_per_wave": t.dm_per_wave, "time_groups": t.time_groups, "chan_chunk": t.chan_chunk}
+
+    def set_tiles(self, beam, dm_per_wave, time_groups, chan_chunk=0):
+        t = _Tiles(int(dm_per_wave), int(time_groups), int(chan_chunk), 0)
+        _check(_lib.spl_batch_set_tiles(self._h, beam, ctypes.byref(t)))
+        if self.ws is not None:
+            self.attach()
+
+    def attach(self):
+        """Allocate (or grow) the workspace with torch and upload the plan tables."""
+        import torch
+        nbytes = self.workspace_bytes()
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = None
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._ws_off = (-base) % 256
+        _check(_lib.spl_batch_set_workspace(self._h, ctypes.c_void_p(base + self._ws_off), nbytes))
+
+    def run(self, blocks, cands=None, stats=None, stream=None):
+        """Enqueue one search.  blocks: list of uint8 CUDA tensors [nch][pitch] (pitch a
+        multiple of 16).  cands: int32 tensor [capacity, 8]; stats: int64 tensor [7]."""
+        import torch
+        if self.ws is None:
+            self.attach()
+        nb = len(self.plans)
+        assert len(blocks) == nb
+        ptrs = (_P * nb)(*[b.data_ptr() for b in blocks])
+        pitches = (_I64 * nb)(*[b.stride(0) for b in blocks])
+        for b in blocks:
+            assert b.dtype == torch.uint8 and b.is_cuda and b.dim() == 2 and b.stride(1) == 1
+        if stats is None:
+            stats = torch.zeros(STATS_WORDS, dtype=torch.int64, device=self.device)
+        cap = 0 if cands is None else cands.shape[0]
+        cptr = None if cands is None else ctypes.c_void_p(cands.data_ptr())
+        if self.mode == MODE_PERSISTENT_GRAPH and stream is None:
+            # graph capture needs a stream other than the default one
+            if self._stream is None:
+                self._stream = torch.cuda.Stream(device=self.device)
+            cur = torch.cuda.current_stream()
+            self._stream.wait_stream(cur)
+            _check(_lib.spl_batch_run(self._h, ptrs, pitches, cptr, cap, ctypes.c_void_p(stats.data_ptr()),
+                                      _stream_handle(self._stream)))
+            cur.wait_stream(self._stream)
+        else:
+            _check(_lib.spl_batch_run(self._h, ptrs, pitches, cptr, cap, ctypes.c_void_p(stats.data_ptr()),
+                                      _stream_handle(stream)))
+        return cands, stats
+
+    def _view(self, ptr, nbytes, dtype):
+        off = ptr - self.ws.data_ptr()
+        assert 0 <= off and off + nbytes <= self.ws.numel()
+        return self.ws[off:off + nbytes].view(dtype)
+
+    def dm_transform(self, beam):
+        """Device view int32 [ndm][pitch] of the last run's DM transform of `beam`."""
+        import torch
+        p = _P()
+        pitch = _I64()
+        _check(_lib.spl_batch_dm_transform(self._h, beam, ctypes.byref(p), ctypes.byref(pitch)))
+        ndm = self.plans[beam].info["ndm"]
+        return self._view(p.value, ndm * pitch.value * 4, torch.int32).view(ndm, pitch.value)
+
+    def moments(self, beam):
+        import torch
+        a, b = _P(), _P()
+        _check(_lib.spl_batch_moments(self._h, beam, ctypes.byref(a), ctypes.byref(b)))
+        info = self.plans[beam].info
+        n = info["ndm"] * info["n_segments"]
+        s1 = self._view(a.value, n * 8, torch.int64).view(info["ndm"], info["n_segments"])
+        s2 = self._view(b.value, n * 8, torch.int64).view(info["ndm"], info["n_segments"])
+        return s1, s2
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.spl_batch_destroy(self._h)
+            self._h = None
+
+
+def new_candidates(capacity, device="cuda"):
+    import torch
+    return torch.empty((int(capacity), 8), dtype=torch.int32, device=device)
+
+
+def candidates_to_numpy(cands, stats) -> np.ndarray:
+    """Copy the written candidate records to a numpy structured array."""
+    n = int(stats[1].item())
+    cap = cands.shape[0]
+    m = min(n, cap)
+    raw = cands[:m].cpu().numpy()
+    return raw.view(CAND_DTYPE).reshape(-1)
+
+
+def stats_dict(stats) -> dict:
+    s = stats.cpu().numpy()
+    ov = int(s[6])
+    return {"n_hits": int(s[0]), "n_candidates": int(s[1]),
+            "n_after_stencil": [int(v) for v in s[2:6]],
+            "hit_overflow": ov & 0xFFFFFFFF, "cand_overflow": (ov >> 32) & 0xFFFFFFFF}
+
+
+def debug_mu_sigma(n, s1, s2, stream=None):
+    """Normaliser on device (test hook): int64 CUDA tensors -> (mu, sigma) float64."""
+    import torch
+    mu = torch.empty(n.shape, dtype=torch.float64, device=n.device)
+    sg = torch.empty(n.shape, dtype=torch.float64, device=n.device)
+    _check(_lib.spl_debug_mu_sigma(ctypes.c_void_p(n.data_ptr()), ctypes.c_void_p(s1.data_ptr()),
+                                   ctypes.c_void_p(s2.data_ptr()), n.numel(), ctypes.c_void_p(mu.data_ptr()),
+                                   ctypes.c_void_p(sg.data_ptr()), _stream_handle(stream)))
+    return mu, sg
+
+
+def upload_block(x_np, device="cuda", pitch=None):
+    """uint8 numpy block [nch][>= n_in] -> CUDA tensor with a 256-multiple pitch."""
+    import torch
+    nch, n = x_np.shape
+    p = pitch or (n + 255) // 256 * 256
+    t = torch.zeros((nch, p), dtype=torch.uint8, device=device)
+    t[:, :n] = torch.from_numpy(np.ascontiguousarray(x_np)).to(device)
+    return t

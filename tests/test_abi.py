@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI (no GPU): every declared symbol is exported, the
+library's own delay table equals the oracle's bit for bit, plan sizes, argument
+validation and batch layout."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_27262_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spotlight.h")
+
+spl = pytest.importorskip("paper_2606_27262_amd.spotlight",
+                          reason="libspotlight.so not built")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(spl_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(n for n in names if not n.startswith("spl_status")))
+
+
+def test_every_declared_function_is_exported():
+    lib = ctypes.CDLL(spl.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 18
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version():
+    assert spl.version() >= 100
+
+
+@pytest.mark.parametrize("mk", [W.plan_c1, W.plan_c2, W.plan_band3_c4, W.plan_band4_c4])
+def test_library_delay_table_equals_oracle(mk):
+    p = mk()
+    plan = spl.Plan.from_dict(p)
+    dms = oracle.dm_trials(p["dm_ranges"])
+    D, ties = oracle.delay_table(p["nchans"], p["fch1"], p["foff"], p["tsamp"], dms)
+    assert ties == 0
+    assert np.array_equal(plan.dms(), dms)
+    assert np.array_equal(plan.delays().astype(np.int64), D)
+    sz = oracle.sizes(D, p["n_out"], p["widths"])
+    info = plan.info
+    assert (info["s_max"], info["n_dd"], info["n_in"]) == (sz["s_max"], sz["n_dd"], sz["n_in"])
+    assert info["ndm"] == dms.size and info["n_segments"] == 1
+
+
+def test_reversed_band_and_multi_range_plan():
+    p = W.plan_c1()
+    ranges = [(0.0, 2.0, 10), (20.0, 5.0, 7)]
+    nch = p["nchans"]
+    f_last = p["fch1"] + (nch - 1) * p["foff"]
+    plan = spl.Plan(nch, f_last, -p["foff"], p["tsamp"], 1000, ranges, (1, 2), 6.0)
+    dms = oracle.dm_trials(ranges)
+    D, _ = oracle.delay_table(nch, f_last, -p["foff"], p["tsamp"], dms)
+    assert np.array_equal(plan.delays(), D)
+    assert np.all(plan.delays()[:, -1] == 0)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(widths=(2, 1)), dict(widths=()), dict(threshold=0.0), dict(tsamp=0.0), dict(nchans=0),
+    dict(n_out=0), dict(widths=(1, 20000)), dict(norm_window=-1),
+])
+def test_plan_validation(bad):
+    args = dict(nchans=16, fch1=500.0, foff=-1.0, tsamp=1e-3, n_out=100, dm_ranges=[(0.0, 1.0, 4)],
+                widths=(1, 2), threshold=6.0)
+    args.update(bad)
+    with pytest.raises(spl.SplError):
+        spl.Plan(**args)
+
+
+def test_int32_overflow_is_refused():
+    with pytest.raises(spl.SplError) as e:
+        spl.Plan(65536, 500.0, -0.001, 1e-3, 1000, [(0.0, 1.0, 2)], (1, 256), 6.0)
+    assert e.value.status == spl.SPL_E_UNSUPPORTED
+
+
+def test_from_delays_rejects_negative():
+    with pytest.raises(spl.SplError):
+        spl.Plan(2, 500.0, -1.0, 1e-3, 10, widths=(1,), delays=np.array([[0, -1]], np.int32))
+
+
+def test_batch_layout_host_only():
+    plans = [spl.Plan.from_dict(W.plan_band3_c4()), spl.Plan.from_dict(W.plan_band4_c4())]
+    b = spl.Batch([plans[0], plans[1], plans[0]], mode=spl.MODE_PERSISTENT_GRAPH, hit_capacity=1 << 20)
+    n = b.workspace_bytes()
+    # at least the three DM transforms
+    need = sum(p.info["ndm"] * p.info["n_dd"] * 4 for p in (plans[0], plans[1], plans[0]))
+    assert n > need
+    t = b.tiles(1)
+    assert t["chan_chunk"] >= 4 and t["dm_per_wave"] in (2, 4, 8, 16)
+    with pytest.raises(spl.SplError):
+        b.set_tiles(0, 3, 1)

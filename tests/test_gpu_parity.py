@@ -1,0 +1,255 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer results (DM transform, moments, candidate lists incl. widths and boxcar
+sums) must match bit for bit; the float32 S/N of a candidate is the binary64 S/N
+of the oracle rounded to float32, so it matches exactly too (tolerance 0).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_27262_amd import synth
+from paper_2606_27262_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_27262_amd import spotlight
+    return spotlight
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(spl, plans, blocks, mode=0, hit_capacity=0, cand_cap=1 << 16, batch=None):
+    if batch is None:
+        batch = spl.Batch(plans, mode=mode, hit_capacity=hit_capacity)
+    tb = [spl.upload_block(x) for x in blocks]
+    cands = spl.new_candidates(cand_cap)
+    cands, stats = batch.run(tb, cands)
+    torch.cuda.synchronize()
+    out = {"cands": spl.candidates_to_numpy(cands, stats), "stats": spl.stats_dict(stats),
+           "batch": batch, "X": [], "S1": [], "S2": []}
+    for b, p in enumerate(plans):
+        out["X"].append(batch.dm_transform(b)[:, :p.info["n_dd"]].cpu().numpy().astype(np.int64))
+        s1, s2 = batch.moments(b)
+        out["S1"].append(s1.cpu().numpy())
+        out["S2"].append(s2.cpu().numpy())
+    return out
+
+
+def oracle_run(plans, blocks, stencils=((1, 1), (5, 5))):
+    res = []
+    for b, (p, x) in enumerate(zip(plans, blocks)):
+        i = p.info
+        D = p.delays().astype(np.int64)
+        widths = p.widths_
+        r = oracle.search_beam(x[:, :i["n_in"]], D, p.dms(), i["n_out"], i["norm_window"], widths,
+                               i["threshold"], stencils=p.stencils_, beam=b)
+        n, s1, s2 = oracle.moments(r["X"], i["n_out"], i["norm_window"])
+        r["S1"], r["S2"] = s1, s2
+        res.append(r)
+    cands = np.concatenate([r["cands"] for r in res]) if res else np.zeros(0, oracle.CAND_DTYPE)
+    return res, cands
+
+
+def make_plan(spl, nch, ndm, n_out, widths, theta, L=0, delays=None, dms=None, stencils=((1, 1), (5, 5)),
+              plan_dict=None):
+    if plan_dict is not None:
+        p = spl.Plan.from_dict(plan_dict, stencils=stencils)
+        p.widths_ = tuple(plan_dict["widths"])
+    else:
+        p = spl.Plan(nch, 500.0, -0.5, 1e-3, n_out, widths=widths, threshold=theta, norm_window=L,
+                     delays=delays, dms=dms, stencils=stencils)
+        p.widths_ = tuple(widths)
+    p.stencils_ = tuple(stencils)
+    return p
+
+
+def compare(g, ref_beams, ref_cands, check_X=True):
+    for b, r in enumerate(ref_beams):
+        if check_X:
+            assert np.array_equal(g["X"][b], r["X"]), f"X differs (beam {b})"
+            assert np.array_equal(g["S1"][b], r["S1"]) and np.array_equal(g["S2"][b], r["S2"]), f"moments (beam {b})"
+    assert g["stats"]["hit_overflow"] == 0
+    assert g["stats"]["n_hits"] == sum(r["hits"]["d"].size for r in ref_beams)
+    assert g["cands"].size == ref_cands.size, (g["cands"].size, ref_cands.size)
+    assert np.array_equal(g["cands"], ref_cands)
+
+
+def test_normaliser_hook_matches_oracle(spl):
+    rng = np.random.default_rng(0)
+    n = rng.integers(1, 40000, 4000).astype(np.int64)
+    v = rng.integers(0, 1_100_000, 4000).astype(np.int64)
+    s1 = n * v + rng.integers(0, 1000, 4000)
+    var = rng.integers(0, 1 << 40, 4000)
+    s2 = np.minimum(n * v * v + var, (1 << 62))
+    # consistent moments for the edge cases: constant rows (V = 0) and tiny V
+    s1[:10] = n[:10] * v[:10]
+    s2[:10] = n[:10] * v[:10] * v[:10]
+    s2[10:20] = n[10:20] * v[10:20] * v[10:20] + 1
+    s1[10:20] = n[10:20] * v[10:20]
+    ok = (n.astype(object) * s2.astype(object) - s1.astype(object) ** 2) >= 0
+    n, s1, s2 = n[ok], s1[ok], s2[ok]
+    mu, sg = spl.debug_mu_sigma(torch.from_numpy(n).cuda(), torch.from_numpy(s1).cuda(), torch.from_numpy(s2).cuda())
+    mu, sg = mu.cpu().numpy(), sg.cpu().numpy()
+    for k in range(n.size):
+        m, s = oracle.mu_sigma(n[k], s1[k], s2[k])
+        assert mu[k] == m and sg[k] == s, (k, n[k], s1[k], s2[k], mu[k], m, sg[k], s)
+
+
+def _random_monotone_delays(rng, ndm, nch, smax):
+    steps = rng.integers(0, 3, size=(ndm, nch))
+    D = np.cumsum(np.cumsum(steps, axis=1), axis=0)
+    D = D - D[:, :1]
+    if D.max() > smax:
+        D = (D * smax) // max(1, D.max())
+    return D.astype(np.int32)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_small_random_batches(spl, mode):
+    """Uneven small plans in one batch (ragged tiles, several segments, odd sizes)."""
+    rng = np.random.default_rng(11 + mode)
+    for trial in range(4):
+        plans, blocks = [], []
+        for b in range(int(rng.integers(1, 4))):
+            nch = int(rng.integers(1, 80))
+            ndm = int(rng.integers(1, 70))
+            n_out = int(rng.integers(1, 3000))
+            widths = tuple(sorted(set(int(w) for w in rng.choice([1, 2, 3, 4, 8, 16, 33], size=3))))
+            widths = tuple(w for w in widths if w <= n_out) or (1,)
+            L = int(rng.integers(1, n_out + 1)) if rng.random() < 0.5 else 0
+            D = _random_monotone_delays(rng, ndm, nch, int(rng.integers(0, 400)))
+            p = make_plan(spl, nch, ndm, n_out, widths, 2.0, L=L, delays=D)
+            x = rng.integers(0, 256, size=(nch, p.info["n_in"]), dtype=np.uint8)
+            if rng.random() < 0.3:
+                x[:] = 7   # constant input: sigma = 0, no hits
+            plans.append(p)
+            blocks.append(x)
+        say("trial", trial, [(p.info["nchans"], p.info["ndm"], p.info["n_out"]) for p in plans])
+        g = gpu_run(spl, plans, blocks, mode=mode)
+        ref, rc = oracle_run(plans, blocks)
+        compare(g, ref, rc)
+
+
+def test_c1_full(spl):
+    p = make_plan(spl, 0, 0, 0, None, 0, plan_dict=W.plan_c1())
+    _, x = W.c1_block(p.info["n_in"], seed=1)
+    blocks = [x[:, :p.info["n_in"]]]
+    g = gpu_run(spl, [p], blocks)
+    ref, rc = oracle_run([p], blocks)
+    compare(g, ref, rc)
+    best = g["cands"][np.argmax(g["cands"]["snr"])]
+    assert best["dm_index"] == 64 and abs(int(best["t_sample"]) - 4096) <= 8
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_c2_full_size(spl, mode):
+    """4096 channels, 2048 trials, 16384 samples, 20 pulses, 2% RFI: DM-0 row = channel
+    sum, sampled DM-transform entries by direct summation, moments, and the candidate
+    list of the oracle's search run on the GPU's DM transform."""
+    pd = W.plan_c2()
+    p = make_plan(spl, 0, 0, 0, None, 0, plan_dict=pd)
+    i = p.info
+    _, x = W.c2_like_block(pd, i["n_in"], seed=2, beam=0, n_pulses=20)
+    x = x[:, :i["n_in"]]
+    say("c2 block generated", x.shape)
+    g = gpu_run(spl, [p], [x], mode=mode)
+    X = g["X"][0]
+    assert np.array_equal(X[0], x[:, :i["n_dd"]].astype(np.int64).sum(0))
+    D = p.delays().astype(np.int64)
+    rng = np.random.default_rng(5)
+    ds = rng.integers(0, i["ndm"], 3000)
+    ts = rng.integers(0, i["n_dd"], 3000)
+    ds[:8] = i["ndm"] - 1
+    ts[:8] = i["n_dd"] - 1 - np.arange(8)
+    ch = np.arange(i["nchans"])
+    for d, t in zip(ds, ts):
+        assert X[d, t] == int(x[ch, t + D[d]].astype(np.int64).sum())
+    n, s1, s2 = oracle.moments(X, i["n_out"], i["norm_window"])
+    assert np.array_equal(g["S1"][0], s1) and np.array_equal(g["S2"][0], s2)
+    hits = oracle.search(X, i["n_out"], i["norm_window"], pd["widths"], pd["threshold"])
+    alive = oracle.nms(hits, i["ndm"], i["n_out"])
+    rc = oracle.candidates(0, hits, alive, p.dms())
+    say("c2 hits", hits["d"].size, "candidates", rc.size)
+    assert g["stats"]["n_hits"] == hits["d"].size
+    assert np.array_equal(g["cands"], rc)
+
+
+def test_tile_shapes_give_identical_results(spl):
+    pd = W.make_plan(512, 300.0, 500.0, 1.31072e-3, 3000, 0.0, 300.0, 100, W.W64)
+    p = make_plan(spl, 0, 0, 0, None, 0, plan_dict=pd)
+    rng = np.random.default_rng(3)
+    x = rng.integers(0, 256, size=(512, p.info["n_in"]), dtype=np.uint8)
+    ref, rc = oracle_run([p], [x])
+    batch = spl.Batch([p])
+    for dw, j in ((2, 2), (2, 4), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2), (16, 1)):
+        for cc in (0, 4, 100, 256):
+            try:
+                batch.set_tiles(0, dw, j, cc)
+            except spl.SplError:
+                continue
+            say("tiles", dw, j, cc, batch.tiles(0))
+            g = gpu_run(spl, [p], [x], batch=batch)
+            compare(g, ref, rc)
+
+
+def test_graph_replays_match_eager(spl):
+    """Graph mode replayed on new block contents (same buffers) with eager runs in
+    between; every replay equals the plain mode's result."""
+    plans = [make_plan(spl, 0, 0, 0, None, 0, plan_dict=W.plan_c1()) for _ in range(3)]
+    n_in = plans[0].info["n_in"]
+    gb = spl.Batch(plans, mode=spl.MODE_PERSISTENT_GRAPH)
+    eb = spl.Batch(plans, mode=spl.MODE_PLAIN_PER_BEAM)
+    bufs = [torch.zeros((256, (n_in + 255) // 256 * 256), dtype=torch.uint8, device="cuda") for _ in range(3)]
+    cg, ce = spl.new_candidates(1 << 14), spl.new_candidates(1 << 14)
+    sg = torch.zeros(spl.STATS_WORDS, dtype=torch.int64, device="cuda")
+    se = torch.zeros(spl.STATS_WORDS, dtype=torch.int64, device="cuda")
+    for rep in range(4):
+        for b in range(3):
+            _, x = W.c1_block(n_in, seed=100 + 10 * rep + b, beam=b)
+            bufs[b].copy_(torch.from_numpy(x[:, :bufs[b].shape[1]]).cuda())
+        gb.run(bufs, cg, sg)
+        eb.run(bufs, ce, se)
+        torch.cuda.synchronize()
+        a = spl.candidates_to_numpy(cg, sg)
+        e = spl.candidates_to_numpy(ce, se)
+        say("replay", rep, a.size)
+        assert a.size > 0 and np.array_equal(a, e)
+        assert spl.stats_dict(sg) == spl.stats_dict(se)
+
+
+def test_capacity_flags(spl):
+    p = make_plan(spl, 0, 0, 0, None, 0, plan_dict=W.plan_c1())
+    _, x = W.c1_block(p.info["n_in"], seed=1)
+    x = x[:, :p.info["n_in"]]
+    ref, rc = oracle_run([p], [x])
+    assert rc.size > 3
+    g = gpu_run(spl, [p], [x], cand_cap=3)
+    assert g["stats"]["cand_overflow"] == 1 and g["stats"]["n_candidates"] == rc.size
+    assert np.array_equal(g["cands"], rc[:3])
+    nh = ref[0]["hits"]["d"].size
+    g2 = gpu_run(spl, [p], [x], hit_capacity=max(1, nh // 2))
+    assert g2["stats"]["hit_overflow"] == 1 and g2["stats"]["n_hits"] == nh
+
+
+def test_degenerate_shapes(spl):
+    rng = np.random.default_rng(8)
+    cases = [(1, 1, 1, (1,)), (1, 3, 5, (1, 2)), (3, 1, 7, (1, 7)), (64, 2, 1025, (1, 4)), (257, 5, 300, (1,))]
+    for nch, ndm, n_out, widths in cases:
+        D = _random_monotone_delays(rng, ndm, nch, 50)
+        p = make_plan(spl, nch, ndm, n_out, widths, 1.0, delays=D, stencils=())
+        x = rng.integers(0, 256, size=(nch, p.info["n_in"]), dtype=np.uint8)
+        g = gpu_run(spl, [p], [x])
+        ref, rc = oracle_run([p], [x])
+        compare(g, ref, rc)
