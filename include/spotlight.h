@@ -156,7 +156,8 @@ void spl_plan_destroy(spl_plan *plan);
 typedef struct spl_batch_opts {
     int32_t mode;
     int32_t reserved0;
-    int64_t hit_capacity;  /* boxcar hits held between search and peak filter; 0: default */
+    int64_t hit_capacity;  /* boxcar hits held between search and peak filter;
+                              0: one per 16 owned (DM trial, sample) cells, at least 2^24 */
 } spl_batch_opts;
 
 /*
@@ -229,19 +230,34 @@ spl_status spl_batch_dm_transform(const spl_batch *batch, int32_t beam, const in
 spl_status spl_batch_moments(const spl_batch *batch, int32_t beam, const int64_t **d_S1,
                              const int64_t **d_S2);
 
-/* Dedispersion tiling of one beam: dm_per_wave DM trials per wavefront (4 wavefronts
- * per workgroup), time_groups groups of 256 samples per workgroup, chan_chunk channels
- * staged in LDS per step (<= 256). */
+/* Dedispersion tiling of one beam: a workgroup of `waves` wavefronts sums a tile of
+ * waves*dm_per_wave DM trials by time_groups*256 samples; chan_chunk channels are staged
+ * in LDS per step (a power of two <= 4*waves; 0: the largest that fits a 64 KiB budget). */
 typedef struct spl_tiles {
     int32_t dm_per_wave;
     int32_t time_groups;
     int32_t chan_chunk;
-    int32_t reserved0;
+    int32_t waves;       /* 4 or 8; 0 selects 4 */
 } spl_tiles;
 spl_status spl_batch_get_tiles(const spl_batch *batch, int32_t beam, spl_tiles *tiles);
 /* Set the tiling of every beam sharing beam's plan; SPL_E_UNSUPPORTED if the shape is
- * not compiled in or does not fit the LDS.  Call spl_batch_set_workspace afterwards. */
+ * not compiled in, does not fit the LDS or a tile's delay spread exceeds the staged
+ * rows.  Call spl_batch_set_workspace afterwards. */
 spl_status spl_batch_set_tiles(spl_batch *batch, int32_t beam, const spl_tiles *tiles);
+
+/* Stage timing.  With profiling on, every run executes its launch sequence eagerly
+ * (no graph) and records a pair of timing events on the run's stream around each
+ * stage of each pass.  spl_batch_stage_times waits for the recorded events, adds
+ * their elapsed times (ms) and counts to running totals and returns the totals in
+ * ms[SPL_N_STAGES] and count[SPL_N_STAGES] (either may be NULL); reset != 0 clears
+ * the totals afterwards.  Stage DEDISP covers the dedispersion kernel launches only. */
+#define SPL_STAGE_DEDISP 0     /* brute-force dedispersion                      */
+#define SPL_STAGE_THRESHOLDS 1 /* moments, mean/sigma, integer thresholds       */
+#define SPL_STAGE_BOXCAR 2     /* boxcar filters, hit counting and emission     */
+#define SPL_STAGE_PEAKS 3      /* peak filters and candidate compaction         */
+#define SPL_N_STAGES 4
+spl_status spl_batch_set_profiling(spl_batch *batch, int32_t enable);
+spl_status spl_batch_stage_times(spl_batch *batch, double *ms, int64_t *count, int32_t reset);
 
 void spl_batch_destroy(spl_batch *batch);
 

@@ -62,8 +62,14 @@ def _load():
         lib.orc_nms.restype = i32
         lib.orc_dbscan.argtypes = [P, P, i64, f64, i32, P]
         lib.orc_dbscan.restype = i32
+        lib.orc_num_threads.argtypes = []
+        lib.orc_num_threads.restype = i32
         _lib = lib
     return _lib
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
 
 
 def _p(a: np.ndarray):

@@ -31,11 +31,24 @@
  * design notes of the repository; each is restated at the function below.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define ORC_DISPERSION_CONSTANT 4148.8064239 /* MHz^2 pc^-1 cm^3 s, Eq. (1) */
+
+/* Threads the oracle's parallel loops use. */
+int32_t orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Eq. (1): integer delay table                                               */

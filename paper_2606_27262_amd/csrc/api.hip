@@ -221,7 +221,7 @@ extern "C" void spl_plan_destroy(spl_plan *p) { delete p; }
 namespace {
 
 struct Tiles {
-    int dw = 8, j = 2, cc = 64;
+    int dw = 4, j = 2, nw = 8, cc = 0;
 };
 
 // Everything that depends on one plan and its tiling.
@@ -229,7 +229,9 @@ struct PlanLayout {
     const spl_plan *plan = nullptr;
     Tiles tiles;
     int td = 0, ndm_pad = 0, ntile_d = 0, ntile_t = 0;
-    std::vector<int32_t> dcm;        // [nch][ndm_pad]
+    std::vector<int32_t> dcm;        // delays [nch][ndm_pad]
+    std::vector<int32_t> dtab;       // LDS byte offsets [nch][ndm_pad]
+    int half = 0;                    // byte offset of the odd-aligned copy
     std::vector<int32_t> tile_base;  // [ntile_d][nch]
     std::vector<int32_t> row_bytes;  // [ntile_d]
     size_t off_dcm = 0, off_base = 0, off_dms = 0;
@@ -256,7 +258,7 @@ struct spl_batch {
     int max_nst = 0, w_max = 0;
     std::vector<DedispItem> items;
     // shape groups for the persistent launch
-    struct Group { int dw, j; int item_lo, item_hi; size_t lds; int occ; };
+    struct Group { int dw, j, nw; int item_lo, item_hi; size_t lds; int occ; };
     std::vector<Group> groups;
     std::vector<size_t> beam_lds;          // per beam (plain per-beam launches)
     // workspace
@@ -275,6 +277,13 @@ struct spl_batch {
     bool staging_pending = false;
     std::vector<const uint8_t *> cur_x;
     std::vector<int64_t> cur_pitch;
+    // stage timing (eager runs only): pairs of events per enqueued stage
+    bool profiling = false;
+    struct Timed { int stage; hipEvent_t a, b; };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> free_events;
+    double stage_ms[SPL_N_STAGES] = {0};
+    int64_t stage_count[SPL_N_STAGES] = {0};
     // graph cache
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -285,10 +294,13 @@ struct spl_batch {
 
 static spl_status layout_plan(PlanLayout &L) {
     const spl_plan &p = *L.plan;
-    if (!dedisp_shape_supported(L.tiles.dw, L.tiles.j))
-        return fail(SPL_E_UNSUPPORTED, "dedispersion tile shape (%d, %d) is not compiled in", L.tiles.dw, L.tiles.j);
-    if (L.tiles.cc < 0 || L.tiles.cc > 256) return fail(SPL_E_UNSUPPORTED, "chan_chunk must be in [0, 256]");
-    L.td = 4 * L.tiles.dw;
+    if (!dedisp_shape_supported(L.tiles.dw, L.tiles.j, L.tiles.nw))
+        return fail(SPL_E_UNSUPPORTED, "dedispersion tile shape (%d, %d, %d) is not compiled in", L.tiles.dw,
+                    L.tiles.j, L.tiles.nw);
+    if (L.tiles.cc < 0 || L.tiles.cc > kDedispStageRows * L.tiles.nw)
+        return fail(SPL_E_UNSUPPORTED, "chan_chunk must be in [0, %d] for %d wavefronts", kDedispStageRows * L.tiles.nw,
+                    L.tiles.nw);
+    L.td = L.tiles.nw * L.tiles.dw;
     L.ndm_pad = (p.ndm + L.td - 1) / L.td * L.td;
     L.ntile_d = L.ndm_pad / L.td;
     const int TT = 256 * L.tiles.j;
@@ -313,30 +325,82 @@ static spl_status layout_plan(PlanLayout &L) {
             L.tile_base[(size_t)k * p.nch + c] = lo;
             span = std::max(span, hi - lo);
         }
-        L.row_bytes[k] = TT + 32 + (int)align_up((size_t)span, 16);
+        // one copy of a staged row: 16-bit samples covering the tile's time span,
+        // its spread of delays and 16-sample alignment slack
+        L.row_bytes[k] = 2 * (TT + 32 + (int)align_up((size_t)span, 16));
+        if (L.row_bytes[k] / 32 > kDedispMaxRowVecs)
+            return fail(SPL_E_UNSUPPORTED, "DM tile %d spans %d samples of delay: too wide for the staged rows of "
+                        "this tile shape (use fewer trials per tile)", k, span);
     }
     return SPL_OK;
 }
 
+// Default tiling: 8 wavefronts x 4 trials x 512 samples, smaller tiles when the plan
+// gives too few work items to fill 256 compute units, fewer trials per tile when the
+// delay spread of a tile would not fit the staged rows.
+static bool tile_fits(const spl_plan &p, int td, int j) {
+    // widest delay spread over td consecutive trials, any channel
+    int worst = 0;
+    for (int c = 0; c < p.nch; c += std::max(1, p.nch / 64)) {
+        for (int d0 = 0; d0 < p.ndm; d0 += td) {
+            const int d1 = std::min(p.ndm, d0 + td) - 1;
+            worst = std::max(worst, std::abs(p.delays[(size_t)d1 * p.nch + c] - p.delays[(size_t)d0 * p.nch + c]));
+        }
+    }
+    const int c = p.nch - 1;
+    for (int d0 = 0; d0 < p.ndm; d0 += td) {
+        const int d1 = std::min(p.ndm, d0 + td) - 1;
+        worst = std::max(worst, std::abs(p.delays[(size_t)d1 * p.nch + c] - p.delays[(size_t)d0 * p.nch + c]));
+    }
+    return 2 * (256 * j + 32 + (int)align_up((size_t)worst + 64, 16)) / 32 <= kDedispMaxRowVecs;
+}
+
 static Tiles default_tiles(const spl_plan &p) {
+    static const int shapes[][3] = {{4, 2, 8}, {4, 1, 8}, {2, 2, 8}, {4, 1, 4}};
+    for (const auto &sh : shapes) {
+        Tiles t;
+        t.dw = sh[0];
+        t.j = sh[1];
+        t.nw = sh[2];
+        const int td = t.dw * t.nw;
+        const int64_t items = (int64_t)((p.ndm + td - 1) / td) * ((p.n_dd + 256 * t.j - 1) / (256 * t.j));
+        if (items < 1024 && &sh != &shapes[3]) continue;
+        if (!tile_fits(p, td, t.j)) continue;
+        return t;
+    }
     Tiles t;
-    // enough work items to fill 256 compute units several times over
-    const int ttiles = (p.n_dd + 511) / 512;
-    t.dw = 8;
-    t.j = 2;
-    if ((int64_t)((p.ndm + 31) / 32) * ttiles < 1024) t.dw = 4;
-    if ((int64_t)((p.ndm + 15) / 16) * ((p.n_dd + 255) / 256) < 2048 && t.dw == 4) t.j = 1;
-    t.cc = 0;   // chosen from the LDS budget
+    t.dw = 4;
+    t.j = 1;
+    t.nw = 4;
     return t;
 }
 
+// Channels per staging step: the largest power of two <= 256 whose two copies fit the
+// LDS budget (a caller-set value is rounded down to a power of two).  Then the table
+// of LDS byte offsets of every delay.
 static void choose_chunk(PlanLayout &L, size_t lds_budget) {
-    if (L.tiles.cc > 0) return;
     const int rmax = *std::max_element(L.row_bytes.begin(), L.row_bytes.end());
-    int cc = (int)(lds_budget / (size_t)rmax);
-    cc = std::max(4, std::min(256, cc));
-    cc = cc / 4 * 4;
-    L.tiles.cc = cc;
+    int cc = L.tiles.cc;
+    if (cc <= 0) {
+        cc = kDedispStageRows * L.tiles.nw;
+        while (cc > 1 && (size_t)2 * cc * rmax > lds_budget) cc >>= 1;
+    }
+    int p2 = 1;
+    while (p2 * 2 <= std::min(cc, 256)) p2 *= 2;
+    L.tiles.cc = p2;
+    L.half = p2 * rmax;
+    const spl_plan &p = *L.plan;
+    L.dtab.assign(L.dcm.size(), 0);
+    for (int c = 0; c < p.nch; ++c) {
+        for (int d = 0; d < L.ndm_pad; ++d) {
+            const size_t k = (size_t)c * L.ndm_pad + d;
+            const int sv = L.dcm[k];
+            // the row of channel c in DM tile d/td starts at sample t0 + (base & ~15)
+            const int b16 = L.tile_base[(size_t)(d / L.td) * p.nch + c] & ~15;
+            L.dtab[k] = 4 * (sv >> 1) + (sv & 1) * L.half - 2 * b16;
+        }
+    }
+    (void)p;
 }
 
 static spl_status build_layout(spl_batch *B) {
@@ -344,7 +408,7 @@ static spl_status build_layout(spl_batch *B) {
     for (auto &L : B->layouts) {
         spl_status st = layout_plan(L);
         if (st != SPL_OK) return st;
-        choose_chunk(L, 40 * 1024);
+        choose_chunk(L, 64 * 1024);
     }
     const int nb = B->nb;
     B->row_base.assign(nb + 1, 0);
@@ -360,11 +424,11 @@ static spl_status build_layout(spl_batch *B) {
         const Tiles &t = B->layouts[B->layout_of_beam[b]].tiles;
         int g = -1;
         for (size_t k = 0; k < B->groups.size(); ++k)
-            if (B->groups[k].dw == t.dw && B->groups[k].j == t.j) g = (int)k;
+            if (B->groups[k].dw == t.dw && B->groups[k].j == t.j && B->groups[k].nw == t.nw) g = (int)k;
         if (g < 0) {
             if ((int)B->groups.size() >= kMaxShapeGroups)
                 return fail(SPL_E_UNSUPPORTED, "at most %d distinct tile shapes per batch", kMaxShapeGroups);
-            B->groups.push_back({t.dw, t.j, 0, 0, 0, 0});
+            B->groups.push_back({t.dw, t.j, t.nw, 0, 0, 0, 0});
         }
     }
     std::vector<std::vector<DedispItem>> per_beam(nb);
@@ -375,8 +439,7 @@ static spl_status build_layout(spl_batch *B) {
         for (int tt = 0; tt < L.ntile_t; ++tt)
             for (int k = 0; k < L.ntile_d; ++k)
                 per_beam[b].push_back({b, k * L.td, tt * TT, L.row_bytes[k]});
-        const int rmax = *std::max_element(L.row_bytes.begin(), L.row_bytes.end());
-        B->beam_lds[b] = (size_t)L.tiles.cc * rmax;
+        B->beam_lds[b] = (size_t)2 * L.half + (size_t)L.tiles.cc * L.td * sizeof(int32_t);
         B->max_nst = std::max(B->max_nst, p.nst);
         B->w_max = std::max(B->w_max, p.w_max);
     }
@@ -394,7 +457,7 @@ static spl_status build_layout(spl_batch *B) {
         size_t lds = 0;
         for (int b = 0; b < nb; ++b) {
             const Tiles &t = B->layouts[B->layout_of_beam[b]].tiles;
-            if (t.dw != g.dw || t.j != g.j) continue;
+            if (t.dw != g.dw || t.j != g.j || t.nw != g.nw) continue;
             B->item_base[b] = (int)B->items.size();
             B->items.insert(B->items.end(), per_beam[b].begin(), per_beam[b].end());
             lds = std::max(lds, B->beam_lds[b]);
@@ -418,7 +481,7 @@ static spl_status build_layout(spl_batch *B) {
     B->off_items = take(sizeof(DedispItem) * std::max(1, B->n_items));
     for (auto &L : B->layouts) {
         const spl_plan &p = *L.plan;
-        L.off_dcm = take(L.dcm.size() * sizeof(int32_t));
+        L.off_dcm = take(L.dtab.size() * sizeof(int32_t));
         L.off_base = take(L.tile_base.size() * sizeof(int32_t));
         L.off_dms = take((size_t)p.ndm * sizeof(double));
     }
@@ -482,7 +545,14 @@ extern "C" spl_status spl_batch_create(const spl_plan *const *plans, int32_t n_b
         delete B;
         return fail(SPL_E_INVALID_ARG, "unknown mode %d", opts->mode);
     }
-    B->hit_cap = (opts && opts->hit_capacity > 0) ? opts->hit_capacity : ((int64_t)1 << 24);
+    if (opts && opts->hit_capacity > 0) {
+        B->hit_cap = opts->hit_capacity;
+    } else {
+        // default: one hit per 16 owned (DM, t) cells of the batch, at least 2^24
+        int64_t cells = 0;
+        for (int b = 0; b < n_beams; ++b) cells += (int64_t)plans[b]->ndm * plans[b]->n_out;
+        B->hit_cap = std::min<int64_t>(((int64_t)1 << 31) - 1, std::max<int64_t>((int64_t)1 << 24, cells / 16));
+    }
     if (B->hit_cap > ((int64_t)1 << 31)) {
         delete B;
         return fail(SPL_E_UNSUPPORTED, "hit capacity above 2^31");
@@ -525,7 +595,7 @@ static void fill_host_beams(spl_batch *B) {
         std::memset(&d, 0, sizeof d);
         d.x = B->cur_x[b];
         d.pitch = B->cur_pitch[b];
-        d.dcm = (const int32_t *)(B->ws + L.off_dcm);
+        d.dtab = (const int32_t *)(B->ws + L.off_dcm);
         d.tile_base = (const int32_t *)(B->ws + L.off_base);
         d.X = (int32_t *)(B->ws + B->off_X[b]);
         d.S1 = (int64_t *)(B->ws + B->off_S[b]);
@@ -548,6 +618,7 @@ static void fill_host_beams(spl_batch *B) {
         d.chunk_base = B->chunk_base[b];
         d.nchunk_t = (p.n_out + kBoxTile - 1) / kBoxTile;
         d.chan_chunk = L.tiles.cc;
+        d.lds_half = L.half;
         d.tile_dm = L.td;
         d.beam = b;
         d.w_max = p.w_max;
@@ -574,7 +645,8 @@ extern "C" spl_status spl_batch_set_workspace(spl_batch *B, void *d_ws, size_t b
     }
     B->ws = (char *)d_ws;
     for (auto &L : B->layouts) {
-        HIP_TRY(hipMemcpy(B->ws + L.off_dcm, L.dcm.data(), L.dcm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(B->ws + L.off_dcm, L.dtab.data(), L.dtab.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(B->ws + L.off_base, L.tile_base.data(), L.tile_base.size() * sizeof(int32_t),
                           hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(B->ws + L.off_dms, L.plan->dms.data(), L.plan->dms.size() * sizeof(double),
@@ -587,13 +659,13 @@ extern "C" spl_status spl_batch_set_workspace(spl_batch *B, void *d_ws, size_t b
     HIP_TRY(hipMemcpy(B->ws + B->off_beams, B->host_beams.data(), sizeof(DevBeam) * B->nb, hipMemcpyHostToDevice));
     for (auto &g : B->groups) {
         int occ = 0;
-        HIP_TRY(prepare_dedisp(g.dw, g.j, g.lds, &occ));
+        HIP_TRY(prepare_dedisp(g.dw, g.j, g.nw, g.lds, &occ));
         g.occ = std::max(1, occ);
     }
     for (int b = 0; b < B->nb; ++b) {
         const Tiles &t = B->layouts[B->layout_of_beam[b]].tiles;
         int occ = 0;
-        HIP_TRY(prepare_dedisp(t.dw, t.j, B->beam_lds[b], &occ));
+        HIP_TRY(prepare_dedisp(t.dw, t.j, t.nw, B->beam_lds[b], &occ));
     }
     if (B->graph_exec) {
         (void)hipGraphExecDestroy(B->graph_exec);
@@ -606,6 +678,37 @@ extern "C" spl_status spl_batch_set_workspace(spl_batch *B, void *d_ws, size_t b
     B->tables_uploaded = true;
     return SPL_OK;
 }
+
+static hipError_t take_event(spl_batch *B, hipEvent_t *e) {
+    if (!B->free_events.empty()) {
+        *e = B->free_events.back();
+        B->free_events.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+// Records an event pair around one stage when profiling is on.
+struct StageTimer {
+    spl_batch *B;
+    hipStream_t s;
+    int stage;
+    hipEvent_t a = nullptr;
+    hipError_t err = hipSuccess;
+    StageTimer(spl_batch *b, hipStream_t st, int k) : B(b), s(st), stage(k) {
+        if (!B->profiling) return;
+        err = take_event(B, &a);
+        if (err == hipSuccess) err = hipEventRecord(a, s);
+    }
+    hipError_t stop() {
+        if (!B->profiling || err != hipSuccess) return err;
+        hipEvent_t b = nullptr;
+        err = take_event(B, &b);
+        if (err == hipSuccess) err = hipEventRecord(b, s);
+        if (err == hipSuccess) B->timed.push_back({stage, a, b});
+        return err;
+    }
+};
 
 // The launch sequence of one beam range [b_lo, b_hi).
 static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persistent, spl_candidate *cands,
@@ -624,14 +727,16 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
     int64_t *pos = (int64_t *)(B->ws + B->off_pos);
     const int64_t cap = B->hit_cap;
 
-    // 1. dedispersion (+ moments)
+    // 1. dedispersion
+    StageTimer t_dd(B, s, SPL_STAGE_DEDISP);
     if (persistent) {
         for (size_t g = 0; g < B->groups.size(); ++g) {
             const auto &G = B->groups[g];
             const int n = G.item_hi - G.item_lo;
             if (n <= 0) continue;
             const int grid = std::min(n, G.occ * 256);
-            HIP_TRY(launch_dedisp(G.dw, G.j, beams, items, G.item_lo, G.item_hi, &run->queue[g], grid, G.lds, s));
+            HIP_TRY(launch_dedisp(G.dw, G.j, G.nw, beams, items, G.item_lo, G.item_hi, &run->queue[g], grid, G.lds,
+                                  s));
         }
     } else {
         for (int b = b_lo; b < b_hi; ++b) {
@@ -639,11 +744,14 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
             const int lo = B->item_base[b];
             const PlanLayout &L = B->layouts[B->layout_of_beam[b]];
             const int hi = lo + L.ntile_d * L.ntile_t;
-            HIP_TRY(launch_dedisp(t.dw, t.j, beams, items, lo, hi, nullptr, hi - lo, B->beam_lds[b], s));
+            HIP_TRY(launch_dedisp(t.dw, t.j, t.nw, beams, items, lo, hi, nullptr, hi - lo, B->beam_lds[b], s));
         }
     }
+    HIP_TRY(t_dd.stop());
     // 2. normaliser and integer thresholds
+    StageTimer t_th(B, s, SPL_STAGE_THRESHOLDS);
     HIP_TRY(launch_thresholds(beams, b_lo, b_hi, row_lo, row_hi, s));
+    HIP_TRY(t_th.stop());
     // 3. boxcar hits: count, scan, emit in (row, t) order
     int w_max = 1;
     int max_nst = 0;
@@ -651,12 +759,15 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
         w_max = std::max(w_max, B->plans[b]->w_max);
         max_nst = std::max(max_nst, B->plans[b]->nst);
     }
+    StageTimer t_bc(B, s, SPL_STAGE_BOXCAR);
     HIP_TRY(launch_boxcar(false, beams, b_lo, b_hi, chunk_lo, chunk_hi, w_max, counts, nullptr, nullptr, 0, s));
     HIP_TRY(launch_scan_i32(counts, nullptr, chunk_hi - chunk_lo, block_sums, chunk_off, &run->n_hits, s));
     HIP_TRY(launch_row_start(beams, b_lo, b_hi, row_lo, row_hi, chunk_lo, chunk_off, &run->n_hits, cap, row_start,
                              s));
     HIP_TRY(launch_boxcar(true, beams, b_lo, b_hi, chunk_lo, chunk_hi, w_max, nullptr, chunk_off, hits, cap, s));
+    HIP_TRY(t_bc.stop());
     // 4. peak filters, then ordered compaction into candidate records
+    StageTimer t_pk(B, s, SPL_STAGE_PEAKS);
     const uint8_t *in = nullptr;
     for (int k = 0; k < max_nst; ++k) {
         uint8_t *o = alive[k & 1];
@@ -673,6 +784,7 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
                                cands, cand_cap, s));
     }
     HIP_TRY(launch_pass_end(run, stats, cap, max_nst, s));
+    HIP_TRY(t_pk.stop());
     return SPL_OK;
 }
 
@@ -726,7 +838,7 @@ extern "C" spl_status spl_batch_run(spl_batch *B, const uint8_t *const *d_blocks
         HIP_TRY(hipEventRecord(B->staging_done, stream));
         B->staging_pending = true;
     }
-    if (B->mode == SPL_MODE_PERSISTENT_GRAPH) {
+    if (B->mode == SPL_MODE_PERSISTENT_GRAPH && !B->profiling) {
         if (stream == nullptr) return fail(SPL_E_INVALID_ARG, "graph mode needs a non-default stream");
         if (!B->graph_exec || B->g_cands != d_cands || B->g_stats != d_stats || B->g_cap != capacity) {
             if (B->graph_exec) { (void)hipGraphExecDestroy(B->graph_exec); B->graph_exec = nullptr; }
@@ -774,26 +886,29 @@ extern "C" spl_status spl_batch_get_tiles(const spl_batch *B, int32_t beam, spl_
     tiles->dm_per_wave = t.dw;
     tiles->time_groups = t.j;
     tiles->chan_chunk = t.cc;
-    tiles->reserved0 = 0;
+    tiles->waves = t.nw;
     return SPL_OK;
 }
 
 extern "C" spl_status spl_batch_set_tiles(spl_batch *B, int32_t beam, const spl_tiles *tiles) {
     if (!B || !tiles || beam < 0 || beam >= B->nb) return fail(SPL_E_INVALID_ARG, "bad argument");
-    if (!dedisp_shape_supported(tiles->dm_per_wave, tiles->time_groups))
-        return fail(SPL_E_UNSUPPORTED, "tile shape (%d, %d) is not compiled in", tiles->dm_per_wave,
-                    tiles->time_groups);
-    if (tiles->chan_chunk < 0 || tiles->chan_chunk > 256)
-        return fail(SPL_E_UNSUPPORTED, "chan_chunk must be in [0, 256] (0: from the LDS budget)");
+    const int nw = tiles->waves ? tiles->waves : 4;
+    if (!dedisp_shape_supported(tiles->dm_per_wave, tiles->time_groups, nw))
+        return fail(SPL_E_UNSUPPORTED, "tile shape (%d, %d, %d) is not compiled in", tiles->dm_per_wave,
+                    tiles->time_groups, nw);
+    if (tiles->chan_chunk < 0 || tiles->chan_chunk > kDedispStageRows * nw)
+        return fail(SPL_E_UNSUPPORTED, "chan_chunk must be in [0, %d] (0: from the LDS budget)",
+                    kDedispStageRows * nw);
     PlanLayout &L = B->layouts[B->layout_of_beam[beam]];
     const Tiles old = L.tiles;
     L.tiles.dw = tiles->dm_per_wave;
     L.tiles.j = tiles->time_groups;
+    L.tiles.nw = nw;
     L.tiles.cc = tiles->chan_chunk;
     spl_status st = build_layout(B);
     if (st == SPL_OK) {
-        const int rmax = *std::max_element(L.row_bytes.begin(), L.row_bytes.end());
-        if ((size_t)L.tiles.cc * rmax > 160 * 1024 - 256) st = fail(SPL_E_UNSUPPORTED, "tile does not fit the LDS");
+        if ((size_t)2 * L.half + (size_t)L.tiles.cc * L.td * 4 > 160 * 1024 - 256)
+            st = fail(SPL_E_UNSUPPORTED, "tile does not fit the LDS");
     }
     if (st != SPL_OK) {
         L.tiles = old;
@@ -803,8 +918,43 @@ extern "C" spl_status spl_batch_set_tiles(spl_batch *B, int32_t beam, const spl_
     return SPL_OK;
 }
 
+extern "C" spl_status spl_batch_set_profiling(spl_batch *B, int32_t enable) {
+    if (!B) return fail(SPL_E_INVALID_ARG, "NULL batch");
+    B->profiling = enable != 0;
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_batch_stage_times(spl_batch *B, double *ms, int64_t *count, int32_t reset) {
+    if (!B) return fail(SPL_E_INVALID_ARG, "NULL batch");
+    for (auto &t : B->timed) {
+        HIP_TRY(hipEventSynchronize(t.b));
+        float e = 0.f;
+        HIP_TRY(hipEventElapsedTime(&e, t.a, t.b));
+        B->stage_ms[t.stage] += e;
+        B->stage_count[t.stage] += 1;
+        B->free_events.push_back(t.a);
+        B->free_events.push_back(t.b);
+    }
+    B->timed.clear();
+    for (int k = 0; k < SPL_N_STAGES; ++k) {
+        if (ms) ms[k] = B->stage_ms[k];
+        if (count) count[k] = B->stage_count[k];
+        if (reset) {
+            B->stage_ms[k] = 0;
+            B->stage_count[k] = 0;
+        }
+    }
+    return SPL_OK;
+}
+
 extern "C" void spl_batch_destroy(spl_batch *B) {
     if (!B) return;
+    for (auto &t : B->timed) {
+        (void)hipEventSynchronize(t.b);
+        B->free_events.push_back(t.a);
+        B->free_events.push_back(t.b);
+    }
+    for (hipEvent_t e : B->free_events) (void)hipEventDestroy(e);
     if (B->staging_pending) (void)hipEventSynchronize(B->staging_done);
     if (B->graph_exec) (void)hipGraphExecDestroy(B->graph_exec);
     if (B->graph) (void)hipGraphDestroy(B->graph);

@@ -7,10 +7,12 @@
 
 namespace spl {
 
-bool dedisp_shape_supported(int dw, int j);
-hipError_t prepare_dedisp(int dw, int j, size_t lds_bytes, int *blocks_per_cu);
-hipError_t launch_dedisp(int dw, int j, const DevBeam *beams, const DedispItem *items, int item_lo, int item_hi,
-                         int *queue, int grid, size_t lds_bytes, hipStream_t s);
+constexpr int kDedispStageRows = 4;   // staged rows per wavefront and chunk
+constexpr int kDedispMaxRowVecs = 128; // 16-byte input vectors per staged row
+bool dedisp_shape_supported(int dw, int j, int nw);
+hipError_t prepare_dedisp(int dw, int j, int nw, size_t lds_bytes, int *blocks_per_cu);
+hipError_t launch_dedisp(int dw, int j, int nw, const DevBeam *beams, const DedispItem *items, int item_lo,
+                         int item_hi, int *queue, int grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_thresholds(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, int row_hi,
                              hipStream_t s);

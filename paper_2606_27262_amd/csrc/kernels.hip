@@ -29,6 +29,11 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 // wave-uniform indices become scalar loads.
 typedef __attribute__((address_space(4))) const int32_t cint32;
 __device__ __forceinline__ const cint32 *as_const(const int32_t *p) { return (const cint32 *)p; }
+// Input blocks are read through the global address space (global_load, not flat_load).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const uint8_t gu8;
+typedef __attribute__((address_space(1))) const u32x4 gu32x4;
+typedef __attribute__((address_space(1))) const uint32_t gu32;
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Correctly rounded (nearest-even) conversion of the unsigned 128-bit integer hi:lo.
@@ -116,22 +121,30 @@ __global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
 }
 
 // ------------------------------------------------------------- dedispersion
-// Workgroup = 4 wavefronts; item = (beam, DM tile of 4*DW trials, time tile of 256*J
-// samples).  Wavefront w owns DM trials d0 + w*DW ... + DW-1; lane l owns samples
-// t0 + 256 j + 4 l + {0,1,2,3}, j < J.  Channels are staged chan_chunk at a time:
-// row r of the LDS holds x[c][ws_c, ws_c + row_bytes) with ws_c the 16-aligned start
-// of the tile's smallest delay for that channel, so every trial of the tile reads its
-// shifted samples from the same staged row.  A trial's delay is wave-uniform: it is
-// loaded through the scalar unit and turned into one LDS address add and two byte-
-// select masks.  v_perm_b32 extracts bytes (t, t+2) and (t+1, t+3) into 16-bit fields,
-// accumulated exactly for up to 256 channels and then widened to int32.
-template <int DW, int J>
-__global__ __launch_bounds__(kThreads) void k_dedisp(const DevBeam *__restrict__ beams,
-                                                     const DedispItem *__restrict__ items,
-                                                     int item_lo, int item_hi, int *queue) {
+// Workgroup = NW wavefronts; item = (beam, DM tile of NW*DW trials, time tile of 256*J
+// samples).  Wavefront w owns DM trials d0 + w*DW ... + DW-1; lane l owns the sample
+// pairs t0 + 128 g + 2 l + {0,1}, g < 2J, so that the lanes of a wavefront read
+// consecutive LDS dwords (no bank conflicts).
+//
+// Channels are staged chan_chunk at a time.  Row r of the LDS holds channel c as
+// 16-bit samples starting at ws_c, the 16-aligned start of the tile's smallest delay,
+// twice: copy A at byte r*R (sample ws_c + k at 16-bit slot k) and copy B at byte
+// half + r*R (sample ws_c + k + 1 at slot k).  Every delay s then starts on a dword
+// boundary of one of the two copies, at byte 4*(s>>1) + (s&1)*half - 2*(ws_c - t0)
+// past the row's origin (ws_c - t0 depends only on the channel and the DM tile); that
+// offset is precomputed per (channel, trial) in the plan table, so a trial costs one
+// address add per channel, and each 2 groups one ds_read2st64_b32 and two packed
+// 16-bit adds (exact for up to 256 channels, then widened into int32 accumulators).  Every staged row is read by all NW*DW trials.
+// The global loads of the next chunk are issued before the current chunk is summed.
+constexpr int kStageRows = 4;   // staged rows per wavefront and chunk (chan_chunk <= 4*NW)
+constexpr int kStageVecs = 2;   // 16-byte input vectors per lane and row (row <= 2048 samples)
+
+template <int DW, int J, int NW>
+__global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ beams,
+                                                    const DedispItem *__restrict__ items,
+                                                    int item_lo, int item_hi, int *queue) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ int s_item;
-    constexpr int TT = 256 * J;
     const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
 
     int it = item_lo + blockIdx.x;
@@ -146,93 +159,150 @@ __global__ __launch_bounds__(kThreads) void k_dedisp(const DevBeam *__restrict__
 
         const DedispItem item = items[it];
         const DevBeam &B = beams[item.beam];
-        const int nch = B.nch, ndm_pad = B.ndm_pad, R = item.row_bytes;
+        const int nch = B.nch, ndm_pad = B.ndm_pad, R = item.row_bytes, half = B.lds_half;
         const int t0 = item.t0, d0 = item.d0;
         const int dw0 = d0 + wave * DW;
-        const int32_t *__restrict__ dcm = B.dcm;
+        const int32_t *__restrict__ tab = B.dtab;
         const int32_t *__restrict__ base = B.tile_base + (size_t)(d0 / B.tile_dm) * nch;
         const int64_t pitch = B.pitch;
         const uint8_t *__restrict__ x = B.x;
         const int cchunk = B.chan_chunk;
+        const int nvec = R >> 5;   // 16 input samples -> 32 bytes per copy
 
         int32_t acc[DW][4 * J];
+        uint32_t a16[DW][2 * J];
 #pragma unroll
-        for (int i = 0; i < DW; ++i)
+        for (int i = 0; i < DW; ++i) {
 #pragma unroll
             for (int k = 0; k < 4 * J; ++k) acc[i][k] = 0;
+#pragma unroll
+            for (int k = 0; k < 2 * J; ++k) a16[i][k] = 0u;
+        }
 
-        for (int c0 = 0; c0 < nch; c0 += cchunk) {
+        // staging registers: rows wave + NW*m, vectors lane + 64*q, and the chunk's slice
+        // of the offset table (cc x TD entries, thread tid takes entries tid + 64*NW*e)
+        constexpr int TD = NW * DW;
+        constexpr int kTabRegs = (4 * NW * TD + 64 * NW - 1) / (64 * NW);
+        int32_t *lds_tab = (int32_t *)(lds + 2 * half);
+        uint4 pv[kStageRows][kStageVecs];
+        uint32_t pv4[kStageRows][kStageVecs];
+        int32_t pt[kTabRegs];
+        auto load_chunk = [&](int c0) {
             const int cc = min(cchunk, nch - c0);
-            __syncthreads();
-            // stage: wavefront w copies rows w, w+4, ... ; lanes stride over 16-byte vectors
-            const int nvec = R >> 4;
-            for (int r = wave; r < cc; r += kThreads / 64) {
+#pragma unroll
+            for (int e = 0; e < kTabRegs; ++e) {
+                const int idx = tid + 64 * NW * e;
+                const int r = idx / TD, k = idx % TD;
+                pt[e] = r < cc ? tab[(size_t)(c0 + r) * ndm_pad + d0 + k] : 0;
+            }
+#pragma unroll
+            for (int m = 0; m < kStageRows; ++m) {
+                const int r = wave + NW * m;
                 const int c = c0 + r;
-                const int64_t ws = (int64_t)((t0 + as_const(base)[c]) & ~15);
-                const uint8_t *src = x + (size_t)c * pitch;
-                uint4 *dst = (uint4 *)(lds + r * R);
-                for (int k = lane; k < nvec; k += 64) {
+                const int64_t ws = r < cc ? (int64_t)((t0 + as_const(base)[c]) & ~15) : 0;
+                const gu8 *src = (const gu8 *)(x + (size_t)c * pitch);
+#pragma unroll
+                for (int q = 0; q < kStageVecs; ++q) {
+                    const int k = lane + 64 * q;
                     const int64_t off = ws + 16 * (int64_t)k;
-                    uint4 v = make_uint4(0, 0, 0, 0);
-                    if (off + 16 <= pitch) v = *(const uint4 *)(src + off);
-                    dst[k] = v;
-                }
-            }
-            __syncthreads();
-
-            uint32_t ae[DW][J], ao[DW][J];
-#pragma unroll
-            for (int i = 0; i < DW; ++i)
-#pragma unroll
-                for (int j = 0; j < J; ++j) ae[i][j] = ao[i][j] = 0u;
-
-            const uint32_t *lds32 = (const uint32_t *)lds;
-            // delays of the next channel are fetched one channel ahead
-            int32_t nd[DW];
-            int32_t nb;
-            {
-                const cint32 *drow = as_const(dcm + (size_t)c0 * ndm_pad + dw0);
-#pragma unroll
-                for (int i = 0; i < DW; ++i) nd[i] = drow[i];
-                nb = as_const(base)[c0];
-            }
-            for (int r = 0; r < cc; ++r) {
-                int32_t cd[DW];
-#pragma unroll
-                for (int i = 0; i < DW; ++i) cd[i] = nd[i];
-                const int cb = nb;
-                if (r + 1 < cc) {
-                    const cint32 *drow = as_const(dcm + (size_t)(c0 + r + 1) * ndm_pad + dw0);
-#pragma unroll
-                    for (int i = 0; i < DW; ++i) nd[i] = drow[i];
-                    nb = as_const(base)[c0 + r + 1];
-                }
-                const int ws = (t0 + cb) & ~15;
-                const int rowoff = r * R + t0 - ws;   // LDS byte of sample t0 + s is rowoff + s
-#pragma unroll
-                for (int i = 0; i < DW; ++i) {
-                    const int o = rowoff + cd[i];
-                    const uint32_t a = (uint32_t)(o & 3);
-                    const uint32_t sel_e = 0x0C000C00u | a | ((a + 2u) << 16);
-                    const uint32_t sel_o = sel_e + 0x00010001u;
-                    const uint32_t *p = lds32 + (o >> 2) + lane;
-#pragma unroll
-                    for (int j = 0; j < J; ++j) {
-                        const uint32_t lo = p[64 * j], hi = p[64 * j + 1];
-                        ae[i][j] += __builtin_amdgcn_perm(hi, lo, sel_e);
-                        ao[i][j] += __builtin_amdgcn_perm(hi, lo, sel_o);
+                    pv[m][q] = make_uint4(0, 0, 0, 0);
+                    pv4[m][q] = 0;
+                    if (r < cc && k < nvec) {
+                        if (off + 16 <= pitch) {
+                            const u32x4 w = *(const gu32x4 *)(src + off);
+                            pv[m][q] = make_uint4(w.x, w.y, w.z, w.w);
+                        }
+                        if (off + 20 <= pitch) pv4[m][q] = *(const gu32 *)(src + off + 16);
                     }
                 }
             }
+        };
+        auto store_chunk = [&](int c0) {
+            const int cc = min(cchunk, nch - c0);
 #pragma unroll
-            for (int i = 0; i < DW; ++i)
+            for (int e = 0; e < kTabRegs; ++e) {
+                const int idx = tid + 64 * NW * e;
+                if (idx / TD < cc) lds_tab[idx] = pt[e];
+            }
 #pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    acc[i][4 * j + 0] += (int32_t)(ae[i][j] & 0xFFFFu);
-                    acc[i][4 * j + 2] += (int32_t)(ae[i][j] >> 16);
-                    acc[i][4 * j + 1] += (int32_t)(ao[i][j] & 0xFFFFu);
-                    acc[i][4 * j + 3] += (int32_t)(ao[i][j] >> 16);
+            for (int m = 0; m < kStageRows; ++m) {
+                const int r = wave + NW * m;
+                uint8_t *rowA = lds + r * R;
+                uint8_t *rowB = rowA + half;
+#pragma unroll
+                for (int q = 0; q < kStageVecs; ++q) {
+                    const int k = lane + 64 * q;
+                    if (!(r < cc && k < nvec)) continue;
+                    const uint4 v = pv[m][q];
+                    const uint32_t v4 = pv4[m][q];
+                    uint4 a0, a1, b0, b1;
+                    a0.x = __builtin_amdgcn_perm(v.x, v.x, 0x0C010C00u);
+                    a0.y = __builtin_amdgcn_perm(v.x, v.x, 0x0C030C02u);
+                    a0.z = __builtin_amdgcn_perm(v.y, v.y, 0x0C010C00u);
+                    a0.w = __builtin_amdgcn_perm(v.y, v.y, 0x0C030C02u);
+                    a1.x = __builtin_amdgcn_perm(v.z, v.z, 0x0C010C00u);
+                    a1.y = __builtin_amdgcn_perm(v.z, v.z, 0x0C030C02u);
+                    a1.z = __builtin_amdgcn_perm(v.w, v.w, 0x0C010C00u);
+                    a1.w = __builtin_amdgcn_perm(v.w, v.w, 0x0C030C02u);
+                    b0.x = __builtin_amdgcn_perm(v.x, v.x, 0x0C020C01u);
+                    b0.y = __builtin_amdgcn_perm(v.y, v.x, 0x0C040C03u);
+                    b0.z = __builtin_amdgcn_perm(v.y, v.y, 0x0C020C01u);
+                    b0.w = __builtin_amdgcn_perm(v.z, v.y, 0x0C040C03u);
+                    b1.x = __builtin_amdgcn_perm(v.z, v.z, 0x0C020C01u);
+                    b1.y = __builtin_amdgcn_perm(v.w, v.z, 0x0C040C03u);
+                    b1.z = __builtin_amdgcn_perm(v.w, v.w, 0x0C020C01u);
+                    b1.w = __builtin_amdgcn_perm(v4, v.w, 0x0C040C03u);
+                    *(uint4 *)(rowA + 32 * k) = a0;
+                    *(uint4 *)(rowA + 32 * k + 16) = a1;
+                    *(uint4 *)(rowB + 32 * k) = b0;
+                    *(uint4 *)(rowB + 32 * k + 16) = b1;
                 }
+            }
+        };
+
+        load_chunk(0);
+        for (int c0 = 0; c0 < nch; c0 += cchunk) {
+            const int cc = min(cchunk, nch - c0);
+            __syncthreads();          // the previous chunk is no longer read
+            store_chunk(c0);
+            if (c0 + cchunk < nch) load_chunk(c0 + cchunk);
+            __syncthreads();          // the chunk is staged
+
+            // lds_tab holds each delay's byte offset from its staged row origin; lane l of
+            // row r starts at lds + r*R + 4*l.  The offsets are read from LDS (one
+            // broadcast read per channel) so that only LDS operations are in flight.
+            const uint8_t *lane_lds = lds + 4 * lane;
+            const int32_t *wtab = lds_tab + wave * DW;
+            int vrow = 0;
+#pragma unroll 2
+            for (int r = 0; r < cc; ++r) {
+                int32_t cd[DW];
+#pragma unroll
+                for (int i = 0; i < DW; ++i) cd[i] = wtab[r * TD + i];
+                uint32_t lv[DW][2 * J];
+#pragma unroll
+                for (int i = 0; i < DW; ++i) {
+                    const uint32_t *p = (const uint32_t *)(lane_lds + (vrow + cd[i]));
+#pragma unroll
+                    for (int g = 0; g < 2 * J; ++g) lv[i][g] = p[64 * g];
+                }
+#pragma unroll
+                for (int i = 0; i < DW; ++i)
+#pragma unroll
+                    for (int g = 0; g < 2 * J; ++g) a16[i][g] += lv[i][g];
+                vrow += R;
+            }
+            // widen every 256 channels (chan_chunk is a power of two <= 256)
+            if (((c0 + cc) & 255) == 0 || c0 + cc >= nch) {
+#pragma unroll
+                for (int i = 0; i < DW; ++i)
+#pragma unroll
+                    for (int g = 0; g < 2 * J; ++g) {
+                        acc[i][2 * g] += (int32_t)(a16[i][g] & 0xFFFFu);
+                        acc[i][2 * g + 1] += (int32_t)(a16[i][g] >> 16);
+                        a16[i][g] = 0u;
+                    }
+            }
         }
 
         // write the DM transform
@@ -243,15 +313,12 @@ __global__ __launch_bounds__(kThreads) void k_dedisp(const DevBeam *__restrict__
             if (d >= ndm) continue;
             int32_t *Xr = B.X + (size_t)d * B.xpitch;
 #pragma unroll
-            for (int j = 0; j < J; ++j) {
-                const int t = t0 + 256 * j + 4 * lane;
-                if (t + 3 < n_dd) {
-                    *(int4 *)(Xr + t) = make_int4(acc[i][4 * j], acc[i][4 * j + 1],
-                                                  acc[i][4 * j + 2], acc[i][4 * j + 3]);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (t + e < n_dd) Xr[t + e] = acc[i][4 * j + e];
+            for (int g = 0; g < 2 * J; ++g) {
+                const int t = t0 + 128 * g + 2 * lane;
+                if (t + 1 < n_dd) {
+                    *(int2 *)(Xr + t) = make_int2(acc[i][2 * g], acc[i][2 * g + 1]);
+                } else if (t < n_dd) {
+                    Xr[t] = acc[i][2 * g];
                 }
             }
         }
@@ -603,62 +670,52 @@ __global__ void k_mu_sigma(const int64_t *n, const int64_t *s1, const int64_t *s
 #define SPL_HIP_LAUNCH_CHECK() \
     do { hipError_t e__ = hipGetLastError(); if (e__ != hipSuccess) return e__; } while (0)
 
-template <int DW, int J>
+template <int DW, int J, int NW>
 static hipError_t prepare_dedisp_t(size_t lds_bytes, int *blocks_per_cu) {
     if (lds_bytes > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_dedisp<DW, J>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_dedisp<DW, J, NW>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
     }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_dedisp<DW, J>, kThreads, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_dedisp<DW, J, NW>, 64 * NW, lds_bytes);
 }
 
-template <int DW, int J>
+template <int DW, int J, int NW>
 static hipError_t launch_dedisp_t(const DevBeam *beams, const DedispItem *items, int item_lo, int item_hi,
                                   int *queue, int grid, size_t lds_bytes, hipStream_t s) {
-    hipLaunchKernelGGL((k_dedisp<DW, J>), dim3(grid), dim3(kThreads), lds_bytes, s, beams, items, item_lo,
+    hipLaunchKernelGGL((k_dedisp<DW, J, NW>), dim3(grid), dim3(64 * NW), lds_bytes, s, beams, items, item_lo,
                        item_hi, queue);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-bool dedisp_shape_supported(int dw, int j) {
-    switch (dw * 16 + j) {
-        case 4 * 16 + 1: case 4 * 16 + 2: case 4 * 16 + 4: case 8 * 16 + 1: case 8 * 16 + 2:
-        case 16 * 16 + 1: case 2 * 16 + 2: case 2 * 16 + 4:
-            return true;
-        default:
-            return false;
-    }
+// The compiled dedispersion shapes (DM trials per wavefront, 256-sample groups per
+// lane, wavefronts per workgroup).
+#define SPL_DEDISP_SHAPES(X) \
+    X(2, 2, 8) X(2, 4, 8) X(4, 1, 4) X(4, 2, 4) X(4, 4, 4) X(4, 1, 8) X(4, 2, 8) \
+    X(8, 1, 4) X(8, 2, 4) X(8, 1, 8) X(16, 1, 4)
+
+bool dedisp_shape_supported(int dw, int j, int nw) {
+#define SPL_X(a, b, c) if (dw == a && j == b && nw == c) return true;
+    SPL_DEDISP_SHAPES(SPL_X)
+#undef SPL_X
+    return false;
 }
 
-hipError_t prepare_dedisp(int dw, int j, size_t lds_bytes, int *blocks_per_cu) {
-    switch (dw * 16 + j) {
-        case 2 * 16 + 2: return prepare_dedisp_t<2, 2>(lds_bytes, blocks_per_cu);
-        case 2 * 16 + 4: return prepare_dedisp_t<2, 4>(lds_bytes, blocks_per_cu);
-        case 4 * 16 + 1: return prepare_dedisp_t<4, 1>(lds_bytes, blocks_per_cu);
-        case 4 * 16 + 2: return prepare_dedisp_t<4, 2>(lds_bytes, blocks_per_cu);
-        case 4 * 16 + 4: return prepare_dedisp_t<4, 4>(lds_bytes, blocks_per_cu);
-        case 8 * 16 + 1: return prepare_dedisp_t<8, 1>(lds_bytes, blocks_per_cu);
-        case 8 * 16 + 2: return prepare_dedisp_t<8, 2>(lds_bytes, blocks_per_cu);
-        case 16 * 16 + 1: return prepare_dedisp_t<16, 1>(lds_bytes, blocks_per_cu);
-        default: return hipErrorInvalidValue;
-    }
+hipError_t prepare_dedisp(int dw, int j, int nw, size_t lds_bytes, int *blocks_per_cu) {
+#define SPL_X(a, b, c) if (dw == a && j == b && nw == c) return prepare_dedisp_t<a, b, c>(lds_bytes, blocks_per_cu);
+    SPL_DEDISP_SHAPES(SPL_X)
+#undef SPL_X
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_dedisp(int dw, int j, const DevBeam *beams, const DedispItem *items, int item_lo,
+hipError_t launch_dedisp(int dw, int j, int nw, const DevBeam *beams, const DedispItem *items, int item_lo,
                          int item_hi, int *queue, int grid, size_t lds_bytes, hipStream_t s) {
-    switch (dw * 16 + j) {
-        case 2 * 16 + 2: return launch_dedisp_t<2, 2>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
-        case 2 * 16 + 4: return launch_dedisp_t<2, 4>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
-        case 4 * 16 + 1: return launch_dedisp_t<4, 1>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
-        case 4 * 16 + 2: return launch_dedisp_t<4, 2>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
-        case 4 * 16 + 4: return launch_dedisp_t<4, 4>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
-        case 8 * 16 + 1: return launch_dedisp_t<8, 1>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
-        case 8 * 16 + 2: return launch_dedisp_t<8, 2>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
-        case 16 * 16 + 1: return launch_dedisp_t<16, 1>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
-        default: return hipErrorInvalidValue;
-    }
+#define SPL_X(a, b, c) \
+    if (dw == a && j == b && nw == c) return launch_dedisp_t<a, b, c>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
+    SPL_DEDISP_SHAPES(SPL_X)
+#undef SPL_X
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {

@@ -18,6 +18,7 @@ if not os.path.exists(LIB_PATH):
                       "(or __graft_entry__.build()) before using the search")
 _lib = ctypes.CDLL(LIB_PATH)
 
+STAGES = ("dedisp", "thresholds", "boxcar", "peaks")
 SPL_OK, SPL_E_INVALID_ARG, SPL_E_HIP, SPL_E_OOM, SPL_E_CAPACITY, SPL_E_UNSUPPORTED, \
     SPL_E_NO_WEIGHTS, SPL_E_INTERNAL = range(8)
 MODE_PLAIN_PER_BEAM, MODE_PERSISTENT_GRAPH = 0, 1
@@ -63,7 +64,7 @@ class _BatchOpts(ctypes.Structure):
 
 class _Tiles(ctypes.Structure):
     _fields_ = [("dm_per_wave", ctypes.c_int32), ("time_groups", ctypes.c_int32),
-                ("chan_chunk", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("chan_chunk", ctypes.c_int32), ("waves", ctypes.c_int32)]
 
 
 STATS_FIELDS = ("n_hits", "n_candidates", "n_after_stencil0", "n_after_stencil1",
@@ -100,6 +101,8 @@ _sig("spl_batch_moments", [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_P)])
 _sig("spl_batch_get_tiles", [_P, _I32, ctypes.POINTER(_Tiles)])
 _sig("spl_batch_set_tiles", [_P, _I32, ctypes.POINTER(_Tiles)])
 _sig("spl_batch_destroy", [_P], None)
+_sig("spl_batch_set_profiling", [_P, _I32])
+_sig("spl_batch_stage_times", [_P, _P, _P, _I32])
 _sig("spl_debug_mu_sigma", [_P, _P, _P, _I64, _P, _P, _P])
 
 
@@ -196,10 +199,11 @@ class Batch:
     def tiles(self, beam=0) -> dict:
         t = _Tiles()
         _check(_lib.spl_batch_get_tiles(self._h, beam, ctypes.byref(t)))
-        return {"dm_per_wave": t.dm_per_wave, "time_groups": t.time_groups, "chan_chunk": t.chan_chunk}
+        return {"dm_per_wave": t.dm_per_wave, "time_groups": t.time_groups, "chan_chunk": t.chan_chunk,
+                "waves": t.waves}
 
-    def set_tiles(self, beam, dm_per_wave, time_groups, chan_chunk=0):
-        t = _Tiles(int(dm_per_wave), int(time_groups), int(chan_chunk), 0)
+    def set_tiles(self, beam, dm_per_wave, time_groups, chan_chunk=0, waves=4):
+        t = _Tiles(int(dm_per_wave), int(time_groups), int(chan_chunk), int(waves))
         _check(_lib.spl_batch_set_tiles(self._h, beam, ctypes.byref(t)))
         if self.ws is not None:
             self.attach()
@@ -244,6 +248,16 @@ class Batch:
             _check(_lib.spl_batch_run(self._h, ptrs, pitches, cptr, cap, ctypes.c_void_p(stats.data_ptr()),
                                       _stream_handle(stream)))
         return cands, stats
+
+    def set_profiling(self, enable=True):
+        _check(_lib.spl_batch_set_profiling(self._h, 1 if enable else 0))
+
+    def stage_times(self, reset=True) -> dict:
+        """Summed HIP-event times (ms) and counts of the profiled stages since the last reset."""
+        ms = np.zeros(len(STAGES), np.float64)
+        cnt = np.zeros(len(STAGES), np.int64)
+        _check(_lib.spl_batch_stage_times(self._h, ms.ctypes.data, cnt.ctypes.data, 1 if reset else 0))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(STAGES)}
 
     def _view(self, ptr, nbytes, dtype):
         off = ptr - self.ws.data_ptr()

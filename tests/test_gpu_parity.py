@@ -193,10 +193,12 @@ def test_tile_shapes_give_identical_results(spl):
     x = rng.integers(0, 256, size=(512, p.info["n_in"]), dtype=np.uint8)
     ref, rc = oracle_run([p], [x])
     batch = spl.Batch([p])
-    for dw, j in ((2, 2), (2, 4), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2), (16, 1)):
-        for cc in (0, 4, 100, 256):
+    shapes = ((2, 2, 8), (2, 4, 8), (4, 1, 4), (4, 2, 4), (4, 4, 4), (4, 1, 8), (4, 2, 8), (8, 1, 4),
+              (8, 2, 4), (8, 1, 8), (16, 1, 4))
+    for dw, j, nw in shapes:
+        for cc in (0, 1, 4, 32):
             try:
-                batch.set_tiles(0, dw, j, cc)
+                batch.set_tiles(0, dw, j, cc, waves=nw)
             except spl.SplError:
                 continue
             say("tiles", dw, j, cc, batch.tiles(0))
