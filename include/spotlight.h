@@ -261,6 +261,46 @@ spl_status spl_batch_stage_times(spl_batch *batch, double *ms, int64_t *count, i
 
 void spl_batch_destroy(spl_batch *batch);
 
+/* ------------------------------------------------- plain optimisation path */
+/* Parameters of the candidate-optimisation stage (candidate optimisation section):
+ * DBSCAN with radius eps and min_pts points (a point counts itself) on the plane
+ * (t_sample*tsamp/t_scale_s, dm/dm_scale); thresholds S/N >= snr_min, DM >= dm_min,
+ * width*tsamp <= width_max_s; with at least coinc_min_beams beams, a candidate is
+ * dropped when more than coinc_frac of the beams hold a thresholded candidate within
+ * coinc_dt_s of its arrival time. */
+typedef struct spl_opt_params {
+    double eps;
+    int32_t min_pts;
+    int32_t coinc_min_beams;
+    double t_scale_s;
+    double dm_scale;
+    double snr_min;
+    double dm_min;
+    double width_max_s;
+    double coinc_dt_s;
+    double coinc_frac;
+} spl_opt_params;
+
+/* eps 0.5, min_pts 5, 50 ms and 20 pc cm^-3 units, S/N 10, DM 10, width 100 ms,
+ * anti-coincidence over >= 3 beams within 50 ms in more than half of them. */
+void spl_opt_defaults(spl_opt_params *params);
+
+/*
+ * Host-side plain path applied to host candidate records (any order; beam in
+ * [0, n_beams)); tsamp_of_beam[b] is beam b's sampling interval.  Per beam the
+ * records are taken in (dm_index, t_sample) order; DBSCAN clusters are the connected
+ * components of core points, numbered by their lowest-index core point; a border
+ * point joins the lowest-numbered cluster among its core neighbours; noise is
+ * dropped and each cluster keeps its highest-S/N member (equal S/N: the earlier
+ * one).  Survivors of the thresholds and the anti-coincidence filter are written to
+ * `out` sorted by (beam, dm_index, t_sample); *n_out receives their number;
+ * SPL_E_CAPACITY if it exceeds `capacity` (the first `capacity` are written).
+ * params NULL selects the defaults.
+ */
+spl_status spl_optimise_plain(const spl_candidate *cands, int64_t n, const double *tsamp_of_beam,
+                              int32_t n_beams, const spl_opt_params *params, spl_candidate *out,
+                              int64_t capacity, int64_t *n_out);
+
 /* ------------------------------------------------------------- test hooks */
 /* The normaliser of the search on device, for parity tests: for i < count,
  * mu[i] = S1/n and sigma[i] = sqrt(n*S2 - S1^2)/n (exact 128-bit difference,

@@ -1,0 +1,166 @@
+"""Float64 reference of the candidate ranker (test infrastructure only).
+
+A small CNN stands in for the paper's FETCH classifier (classification section):
+its input is the two 64x256 feature planes of a candidate (DM-time and
+frequency-time), and it outputs one logit; a probability >= 0.5 keeps the
+candidate.  Layers, in order:
+  4 x [3x3 convolution, stride 1, zero padding 1, bias -> ReLU -> 2x2 max pool]
+      with channels 2 -> 32 -> 32 -> 32 -> 32   (64x256 -> 4x16)
+  flatten (channel, row, column) -> 2048
+  fully connected 2048 -> 64, bias -> ReLU -> fully connected 64 -> 1, bias
+Loss: binary cross-entropy on the logit, averaged over the batch.
+Max-pool ties go to the first element of the window in row-major order.
+Parameters are a dict of float64 arrays:
+  c{k}w [32][Cin][3][3], c{k}b [32] (k = 1..4), f1w [64][2048], f1b [64],
+  f2w [1][64], f2b [1].
+Plain numpy: convolution as a sum of 9 shifted products, no fusion or blocking.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CONV_CHANNELS = (2, 32, 32, 32, 32)
+IN_H, IN_W = 64, 256
+FC_IN, FC_HIDDEN = 2048, 64
+PARAM_ORDER = ("c1w", "c1b", "c2w", "c2b", "c3w", "c3b", "c4w", "c4b", "f1w", "f1b", "f2w", "f2b")
+
+
+def param_shapes() -> dict:
+    s = {}
+    for k in range(4):
+        cin, cout = CONV_CHANNELS[k], CONV_CHANNELS[k + 1]
+        s[f"c{k + 1}w"] = (cout, cin, 3, 3)
+        s[f"c{k + 1}b"] = (cout,)
+    s["f1w"] = (FC_HIDDEN, FC_IN)
+    s["f1b"] = (FC_HIDDEN,)
+    s["f2w"] = (1, FC_HIDDEN)
+    s["f2b"] = (1,)
+    return s
+
+
+def init_params(seed: int = 0) -> dict:
+    """He-uniform weights, zero biases (float64)."""
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, shp in param_shapes().items():
+        if name.endswith("b"):
+            p[name] = np.zeros(shp)
+        else:
+            fan_in = int(np.prod(shp[1:]))
+            lim = np.sqrt(6.0 / fan_in)
+            p[name] = rng.uniform(-lim, lim, size=shp)
+    return p
+
+
+def flatten_params(p: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(p[k], np.float64).ravel() for k in PARAM_ORDER])
+
+
+def unflatten_params(v: np.ndarray) -> dict:
+    out, o = {}, 0
+    for k in PARAM_ORDER:
+        shp = param_shapes()[k]
+        n = int(np.prod(shp))
+        out[k] = np.asarray(v[o:o + n], np.float64).reshape(shp)
+        o += n
+    return out
+
+
+def n_params() -> int:
+    return sum(int(np.prod(s)) for s in param_shapes().values())
+
+
+def conv3x3(x, w, b):
+    n, c, h, wd = x.shape
+    xp = np.pad(x, ((0, 0), (0, 0), (1, 1), (1, 1)))
+    out = np.zeros((n, w.shape[0], h, wd))
+    for ky in range(3):
+        for kx in range(3):
+            out += np.einsum("nchw,oc->nohw", xp[:, :, ky:ky + h, kx:kx + wd], w[:, :, ky, kx])
+    return out + b[None, :, None, None]
+
+
+def conv3x3_backward(x, w, gout):
+    """Gradients of conv3x3 with respect to input, weight and bias."""
+    n, c, h, wd = x.shape
+    xp = np.pad(x, ((0, 0), (0, 0), (1, 1), (1, 1)))
+    gxp = np.zeros_like(xp)
+    gw = np.zeros_like(w)
+    for ky in range(3):
+        for kx in range(3):
+            gw[:, :, ky, kx] = np.einsum("nohw,nchw->oc", gout, xp[:, :, ky:ky + h, kx:kx + wd])
+            gxp[:, :, ky:ky + h, kx:kx + wd] += np.einsum("nohw,oc->nchw", gout, w[:, :, ky, kx])
+    return gxp[:, :, 1:-1, 1:-1], gw, gout.sum(axis=(0, 2, 3))
+
+
+def maxpool2(x):
+    """2x2 max pool and the window position (0..3, row-major) of each maximum."""
+    n, c, h, w = x.shape
+    win = x.reshape(n, c, h // 2, 2, w // 2, 2).transpose(0, 1, 2, 4, 3, 5).reshape(n, c, h // 2, w // 2, 4)
+    arg = np.argmax(win, axis=-1)          # first maximum on ties
+    return np.take_along_axis(win, arg[..., None], axis=-1)[..., 0], arg
+
+
+def maxpool2_backward(gout, arg, shape):
+    n, c, h, w = shape
+    g = np.zeros((n, c, h // 2, w // 2, 4))
+    np.put_along_axis(g, arg[..., None], gout[..., None], axis=-1)
+    return g.reshape(n, c, h // 2, w // 2, 2, 2).transpose(0, 1, 2, 4, 3, 5).reshape(n, c, h, w)
+
+
+def forward(p: dict, x: np.ndarray):
+    """x [N][2][64][256] -> logits [N] and the saved activations."""
+    cache = {"x0": np.asarray(x, np.float64)}
+    a = cache["x0"]
+    for k in range(1, 5):
+        z = conv3x3(a, p[f"c{k}w"], p[f"c{k}b"])
+        r = np.maximum(z, 0.0)
+        a, arg = maxpool2(r)
+        cache[f"z{k}"], cache[f"arg{k}"], cache[f"x{k}"] = z, arg, a
+    f = a.reshape(a.shape[0], -1)
+    h = f @ p["f1w"].T + p["f1b"]
+    hr = np.maximum(h, 0.0)
+    logit = (hr @ p["f2w"].T + p["f2b"])[:, 0]
+    cache.update(f=f, h=h, hr=hr)
+    return logit, cache
+
+
+def bce_with_logits(logit, y):
+    """Mean of max(z, 0) - z*y + log(1 + exp(-|z|))."""
+    z = np.asarray(logit, np.float64)
+    return float(np.mean(np.maximum(z, 0.0) - z * y + np.log1p(np.exp(-np.abs(z)))))
+
+
+def backward(p: dict, cache: dict, y: np.ndarray) -> tuple[float, dict]:
+    """Loss and gradients of the mean BCE loss with respect to every parameter."""
+    x0 = cache["x0"]
+    n = x0.shape[0]
+    hr, h, f = cache["hr"], cache["h"], cache["f"]
+    logit = (hr @ p["f2w"].T + p["f2b"])[:, 0]
+    loss = bce_with_logits(logit, y)
+    g = {}
+    gz = (1.0 / (1.0 + np.exp(-logit)) - y) / n          # d loss / d logit
+    g["f2w"] = gz[None, :] @ hr
+    g["f2b"] = np.array([gz.sum()])
+    ghr = gz[:, None] * p["f2w"]
+    gh = ghr * (h > 0)
+    g["f1w"] = gh.T @ f
+    g["f1b"] = gh.sum(axis=0)
+    gf = gh @ p["f1w"]
+    ga = gf.reshape(cache["x4"].shape)
+    for k in range(4, 0, -1):
+        z = cache[f"z{k}"]
+        gr = maxpool2_backward(ga, cache[f"arg{k}"], z.shape)
+        gzk = gr * (z > 0)
+        xin = cache[f"x{k - 1}"]
+        ga, g[f"c{k}w"], g[f"c{k}b"] = conv3x3_backward(xin, p[f"c{k}w"], gzk)
+    return loss, g
+
+
+def flops_forward_per_sample() -> int:
+    """Multiply-adds x 2 of one forward pass (convolutions and fully connected layers)."""
+    tot, h, w = 0, IN_H, IN_W
+    for k in range(4):
+        tot += 2 * 9 * CONV_CHANNELS[k] * CONV_CHANNELS[k + 1] * h * w
+        h, w = h // 2, w // 2
+    return tot + 2 * FC_IN * FC_HIDDEN + 2 * FC_HIDDEN

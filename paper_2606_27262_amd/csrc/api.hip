@@ -40,6 +40,8 @@ static spl_status fail(spl_status st, const char *fmt, ...) {
                         __FILE__, __LINE__);                                                  \
     } while (0)
 
+spl_status spl_internal_fail(spl_status st, const char *msg) { return fail(st, "%s", msg); }
+
 extern "C" const char *spl_last_error(void) { return g_err.c_str(); }
 extern "C" int32_t spl_version(void) { return 100; }
 

@@ -67,6 +67,13 @@ class _Tiles(ctypes.Structure):
                 ("chan_chunk", ctypes.c_int32), ("waves", ctypes.c_int32)]
 
 
+class _OptParams(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("min_pts", ctypes.c_int32), ("coinc_min_beams", ctypes.c_int32),
+                ("t_scale_s", ctypes.c_double), ("dm_scale", ctypes.c_double), ("snr_min", ctypes.c_double),
+                ("dm_min", ctypes.c_double), ("width_max_s", ctypes.c_double), ("coinc_dt_s", ctypes.c_double),
+                ("coinc_frac", ctypes.c_double)]
+
+
 STATS_FIELDS = ("n_hits", "n_candidates", "n_after_stencil0", "n_after_stencil1",
                 "n_after_stencil2", "n_after_stencil3", "overflow")
 STATS_WORDS = 7   # int64 words of spl_run_stats
@@ -104,6 +111,8 @@ _sig("spl_batch_destroy", [_P], None)
 _sig("spl_batch_set_profiling", [_P, _I32])
 _sig("spl_batch_stage_times", [_P, _P, _P, _I32])
 _sig("spl_debug_mu_sigma", [_P, _P, _P, _I64, _P, _P, _P])
+_sig("spl_opt_defaults", [ctypes.POINTER(_OptParams)], None)
+_sig("spl_optimise_plain", [_P, _I64, _P, _I32, ctypes.POINTER(_OptParams), _P, _I64, ctypes.POINTER(_I64)])
 
 
 def _check(st):
@@ -309,6 +318,26 @@ def stats_dict(stats) -> dict:
     return {"n_hits": int(s[0]), "n_candidates": int(s[1]),
             "n_after_stencil": [int(v) for v in s[2:6]],
             "hit_overflow": ov & 0xFFFFFFFF, "cand_overflow": (ov >> 32) & 0xFFFFFFFF}
+
+
+def opt_params(**kw) -> _OptParams:
+    p = _OptParams()
+    _lib.spl_opt_defaults(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def optimise_plain(cands: np.ndarray, tsamp_of_beam, n_beams: int, **kw) -> np.ndarray:
+    """Plain candidate-optimisation path on host records (numpy CAND_DTYPE)."""
+    c = np.ascontiguousarray(cands, dtype=CAND_DTYPE)
+    ts = np.ascontiguousarray(tsamp_of_beam, np.float64)
+    out = np.zeros(max(1, c.size), CAND_DTYPE)
+    n_out = _I64()
+    p = opt_params(**kw)
+    _check(_lib.spl_optimise_plain(c.ctypes.data if c.size else None, c.size, ts.ctypes.data, int(n_beams),
+                                   ctypes.byref(p), out.ctypes.data, out.size, ctypes.byref(n_out)))
+    return out[:n_out.value].copy()
 
 
 def debug_mu_sigma(n, s1, s2, stream=None):

@@ -98,3 +98,55 @@ def test_batch_layout_host_only():
     assert t["chan_chunk"] >= 4 and t["dm_per_wave"] in (2, 4, 8, 16)
     with pytest.raises(spl.SplError):
         b.set_tiles(0, 3, 1)
+
+
+def _rand_cands(rng, n_beams, per_beam, clustered=True):
+    parts = []
+    for b in range(n_beams):
+        n = int(rng.integers(0, per_beam))
+        c = np.zeros(n, oracle.CAND_DTYPE)
+        c["beam"] = b
+        if clustered and n:
+            centres = rng.integers(0, 2000, size=(4, 2))
+            k = rng.integers(0, 4, n)
+            c["dm_index"] = np.clip(centres[k, 0] + rng.integers(-15, 16, n), 0, 2047)
+            c["t_sample"] = np.clip(centres[k, 1] * 8 + rng.integers(-30, 31, n), 0, 16383)
+        else:
+            c["dm_index"] = rng.integers(0, 2048, n)
+            c["t_sample"] = rng.integers(0, 16384, n)
+        c["width"] = rng.choice([1, 2, 4, 8, 16, 32, 64, 128], n)
+        c["snr"] = rng.uniform(6, 30, n).astype(np.float32).round(1)
+        c["dm"] = (c["dm_index"] * 0.9765625).astype(np.float32)
+        parts.append(c)
+    c = np.concatenate(parts) if parts else np.zeros(0, oracle.CAND_DTYPE)
+    # unique (beam, d, t), sorted like the search output
+    _, u = np.unique(c[["beam", "dm_index", "t_sample"]], return_index=True)
+    c = c[np.sort(u)]
+    return c[np.lexsort((c["t_sample"], c["dm_index"], c["beam"]))]
+
+
+@pytest.mark.parametrize("n_beams", [1, 2, 5, 24])
+def test_plain_path_library_equals_oracle(n_beams):
+    rng = np.random.default_rng(100 + n_beams)
+    for trial in range(6):
+        c = _rand_cands(rng, n_beams, 400, clustered=trial % 2 == 0)
+        ts = np.full(n_beams, 1.31072e-3)
+        ts[::2] = 0.65536e-3
+        ref = oracle.plain_optimise(c, ts, n_beams)
+        got = spl.optimise_plain(c, ts, n_beams)
+        assert np.array_equal(got, ref), (trial, got.size, ref.size)
+    # a coincident burst in every beam is removed
+    if n_beams >= 3:
+        parts = [c]
+        for b in range(n_beams):
+            for k in range(6):
+                x = np.zeros(1, oracle.CAND_DTYPE)
+                x["beam"], x["dm_index"], x["t_sample"], x["width"] = b, 300 + k, 9000 + k, 4
+                x["snr"], x["dm"] = 25.0 + k, 300.0 + k
+                parts.append(x)
+        c2 = np.concatenate(parts)
+        ts = np.full(n_beams, 1.31072e-3)   # same arrival time in seconds in every beam
+        ref = oracle.plain_optimise(c2, ts, n_beams)
+        got = spl.optimise_plain(c2, ts, n_beams)
+        assert np.array_equal(got, ref)
+        assert not np.any((got["t_sample"] >= 9000) & (got["t_sample"] < 9006))

@@ -1,0 +1,74 @@
+"""Pins of the float64 ranker oracle: torch's float64 convolution, pooling, linear
+layers, loss and autograd (library routines), and central finite differences."""
+import numpy as np
+import pytest
+
+from oracle import cnn
+
+torch = pytest.importorskip("torch")
+F = torch.nn.functional
+
+
+def _torch_forward(p, x):
+    t = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in p.items()}
+    a = torch.tensor(x, dtype=torch.float64)
+    for k in range(1, 5):
+        a = F.max_pool2d(F.relu(F.conv2d(a, t[f"c{k}w"], t[f"c{k}b"], padding=1)), 2)
+    h = F.relu(F.linear(a.reshape(a.shape[0], -1), t["f1w"], t["f1b"]))
+    return F.linear(h, t["f2w"], t["f2b"])[:, 0], t
+
+
+def test_param_count_and_flops():
+    assert cnn.n_params() == (2 * 32 * 9 + 32) + 3 * (32 * 32 * 9 + 32) + (2048 * 64 + 64) + (64 + 1)
+    # about 118 MFLOP per forward pass
+    assert 1.15e8 < cnn.flops_forward_per_sample() < 1.21e8
+
+
+def test_forward_and_backward_match_torch_float64():
+    rng = np.random.default_rng(0)
+    p = cnn.init_params(1)
+    for k in p:
+        if k.endswith("b"):
+            p[k] = rng.normal(0, 0.1, p[k].shape)
+    x = rng.normal(0, 1, size=(3, 2, 64, 256))
+    y = np.array([1.0, 0.0, 1.0])
+    logit, cache = cnn.forward(p, x)
+    tl, tp = _torch_forward(p, x)
+    assert np.allclose(logit, tl.detach().numpy(), rtol=1e-12, atol=1e-12)
+    loss, g = cnn.backward(p, cache, y)
+    tloss = F.binary_cross_entropy_with_logits(tl, torch.tensor(y))
+    assert abs(loss - tloss.item()) < 1e-12
+    tloss.backward()
+    for k in p:
+        ref = tp[k].grad.numpy()
+        assert np.allclose(g[k], ref, rtol=1e-9, atol=1e-13), k
+
+
+def test_central_finite_differences():
+    rng = np.random.default_rng(2)
+    p = cnn.init_params(3)
+    x = rng.normal(0, 1, size=(1, 2, 64, 256))
+    y = np.array([1.0])
+    logit, cache = cnn.forward(p, x)
+    _, g = cnn.backward(p, cache, y)
+    eps = 1e-7   # small enough that no ReLU or pooling kink is crossed
+    for name in cnn.PARAM_ORDER:
+        flat = p[name].ravel()
+        for idx in rng.choice(flat.size, size=min(2, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + eps
+            lp = cnn.bce_with_logits(cnn.forward(p, x)[0], y)
+            flat[idx] = old - eps
+            lm = cnn.bce_with_logits(cnn.forward(p, x)[0], y)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * eps)
+            an = g[name].ravel()[idx]
+            assert abs(fd - an) <= 1e-6 * max(1e-2, abs(an)), (name, idx, fd, an)
+
+
+def test_maxpool_tie_goes_to_first():
+    x = np.zeros((1, 1, 2, 2))
+    out, arg = cnn.maxpool2(x)
+    assert arg[0, 0, 0, 0] == 0
+    g = cnn.maxpool2_backward(np.ones((1, 1, 1, 1)), arg, x.shape)
+    assert g[0, 0, 0, 0] == 1 and g.sum() == 1
