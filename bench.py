@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--mode", default="auto", choices=["auto", "plain", "graph"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default dedispersion tiles")
+    ap.add_argument("--tile-cache", default=None, help="autotuner cache file (default: a file in $TMPDIR)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -131,6 +133,12 @@ def main():
         mode = "plain" if nb == 1 else "graph"
     batch = spl.Batch(plans, mode=spl.MODE_PERSISTENT_GRAPH if mode == "graph" else spl.MODE_PLAIN_PER_BEAM)
     batch.attach()
+    if not args.no_autotune:
+        import tempfile
+        cache = args.tile_cache or os.path.join(tempfile.gettempdir(), "spotlight_tiles.txt")
+        t_tune = time.perf_counter()
+        batch.autotune(blocks, cache_path=cache)
+        log(f"autotune {time.perf_counter() - t_tune:.1f}s -> {batch.tiles(0)}")
     cands = spl.new_candidates(1 << 20)
     stats = torch.zeros(spl.STATS_WORDS, dtype=torch.int64, device="cuda")
     stream = torch.cuda.Stream()
@@ -188,7 +196,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "beams": nb, "mode": mode,
+        "config": {"workload": args.workload, "beams": nb, "mode": mode, "autotuned": not args.no_autotune,
                    "plans": sorted(set(W.describe(pd) for pd in pds)),
                    "tiles": [batch.tiles(b) for b in sorted(set(range(nb)) & {0, nb - 1})]},
         "real_time_factor": rtf,

@@ -232,7 +232,8 @@ spl_status spl_batch_moments(const spl_batch *batch, int32_t beam, const int64_t
 
 /* Dedispersion tiling of one beam: a workgroup of `waves` wavefronts sums a tile of
  * waves*dm_per_wave DM trials by time_groups*256 samples; chan_chunk channels are staged
- * in LDS per step (a power of two <= 4*waves; 0: the largest that fits a 64 KiB budget). */
+ * in LDS per step (a power of two in [2, 2*waves]; 0: the largest that fits a 64 KiB
+ * budget). */
 typedef struct spl_tiles {
     int32_t dm_per_wave;
     int32_t time_groups;
@@ -258,6 +259,20 @@ spl_status spl_batch_set_tiles(spl_batch *batch, int32_t beam, const spl_tiles *
 #define SPL_N_STAGES 4
 spl_status spl_batch_set_profiling(spl_batch *batch, int32_t enable);
 spl_status spl_batch_stage_times(spl_batch *batch, double *ms, int64_t *count, int32_t reset);
+
+/*
+ * Autotuner: for every distinct plan of the batch, time the dedispersion kernel on the
+ * given blocks (uint8 [nch][pitch] device blocks as for spl_batch_run) for every compiled
+ * tile shape and staging depth that fits, check that each shape gives a bit-identical DM
+ * transform (SPL_E_INTERNAL otherwise), and keep the fastest.  Results are cached in the
+ * text file cache_path (NULL: no cache), one line per plan signature (sizes and a hash of
+ * the delay table); a cached plan is not re-timed unless flags has SPL_TUNE_FORCE.
+ * Synchronous on `stream`; overwrites the batch's intermediate results and uses only the
+ * attached workspace (which is sized for every tiling).
+ */
+#define SPL_TUNE_FORCE 1
+spl_status spl_autotune(spl_batch *batch, const uint8_t *const *d_blocks, const int64_t *pitches,
+                        const char *cache_path, int32_t flags, hipStream_t stream);
 
 void spl_batch_destroy(spl_batch *batch);
 

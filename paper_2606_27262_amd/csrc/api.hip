@@ -224,6 +224,7 @@ namespace {
 
 struct Tiles {
     int dw = 4, j = 2, nw = 8, cc = 0;
+    int sv = 1;   // staged 16-byte vectors per lane and row, from the widest row of the plan
 };
 
 // Everything that depends on one plan and its tiling.
@@ -233,7 +234,7 @@ struct PlanLayout {
     int td = 0, ndm_pad = 0, ntile_d = 0, ntile_t = 0;
     std::vector<int32_t> dcm;        // delays [nch][ndm_pad]
     std::vector<int32_t> dtab;       // LDS byte offsets [nch][ndm_pad]
-    int half = 0;                    // byte offset of the odd-aligned copy
+    int quarter = 0;                 // bytes per shifted copy of the staged rows
     std::vector<int32_t> tile_base;  // [ntile_d][nch]
     std::vector<int32_t> row_bytes;  // [ntile_d]
     size_t off_dcm = 0, off_base = 0, off_dms = 0;
@@ -260,11 +261,11 @@ struct spl_batch {
     int max_nst = 0, w_max = 0;
     std::vector<DedispItem> items;
     // shape groups for the persistent launch
-    struct Group { int dw, j, nw; int item_lo, item_hi; size_t lds; int occ; };
+    struct Group { int dw, j, nw, sv; int item_lo, item_hi; size_t lds; int occ; };
     std::vector<Group> groups;
     std::vector<size_t> beam_lds;          // per beam (plain per-beam launches)
     // workspace
-    size_t ws_bytes = 0;
+    size_t ws_bytes = 0, ws_given = 0;
     char *ws = nullptr;
     size_t off_beams = 0, off_items = 0;
     std::vector<size_t> off_X, off_S, off_mu, off_sigma, off_T;   // per beam
@@ -296,7 +297,7 @@ struct spl_batch {
 
 static spl_status layout_plan(PlanLayout &L) {
     const spl_plan &p = *L.plan;
-    if (!dedisp_shape_supported(L.tiles.dw, L.tiles.j, L.tiles.nw))
+    if (!dedisp_shape_supported(L.tiles.dw, L.tiles.j, L.tiles.nw, 1))
         return fail(SPL_E_UNSUPPORTED, "dedispersion tile shape (%d, %d, %d) is not compiled in", L.tiles.dw,
                     L.tiles.j, L.tiles.nw);
     if (L.tiles.cc < 0 || L.tiles.cc > kDedispStageRows * L.tiles.nw)
@@ -327,13 +328,15 @@ static spl_status layout_plan(PlanLayout &L) {
             L.tile_base[(size_t)k * p.nch + c] = lo;
             span = std::max(span, hi - lo);
         }
-        // one copy of a staged row: 16-bit samples covering the tile's time span,
-        // its spread of delays and 16-sample alignment slack
-        L.row_bytes[k] = 2 * (TT + 32 + (int)align_up((size_t)span, 16));
-        if (L.row_bytes[k] / 32 > kDedispMaxRowVecs)
-            return fail(SPL_E_UNSUPPORTED, "DM tile %d spans %d samples of delay: too wide for the staged rows of "
-                        "this tile shape (use fewer trials per tile)", k, span);
+        // one copy of a staged row: 8-bit samples covering the tile's time span, its
+        // spread of delays and 16-sample alignment slack
+        L.row_bytes[k] = TT + 32 + (int)align_up((size_t)span, 16);
     }
+    const int rmax = *std::max_element(L.row_bytes.begin(), L.row_bytes.end());
+    L.tiles.sv = rmax <= 1024 ? 1 : 2;
+    if (rmax > 2048 || !dedisp_shape_supported(L.tiles.dw, L.tiles.j, L.tiles.nw, L.tiles.sv))
+        return fail(SPL_E_UNSUPPORTED, "a DM tile spans %d bytes of staged row: too wide for this tile shape "
+                    "(use fewer trials per tile)", rmax);
     return SPL_OK;
 }
 
@@ -354,11 +357,11 @@ static bool tile_fits(const spl_plan &p, int td, int j) {
         const int d1 = std::min(p.ndm, d0 + td) - 1;
         worst = std::max(worst, std::abs(p.delays[(size_t)d1 * p.nch + c] - p.delays[(size_t)d0 * p.nch + c]));
     }
-    return 2 * (256 * j + 32 + (int)align_up((size_t)worst + 64, 16)) / 32 <= kDedispMaxRowVecs;
+    return 256 * j + 32 + (int)align_up((size_t)worst + 64, 16) <= 2048;
 }
 
 static Tiles default_tiles(const spl_plan &p) {
-    static const int shapes[][3] = {{4, 2, 8}, {4, 1, 8}, {2, 2, 8}, {4, 1, 4}};
+    static const int shapes[][3] = {{4, 2, 8}, {4, 1, 8}, {2, 2, 8}, {4, 1, 4}};   // (trials/wave, groups, waves)
     for (const auto &sh : shapes) {
         Tiles t;
         t.dw = sh[0];
@@ -385,12 +388,12 @@ static void choose_chunk(PlanLayout &L, size_t lds_budget) {
     int cc = L.tiles.cc;
     if (cc <= 0) {
         cc = kDedispStageRows * L.tiles.nw;
-        while (cc > 1 && (size_t)2 * cc * rmax > lds_budget) cc >>= 1;
+        while (cc > 2 && (size_t)4 * (cc + 1) * rmax + (size_t)(cc + 4) * 4 * L.td > lds_budget) cc >>= 1;
     }
-    int p2 = 1;
+    int p2 = 2;   // at least 2: an odd last chunk is padded with a zero row
     while (p2 * 2 <= std::min(cc, 256)) p2 *= 2;
     L.tiles.cc = p2;
-    L.half = p2 * rmax;
+    L.quarter = (p2 + 1) * rmax;   // chan_chunk rows + the zero row
     const spl_plan &p = *L.plan;
     L.dtab.assign(L.dcm.size(), 0);
     for (int c = 0; c < p.nch; ++c) {
@@ -399,7 +402,7 @@ static void choose_chunk(PlanLayout &L, size_t lds_budget) {
             const int sv = L.dcm[k];
             // the row of channel c in DM tile d/td starts at sample t0 + (base & ~15)
             const int b16 = L.tile_base[(size_t)(d / L.td) * p.nch + c] & ~15;
-            L.dtab[k] = 4 * (sv >> 1) + (sv & 1) * L.half - 2 * b16;
+            L.dtab[k] = ((sv - b16) & ~3) + (sv & 3) * L.quarter;
         }
     }
     (void)p;
@@ -426,11 +429,13 @@ static spl_status build_layout(spl_batch *B) {
         const Tiles &t = B->layouts[B->layout_of_beam[b]].tiles;
         int g = -1;
         for (size_t k = 0; k < B->groups.size(); ++k)
-            if (B->groups[k].dw == t.dw && B->groups[k].j == t.j && B->groups[k].nw == t.nw) g = (int)k;
+            if (B->groups[k].dw == t.dw && B->groups[k].j == t.j && B->groups[k].nw == t.nw &&
+                B->groups[k].sv == t.sv)
+                g = (int)k;
         if (g < 0) {
             if ((int)B->groups.size() >= kMaxShapeGroups)
                 return fail(SPL_E_UNSUPPORTED, "at most %d distinct tile shapes per batch", kMaxShapeGroups);
-            B->groups.push_back({t.dw, t.j, t.nw, 0, 0, 0, 0});
+            B->groups.push_back({t.dw, t.j, t.nw, t.sv, 0, 0, 0, 0});
         }
     }
     std::vector<std::vector<DedispItem>> per_beam(nb);
@@ -441,7 +446,7 @@ static spl_status build_layout(spl_batch *B) {
         for (int tt = 0; tt < L.ntile_t; ++tt)
             for (int k = 0; k < L.ntile_d; ++k)
                 per_beam[b].push_back({b, k * L.td, tt * TT, L.row_bytes[k]});
-        B->beam_lds[b] = (size_t)2 * L.half + (size_t)L.tiles.cc * L.td * sizeof(int32_t);
+        B->beam_lds[b] = (size_t)4 * L.quarter + (size_t)(kDedispStageRows * L.tiles.nw + 4) * L.td * sizeof(int32_t);
         B->max_nst = std::max(B->max_nst, p.nst);
         B->w_max = std::max(B->w_max, p.w_max);
     }
@@ -459,7 +464,7 @@ static spl_status build_layout(spl_batch *B) {
         size_t lds = 0;
         for (int b = 0; b < nb; ++b) {
             const Tiles &t = B->layouts[B->layout_of_beam[b]].tiles;
-            if (t.dw != g.dw || t.j != g.j || t.nw != g.nw) continue;
+            if (t.dw != g.dw || t.j != g.j || t.nw != g.nw || t.sv != g.sv) continue;
             B->item_base[b] = (int)B->items.size();
             B->items.insert(B->items.end(), per_beam[b].begin(), per_beam[b].end());
             lds = std::max(lds, B->beam_lds[b]);
@@ -479,12 +484,20 @@ static spl_status build_layout(spl_batch *B) {
         off += bytes;
         return o;
     };
+    // plan tables and work items are reserved for the smallest compiled tile (16 trials x
+    // 256 samples) and the widest padding (64 trials), so that retiling (spl_batch_set_tiles,
+    // spl_autotune) never needs a larger workspace
+    size_t res_items = 0;
+    for (int b = 0; b < nb; ++b) {
+        const spl_plan &p = *B->plans[b];
+        res_items += (size_t)((p.ndm + 15) / 16) * ((p.n_dd + 255) / 256);
+    }
     B->off_beams = take(sizeof(DevBeam) * nb);
-    B->off_items = take(sizeof(DedispItem) * std::max(1, B->n_items));
+    B->off_items = take(sizeof(DedispItem) * std::max<size_t>(1, res_items));
     for (auto &L : B->layouts) {
         const spl_plan &p = *L.plan;
-        L.off_dcm = take(L.dtab.size() * sizeof(int32_t));
-        L.off_base = take(L.tile_base.size() * sizeof(int32_t));
+        L.off_dcm = take((size_t)p.nch * ((p.ndm + 63) / 64 * 64) * sizeof(int32_t));
+        L.off_base = take((size_t)((p.ndm + 15) / 16) * p.nch * sizeof(int32_t));
         L.off_dms = take((size_t)p.ndm * sizeof(double));
     }
     B->off_X.assign(nb, 0);
@@ -620,7 +633,7 @@ static void fill_host_beams(spl_batch *B) {
         d.chunk_base = B->chunk_base[b];
         d.nchunk_t = (p.n_out + kBoxTile - 1) / kBoxTile;
         d.chan_chunk = L.tiles.cc;
-        d.lds_half = L.half;
+        d.lds_quarter = L.quarter;
         d.tile_dm = L.td;
         d.beam = b;
         d.w_max = p.w_max;
@@ -633,19 +646,12 @@ static void fill_host_beams(spl_batch *B) {
     }
 }
 
-extern "C" spl_status spl_batch_set_workspace(spl_batch *B, void *d_ws, size_t bytes) {
-    if (!B || !d_ws) return fail(SPL_E_INVALID_ARG, "NULL argument");
-    if (bytes < B->ws_bytes) return fail(SPL_E_OOM, "workspace too small: %zu < %zu bytes", bytes, B->ws_bytes);
-    if (((uintptr_t)d_ws & 255) != 0) return fail(SPL_E_INVALID_ARG, "workspace must be 256-byte aligned");
+// Upload the plan tables and beam descriptors of the current layout (synchronous).
+static spl_status upload_tables(spl_batch *B) {
     if (B->staging_pending) {
         HIP_TRY(hipEventSynchronize(B->staging_done));
         B->staging_pending = false;
     }
-    if (!B->staging) {
-        HIP_TRY(hipHostMalloc((void **)&B->staging, sizeof(DevBeam) * B->nb, hipHostMallocDefault));
-        HIP_TRY(hipEventCreateWithFlags(&B->staging_done, hipEventDisableTiming));
-    }
-    B->ws = (char *)d_ws;
     for (auto &L : B->layouts) {
         HIP_TRY(hipMemcpy(B->ws + L.off_dcm, L.dtab.data(), L.dtab.size() * sizeof(int32_t),
                           hipMemcpyHostToDevice));
@@ -661,13 +667,13 @@ extern "C" spl_status spl_batch_set_workspace(spl_batch *B, void *d_ws, size_t b
     HIP_TRY(hipMemcpy(B->ws + B->off_beams, B->host_beams.data(), sizeof(DevBeam) * B->nb, hipMemcpyHostToDevice));
     for (auto &g : B->groups) {
         int occ = 0;
-        HIP_TRY(prepare_dedisp(g.dw, g.j, g.nw, g.lds, &occ));
+        HIP_TRY(prepare_dedisp(g.dw, g.j, g.nw, g.sv, g.lds, &occ));
         g.occ = std::max(1, occ);
     }
     for (int b = 0; b < B->nb; ++b) {
         const Tiles &t = B->layouts[B->layout_of_beam[b]].tiles;
         int occ = 0;
-        HIP_TRY(prepare_dedisp(t.dw, t.j, t.nw, B->beam_lds[b], &occ));
+        HIP_TRY(prepare_dedisp(t.dw, t.j, t.nw, t.sv, B->beam_lds[b], &occ));
     }
     if (B->graph_exec) {
         (void)hipGraphExecDestroy(B->graph_exec);
@@ -679,6 +685,19 @@ extern "C" spl_status spl_batch_set_workspace(spl_batch *B, void *d_ws, size_t b
     }
     B->tables_uploaded = true;
     return SPL_OK;
+}
+
+extern "C" spl_status spl_batch_set_workspace(spl_batch *B, void *d_ws, size_t bytes) {
+    if (!B || !d_ws) return fail(SPL_E_INVALID_ARG, "NULL argument");
+    if (bytes < B->ws_bytes) return fail(SPL_E_OOM, "workspace too small: %zu < %zu bytes", bytes, B->ws_bytes);
+    if (((uintptr_t)d_ws & 255) != 0) return fail(SPL_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (!B->staging) {
+        HIP_TRY(hipHostMalloc((void **)&B->staging, sizeof(DevBeam) * B->nb, hipHostMallocDefault));
+        HIP_TRY(hipEventCreateWithFlags(&B->staging_done, hipEventDisableTiming));
+    }
+    B->ws = (char *)d_ws;
+    B->ws_given = bytes;
+    return upload_tables(B);
 }
 
 static hipError_t take_event(spl_batch *B, hipEvent_t *e) {
@@ -737,8 +756,8 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
             const int n = G.item_hi - G.item_lo;
             if (n <= 0) continue;
             const int grid = std::min(n, G.occ * 256);
-            HIP_TRY(launch_dedisp(G.dw, G.j, G.nw, beams, items, G.item_lo, G.item_hi, &run->queue[g], grid, G.lds,
-                                  s));
+            HIP_TRY(launch_dedisp(G.dw, G.j, G.nw, G.sv, beams, items, G.item_lo, G.item_hi, &run->queue[g], grid,
+                                  G.lds, s));
         }
     } else {
         for (int b = b_lo; b < b_hi; ++b) {
@@ -746,7 +765,7 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
             const int lo = B->item_base[b];
             const PlanLayout &L = B->layouts[B->layout_of_beam[b]];
             const int hi = lo + L.ntile_d * L.ntile_t;
-            HIP_TRY(launch_dedisp(t.dw, t.j, t.nw, beams, items, lo, hi, nullptr, hi - lo, B->beam_lds[b], s));
+            HIP_TRY(launch_dedisp(t.dw, t.j, t.nw, t.sv, beams, items, lo, hi, nullptr, hi - lo, B->beam_lds[b], s));
         }
     }
     HIP_TRY(t_dd.stop());
@@ -895,7 +914,7 @@ extern "C" spl_status spl_batch_get_tiles(const spl_batch *B, int32_t beam, spl_
 extern "C" spl_status spl_batch_set_tiles(spl_batch *B, int32_t beam, const spl_tiles *tiles) {
     if (!B || !tiles || beam < 0 || beam >= B->nb) return fail(SPL_E_INVALID_ARG, "bad argument");
     const int nw = tiles->waves ? tiles->waves : 4;
-    if (!dedisp_shape_supported(tiles->dm_per_wave, tiles->time_groups, nw))
+    if (!dedisp_shape_supported(tiles->dm_per_wave, tiles->time_groups, nw, 1))
         return fail(SPL_E_UNSUPPORTED, "tile shape (%d, %d, %d) is not compiled in", tiles->dm_per_wave,
                     tiles->time_groups, nw);
     if (tiles->chan_chunk < 0 || tiles->chan_chunk > kDedispStageRows * nw)
@@ -909,15 +928,183 @@ extern "C" spl_status spl_batch_set_tiles(spl_batch *B, int32_t beam, const spl_
     L.tiles.cc = tiles->chan_chunk;
     spl_status st = build_layout(B);
     if (st == SPL_OK) {
-        if ((size_t)2 * L.half + (size_t)L.tiles.cc * L.td * 4 > 160 * 1024 - 256)
+        if ((size_t)4 * L.quarter + (size_t)(kDedispStageRows * L.tiles.nw + 4) * L.td * 4 > 160 * 1024 - 256)
             st = fail(SPL_E_UNSUPPORTED, "tile does not fit the LDS");
     }
     if (st != SPL_OK) {
         L.tiles = old;
         (void)build_layout(B);
+        if (B->ws) (void)upload_tables(B);
         return st;
     }
+    if (B->ws) return upload_tables(B);
     return SPL_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+namespace {
+
+uint64_t fnv64(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// Everything the dedispersion kernel's speed depends on: sizes and the delay table.
+std::string plan_signature(const spl_plan &p) {
+    uint64_t h = fnv64(p.delays.data(), p.delays.size() * sizeof(int32_t));
+    char buf[160];
+    snprintf(buf, sizeof buf, "nch%d-ndm%d-nout%d-ndd%d-d%016llx", p.nch, p.ndm, p.n_out, p.n_dd,
+             (unsigned long long)h);
+    return buf;
+}
+
+struct TuneEntry {
+    Tiles t;
+    double ms = 0;
+};
+
+// Cache file: one line per plan, "<signature> <trials/wave> <groups> <waves> <chan_chunk> <ms>".
+std::vector<std::pair<std::string, TuneEntry>> read_cache(const char *path) {
+    std::vector<std::pair<std::string, TuneEntry>> out;
+    if (!path) return out;
+    FILE *f = fopen(path, "r");
+    if (!f) return out;
+    char sig[256];
+    TuneEntry e;
+    while (fscanf(f, "%255s %d %d %d %d %lf", sig, &e.t.dw, &e.t.j, &e.t.nw, &e.t.cc, &e.ms) == 6)
+        out.emplace_back(sig, e);
+    fclose(f);
+    return out;
+}
+
+void write_cache(const char *path, const std::vector<std::pair<std::string, TuneEntry>> &c) {
+    if (!path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (const auto &kv : c)
+        fprintf(f, "%s %d %d %d %d %.6f\n", kv.first.c_str(), kv.second.t.dw, kv.second.t.j, kv.second.t.nw,
+                kv.second.t.cc, kv.second.ms);
+    fclose(f);
+    (void)rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
+extern "C" spl_status spl_autotune(spl_batch *B, const uint8_t *const *d_blocks, const int64_t *pitches,
+                                   const char *cache_path, int32_t flags, hipStream_t stream) {
+    if (!B || !d_blocks || !pitches) return fail(SPL_E_INVALID_ARG, "NULL argument");
+    if (!B->tables_uploaded) return fail(SPL_E_INVALID_ARG, "spl_batch_set_workspace was not called");
+    for (int b = 0; b < B->nb; ++b) {
+        const spl_plan &p = *B->plans[b];
+        if (!d_blocks[b] || ((uintptr_t)d_blocks[b] & 15) || pitches[b] < p.n_in || (pitches[b] & 15))
+            return fail(SPL_E_INVALID_ARG, "block or pitch of beam %d is invalid", b);
+        B->cur_x[b] = d_blocks[b];
+        B->cur_pitch[b] = pitches[b];
+    }
+    auto cache = read_cache(cache_path);
+    static const int shapes[][3] = {{2, 2, 8}, {4, 1, 4}, {4, 2, 4}, {4, 1, 8}, {4, 2, 8}, {8, 1, 4}, {8, 1, 8}};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    unsigned long long *d_sum = (unsigned long long *)(B->ws + B->off_run);   // run state is scratch here
+    spl_status result = SPL_OK;
+    for (size_t li = 0; li < B->layouts.size() && result == SPL_OK; ++li) {
+        int rep = 0;
+        while (B->layout_of_beam[rep] != (int)li) ++rep;
+        const std::string sig = plan_signature(*B->layouts[li].plan);
+        bool cached = false;
+        if (!(flags & SPL_TUNE_FORCE)) {
+            for (const auto &kv : cache)
+                if (kv.first == sig) {
+                    B->layouts[li].tiles = kv.second.t;
+                    B->layouts[li].tiles.sv = 1;
+                    cached = true;
+                }
+        }
+        if (cached) {
+            if (build_layout(B) == SPL_OK) continue;
+            B->layouts[li].tiles = Tiles{};   // a stale entry: tune afresh
+        }
+        TuneEntry best;
+        best.ms = 1e300;
+        bool have_ref = false;
+        unsigned long long ref = 0;
+        for (const auto &sh : shapes) {
+            for (int cc = 2; cc <= 2 * sh[2]; cc *= 2) {
+                PlanLayout &L = B->layouts[li];
+                L.tiles = Tiles{};
+                L.tiles.dw = sh[0];
+                L.tiles.j = sh[1];
+                L.tiles.nw = sh[2];
+                L.tiles.cc = cc;
+                if (build_layout(B) != SPL_OK) continue;
+                if (B->beam_lds[rep] > 160 * 1024 - 256) continue;
+                spl_status st = upload_tables(B);
+                if (st != SPL_OK) { result = st; break; }
+                const DevBeam *beams = (const DevBeam *)(B->ws + B->off_beams);
+                const DedispItem *items = (const DedispItem *)(B->ws + B->off_items);
+                const int lo = B->item_base[rep], hi = lo + L.ntile_d * L.ntile_t;
+                const Tiles t = L.tiles;
+                float best_run = 1e30f;
+                for (int r = 0; r < 4; ++r) {
+                    HIP_TRY(hipEventRecord(e0, stream));
+                    HIP_TRY(launch_dedisp(t.dw, t.j, t.nw, t.sv, beams, items, lo, hi, nullptr, hi - lo,
+                                          B->beam_lds[rep], stream));
+                    HIP_TRY(hipEventRecord(e1, stream));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    if (r > 0) best_run = std::min(best_run, ms);   // first run warms caches
+                }
+                HIP_TRY(hipMemsetAsync(d_sum, 0, sizeof(unsigned long long), stream));
+                const spl_plan &p = *L.plan;
+                HIP_TRY(launch_checksum((const int32_t *)(B->ws + B->off_X[rep]), p.ndm, B->xpitch[rep], p.n_dd,
+                                        d_sum, stream));
+                unsigned long long sum = 0;
+                HIP_TRY(hipMemcpyAsync(&sum, d_sum, sizeof sum, hipMemcpyDeviceToHost, stream));
+                HIP_TRY(hipStreamSynchronize(stream));
+                if (!have_ref) {
+                    ref = sum;
+                    have_ref = true;
+                } else if (sum != ref) {
+                    result = fail(SPL_E_INTERNAL, "tile shape (%d, %d, %d, %d) changed the DM transform", t.dw, t.j,
+                                  t.nw, t.cc);
+                    break;
+                }
+                if (best_run < best.ms) {
+                    best.ms = best_run;
+                    best.t = t;
+                }
+            }
+            if (result != SPL_OK) break;
+        }
+        if (result != SPL_OK) break;
+        if (!have_ref) {
+            result = fail(SPL_E_UNSUPPORTED, "no compiled tile shape fits the plan");
+            break;
+        }
+        B->layouts[li].tiles = best.t;
+        spl_status st = build_layout(B);
+        if (st != SPL_OK) { result = st; break; }
+        bool replaced = false;
+        for (auto &kv : cache)
+            if (kv.first == sig) { kv.second = best; replaced = true; }
+        if (!replaced) cache.emplace_back(sig, best);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != SPL_OK) {
+        (void)build_layout(B);
+        (void)upload_tables(B);
+        return result;
+    }
+    write_cache(cache_path, cache);
+    return upload_tables(B);
 }
 
 extern "C" spl_status spl_batch_set_profiling(spl_batch *B, int32_t enable) {

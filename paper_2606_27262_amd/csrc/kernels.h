@@ -7,11 +7,11 @@
 
 namespace spl {
 
-constexpr int kDedispStageRows = 4;   // staged rows per wavefront and chunk
-constexpr int kDedispMaxRowVecs = 128; // 16-byte input vectors per staged row
-bool dedisp_shape_supported(int dw, int j, int nw);
-hipError_t prepare_dedisp(int dw, int j, int nw, size_t lds_bytes, int *blocks_per_cu);
-hipError_t launch_dedisp(int dw, int j, int nw, const DevBeam *beams, const DedispItem *items, int item_lo,
+constexpr int kDedispStageRows = 2;   // staged rows per wavefront and chunk (chan_chunk <= 2 * waves)
+// A staged row holds up to 1024 * sv bytes (sv = 16-byte vectors per lane, 1 or 2).
+bool dedisp_shape_supported(int dw, int j, int nw, int sv);
+hipError_t prepare_dedisp(int dw, int j, int nw, int sv, size_t lds_bytes, int *blocks_per_cu);
+hipError_t launch_dedisp(int dw, int j, int nw, int sv, const DevBeam *beams, const DedispItem *items, int item_lo,
                          int item_hi, int *queue, int grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_thresholds(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, int row_hi,
@@ -35,6 +35,8 @@ hipError_t launch_scatter(const DevBeam *beams, int beam_lo, int beam_hi, const 
                           spl_candidate *cands, int64_t cand_cap, hipStream_t s);
 hipError_t launch_pass_end(DevRun *run, spl_run_stats *stats, int64_t hit_cap, int nst, hipStream_t s);
 hipError_t launch_finalize(DevRun *run, spl_run_stats *stats, int64_t cand_cap, hipStream_t s);
+hipError_t launch_checksum(const int32_t *X, int ndm, int xpitch, int n_dd, unsigned long long *out,
+                           hipStream_t s);
 hipError_t launch_mu_sigma(const int64_t *n, const int64_t *s1, const int64_t *s2, int64_t count, double *mu,
                            double *sigma, hipStream_t s);
 

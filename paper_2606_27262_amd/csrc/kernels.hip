@@ -122,30 +122,38 @@ __global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
 
 // ------------------------------------------------------------- dedispersion
 // Workgroup = NW wavefronts; item = (beam, DM tile of NW*DW trials, time tile of 256*J
-// samples).  Wavefront w owns DM trials d0 + w*DW ... + DW-1; lane l owns the sample
-// pairs t0 + 128 g + 2 l + {0,1}, g < 2J, so that the lanes of a wavefront read
-// consecutive LDS dwords (no bank conflicts).
+// samples).  Wavefront w owns DM trials d0 + w*DW ... + DW-1; lane l owns samples
+// t0 + 256 j + 4 l + {0,1,2,3}, j < J.
 //
-// Channels are staged chan_chunk at a time.  Row r of the LDS holds channel c as
-// 16-bit samples starting at ws_c, the 16-aligned start of the tile's smallest delay,
-// twice: copy A at byte r*R (sample ws_c + k at 16-bit slot k) and copy B at byte
-// half + r*R (sample ws_c + k + 1 at slot k).  Every delay s then starts on a dword
-// boundary of one of the two copies, at byte 4*(s>>1) + (s&1)*half - 2*(ws_c - t0)
-// past the row's origin (ws_c - t0 depends only on the channel and the DM tile); that
-// offset is precomputed per (channel, trial) in the plan table, so a trial costs one
-// address add per channel, and each 2 groups one ds_read2st64_b32 and two packed
-// 16-bit adds (exact for up to 256 channels, then widened into int32 accumulators).  Every staged row is read by all NW*DW trials.
-// The global loads of the next chunk are issued before the current chunk is summed.
-constexpr int kStageRows = 4;   // staged rows per wavefront and chunk (chan_chunk <= 4*NW)
-constexpr int kStageVecs = 2;   // 16-byte input vectors per lane and row (row <= 2048 samples)
-
-template <int DW, int J, int NW>
+// Channels are staged chan_chunk at a time.  Row r of the LDS holds channel c from
+// ws_c = t0 + (tile_base_c & ~15) (16-aligned start of the tile's smallest delay) in
+// four copies, copy k shifted by k bytes (copy k, byte i = sample ws_c + k + i), so that
+// the 4 samples a lane needs for any delay s are one aligned dword of copy s & 3, at
+// byte ((s - ws_c + t0) & ~3) + (s & 3)*quarter of the row.  That offset is precomputed
+// per (channel, trial) in the plan table; the chunk's slice of the table is staged in
+// LDS with the samples.  Per (trial, channel) a lane does one address add, per 256
+// samples one dword read (lanes read consecutive dwords: conflict-free, paired into
+// ds_read2st64_b32), and two v_perm that spread bytes (t, t+2) and (t+1, t+3) into
+// 16-bit fields, summed for two channels at a time with v_add3_u32 (exact for up to
+// 256 channels, then widened into int32 accumulators).  The LDS loads of the next
+// channel are in flight while the current one is summed, and the global loads of the
+// next chunk while the current chunk is summed.
+// SV: 16-byte input vectors staged per lane and row (rows of up to 1024*SV bytes);
+// each wavefront stages up to kDedispStageRows rows per chunk (chan_chunk <= that * NW).
+template <int DW, int J, int NW, int SV>
 __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ beams,
                                                     const DedispItem *__restrict__ items,
                                                     int item_lo, int item_hi, int *queue) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ int s_item;
     const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+    constexpr int TD = NW * DW;
+    constexpr int kStageRows = kDedispStageRows;
+    constexpr int kStageVecs = SV;
+    constexpr int kTabRows = kStageRows * NW + 4;   // chan_chunk rows + 4 rows of prefetch padding
+    constexpr int kTabRegs = (kTabRows * TD + 64 * NW - 1) / (64 * NW);
+    constexpr uint32_t kSelEven = 0x0C020C00u;   // bytes 0, 2 -> 16-bit fields
+    constexpr uint32_t kSelOdd = 0x0C030C01u;    // bytes 1, 3 -> 16-bit fields
 
     int it = item_lo + blockIdx.x;
     for (;;) {
@@ -159,31 +167,28 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
 
         const DedispItem item = items[it];
         const DevBeam &B = beams[item.beam];
-        const int nch = B.nch, ndm_pad = B.ndm_pad, R = item.row_bytes, half = B.lds_half;
+        const int nch = B.nch, ndm_pad = B.ndm_pad, R = item.row_bytes, quarter = B.lds_quarter;
         const int t0 = item.t0, d0 = item.d0;
-        const int dw0 = d0 + wave * DW;
         const int32_t *__restrict__ tab = B.dtab;
         const int32_t *__restrict__ base = B.tile_base + (size_t)(d0 / B.tile_dm) * nch;
         const int64_t pitch = B.pitch;
         const uint8_t *__restrict__ x = B.x;
         const int cchunk = B.chan_chunk;
-        const int nvec = R >> 5;   // 16 input samples -> 32 bytes per copy
+        const int nvec = R >> 4;   // 16-byte vectors per row and copy
+        int32_t *lds_tab = (int32_t *)(lds + 4 * quarter);
 
         int32_t acc[DW][4 * J];
-        uint32_t a16[DW][2 * J];
+        uint32_t ae[DW][J], ao[DW][J];
 #pragma unroll
         for (int i = 0; i < DW; ++i) {
 #pragma unroll
             for (int k = 0; k < 4 * J; ++k) acc[i][k] = 0;
 #pragma unroll
-            for (int k = 0; k < 2 * J; ++k) a16[i][k] = 0u;
+            for (int j = 0; j < J; ++j) ae[i][j] = ao[i][j] = 0u;
         }
 
         // staging registers: rows wave + NW*m, vectors lane + 64*q, and the chunk's slice
         // of the offset table (cc x TD entries, thread tid takes entries tid + 64*NW*e)
-        constexpr int TD = NW * DW;
-        constexpr int kTabRegs = (4 * NW * TD + 64 * NW - 1) / (64 * NW);
-        int32_t *lds_tab = (int32_t *)(lds + 2 * half);
         uint4 pv[kStageRows][kStageVecs];
         uint32_t pv4[kStageRows][kStageVecs];
         int32_t pt[kTabRegs];
@@ -222,42 +227,81 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
 #pragma unroll
             for (int e = 0; e < kTabRegs; ++e) {
                 const int idx = tid + 64 * NW * e;
-                if (idx / TD < cc) lds_tab[idx] = pt[e];
+                const int r = idx / TD;
+                // rows past cc (read by the branch-free prefetch) point at row cc
+                lds_tab[idx] = r < cc ? pt[e] + r * R : cc * R;
+            }
+            if (cc & 1) {   // an odd chunk ends with a zero row (the pair's second row)
+                for (int v = tid; v < 4 * nvec; v += 64 * NW)
+                    *(uint4 *)(lds + (v / nvec) * quarter + cc * R + 16 * (v % nvec)) = make_uint4(0, 0, 0, 0);
             }
 #pragma unroll
             for (int m = 0; m < kStageRows; ++m) {
                 const int r = wave + NW * m;
-                uint8_t *rowA = lds + r * R;
-                uint8_t *rowB = rowA + half;
+                uint8_t *row = lds + r * R;
 #pragma unroll
                 for (int q = 0; q < kStageVecs; ++q) {
                     const int k = lane + 64 * q;
                     if (!(r < cc && k < nvec)) continue;
                     const uint4 v = pv[m][q];
                     const uint32_t v4 = pv4[m][q];
-                    uint4 a0, a1, b0, b1;
-                    a0.x = __builtin_amdgcn_perm(v.x, v.x, 0x0C010C00u);
-                    a0.y = __builtin_amdgcn_perm(v.x, v.x, 0x0C030C02u);
-                    a0.z = __builtin_amdgcn_perm(v.y, v.y, 0x0C010C00u);
-                    a0.w = __builtin_amdgcn_perm(v.y, v.y, 0x0C030C02u);
-                    a1.x = __builtin_amdgcn_perm(v.z, v.z, 0x0C010C00u);
-                    a1.y = __builtin_amdgcn_perm(v.z, v.z, 0x0C030C02u);
-                    a1.z = __builtin_amdgcn_perm(v.w, v.w, 0x0C010C00u);
-                    a1.w = __builtin_amdgcn_perm(v.w, v.w, 0x0C030C02u);
-                    b0.x = __builtin_amdgcn_perm(v.x, v.x, 0x0C020C01u);
-                    b0.y = __builtin_amdgcn_perm(v.y, v.x, 0x0C040C03u);
-                    b0.z = __builtin_amdgcn_perm(v.y, v.y, 0x0C020C01u);
-                    b0.w = __builtin_amdgcn_perm(v.z, v.y, 0x0C040C03u);
-                    b1.x = __builtin_amdgcn_perm(v.z, v.z, 0x0C020C01u);
-                    b1.y = __builtin_amdgcn_perm(v.w, v.z, 0x0C040C03u);
-                    b1.z = __builtin_amdgcn_perm(v.w, v.w, 0x0C020C01u);
-                    b1.w = __builtin_amdgcn_perm(v4, v.w, 0x0C040C03u);
-                    *(uint4 *)(rowA + 32 * k) = a0;
-                    *(uint4 *)(rowA + 32 * k + 16) = a1;
-                    *(uint4 *)(rowB + 32 * k) = b0;
-                    *(uint4 *)(rowB + 32 * k + 16) = b1;
+                    uint4 c1, c2, c3;
+                    c1.x = __builtin_amdgcn_alignbyte(v.y, v.x, 1);
+                    c1.y = __builtin_amdgcn_alignbyte(v.z, v.y, 1);
+                    c1.z = __builtin_amdgcn_alignbyte(v.w, v.z, 1);
+                    c1.w = __builtin_amdgcn_alignbyte(v4, v.w, 1);
+                    c2.x = __builtin_amdgcn_alignbyte(v.y, v.x, 2);
+                    c2.y = __builtin_amdgcn_alignbyte(v.z, v.y, 2);
+                    c2.z = __builtin_amdgcn_alignbyte(v.w, v.z, 2);
+                    c2.w = __builtin_amdgcn_alignbyte(v4, v.w, 2);
+                    c3.x = __builtin_amdgcn_alignbyte(v.y, v.x, 3);
+                    c3.y = __builtin_amdgcn_alignbyte(v.z, v.y, 3);
+                    c3.z = __builtin_amdgcn_alignbyte(v.w, v.z, 3);
+                    c3.w = __builtin_amdgcn_alignbyte(v4, v.w, 3);
+                    *(uint4 *)(row + 16 * k) = v;
+                    *(uint4 *)(row + quarter + 16 * k) = c1;
+                    *(uint4 *)(row + 2 * quarter + 16 * k) = c2;
+                    *(uint4 *)(row + 3 * quarter + 16 * k) = c3;
                 }
             }
+        };
+
+        const uint8_t *lane_lds = lds + 4 * lane;
+        const int32_t *wtab = lds_tab + wave * DW;
+        // the wave's DW offsets of one staged row (16-byte LDS reads)
+        auto read_tab = [&](int r, int32_t (&t)[DW]) {
+            if constexpr (DW % 4 == 0) {
+#pragma unroll
+                for (int i = 0; i < DW; i += 4) {
+                    const int4 v = *(const int4 *)(wtab + r * TD + i);
+                    t[i] = v.x;
+                    t[i + 1] = v.y;
+                    t[i + 2] = v.z;
+                    t[i + 3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < DW; ++i) t[i] = wtab[r * TD + i];
+            }
+        };
+        auto load_row = [&](const int32_t (&t)[DW], uint32_t (&v)[DW][J]) {
+#pragma unroll
+            for (int i = 0; i < DW; ++i) {
+                const uint32_t *p = (const uint32_t *)(lane_lds + t[i]);
+#pragma unroll
+                for (int j = 0; j < J; ++j) v[i][j] = p[64 * j];
+            }
+        };
+        auto add_rows = [&](const uint32_t (&u)[DW][J], const uint32_t (&v)[DW][J]) {
+#pragma unroll
+            for (int i = 0; i < DW; ++i)
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    ae[i][j] += __builtin_amdgcn_perm(u[i][j], u[i][j], kSelEven) +
+                                __builtin_amdgcn_perm(v[i][j], v[i][j], kSelEven);
+                    ao[i][j] += __builtin_amdgcn_perm(u[i][j], u[i][j], kSelOdd) +
+                                __builtin_amdgcn_perm(v[i][j], v[i][j], kSelOdd);
+                }
         };
 
         load_chunk(0);
@@ -268,57 +312,72 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
             if (c0 + cchunk < nch) load_chunk(c0 + cchunk);
             __syncthreads();          // the chunk is staged
 
-            // lds_tab holds each delay's byte offset from its staged row origin; lane l of
-            // row r starts at lds + r*R + 4*l.  The offsets are read from LDS (one
-            // broadcast read per channel) so that only LDS operations are in flight.
-            const uint8_t *lane_lds = lds + 4 * lane;
-            const int32_t *wtab = lds_tab + wave * DW;
-            int vrow = 0;
-#pragma unroll 2
-            for (int r = 0; r < cc; ++r) {
-                int32_t cd[DW];
-#pragma unroll
-                for (int i = 0; i < DW; ++i) cd[i] = wtab[r * TD + i];
-                uint32_t lv[DW][2 * J];
-#pragma unroll
-                for (int i = 0; i < DW; ++i) {
-                    const uint32_t *p = (const uint32_t *)(lane_lds + (vrow + cd[i]));
-#pragma unroll
-                    for (int g = 0; g < 2 * J; ++g) lv[i][g] = p[64 * g];
-                }
-#pragma unroll
-                for (int i = 0; i < DW; ++i)
-#pragma unroll
-                    for (int g = 0; g < 2 * J; ++g) a16[i][g] += lv[i][g];
-                vrow += R;
+            // channel pairs (an odd chunk ends with the zero row).  Software pipeline:
+            // while pair k is summed, the samples of pair k+1 and the offsets of pair
+            // k+2 are in flight (ping-pong buffers, branch-free steady state).
+            const int np = (cc + 1) >> 1;
+            int32_t ta[DW], tb[DW];
+            uint32_t la[DW][J], lb[DW][J], na[DW][J], nb[DW][J];
+            read_tab(0, ta);
+            read_tab(1, tb);
+            load_row(ta, la);
+            load_row(tb, lb);
+            read_tab(2, ta);
+            read_tab(3, tb);
+            int k = 0;
+            for (; k + 3 <= np; k += 2) {
+                load_row(ta, na);               // pair k+1
+                load_row(tb, nb);
+                read_tab(2 * k + 4, ta);        // offsets of pair k+2
+                read_tab(2 * k + 5, tb);
+                add_rows(la, lb);               // pair k
+                load_row(ta, la);               // pair k+2
+                load_row(tb, lb);
+                read_tab(2 * k + 6, ta);        // offsets of pair k+3 (padding rows past the end)
+                read_tab(2 * k + 7, tb);
+                add_rows(na, nb);               // pair k+1
+            }
+            if (np - k == 2) {
+                load_row(ta, na);
+                load_row(tb, nb);
+                add_rows(la, lb);
+                add_rows(na, nb);
+            } else {
+                add_rows(la, lb);
             }
             // widen every 256 channels (chan_chunk is a power of two <= 256)
             if (((c0 + cc) & 255) == 0 || c0 + cc >= nch) {
 #pragma unroll
                 for (int i = 0; i < DW; ++i)
 #pragma unroll
-                    for (int g = 0; g < 2 * J; ++g) {
-                        acc[i][2 * g] += (int32_t)(a16[i][g] & 0xFFFFu);
-                        acc[i][2 * g + 1] += (int32_t)(a16[i][g] >> 16);
-                        a16[i][g] = 0u;
+                    for (int j = 0; j < J; ++j) {
+                        acc[i][4 * j + 0] += (int32_t)(ae[i][j] & 0xFFFFu);
+                        acc[i][4 * j + 2] += (int32_t)(ae[i][j] >> 16);
+                        acc[i][4 * j + 1] += (int32_t)(ao[i][j] & 0xFFFFu);
+                        acc[i][4 * j + 3] += (int32_t)(ao[i][j] >> 16);
+                        ae[i][j] = ao[i][j] = 0u;
                     }
             }
         }
 
         // write the DM transform
         const int ndm = B.ndm, n_dd = B.n_dd;
+        const int dw0 = d0 + wave * DW;
 #pragma unroll
         for (int i = 0; i < DW; ++i) {
             const int d = dw0 + i;
             if (d >= ndm) continue;
             int32_t *Xr = B.X + (size_t)d * B.xpitch;
 #pragma unroll
-            for (int g = 0; g < 2 * J; ++g) {
-                const int t = t0 + 128 * g + 2 * lane;
-                if (t + 1 < n_dd) {
-                    *(int2 *)(Xr + t) = make_int2(acc[i][2 * g], acc[i][2 * g + 1]);
-                } else if (t < n_dd) {
-                    Xr[t] = acc[i][2 * g];
+            for (int j = 0; j < J; ++j) {
+                const int t = t0 + 256 * j + 4 * lane;
+                if (t + 3 < n_dd) {
+                    *(int4 *)(Xr + t) = make_int4(acc[i][4 * j], acc[i][4 * j + 1],
+                                                  acc[i][4 * j + 2], acc[i][4 * j + 3]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (t + e < n_dd) Xr[t + e] = acc[i][4 * j + e];
                 }
             }
         }
@@ -659,6 +718,22 @@ __global__ void k_finalize(DevRun *run, spl_run_stats *stats, int64_t cand_cap) 
     stats->cand_overflow = run->n_cand_total > cand_cap ? 1 : 0;
 }
 
+// Position-weighted checksum of a DM transform (verifies that retiled kernels give
+// identical output): sum over (d, t) of X[d][t] * (1 + d * 65599 + t * 131), wrapping.
+__global__ void k_checksum(const int32_t *X, int ndm, int xpitch, int n_dd, unsigned long long *out) {
+    __shared__ unsigned long long sh[kThreads / 64];
+    unsigned long long s = 0;
+    const int64_t n = (int64_t)ndm * n_dd;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int d = (int)(i / n_dd), t = (int)(i - (int64_t)d * n_dd);
+        s += (unsigned long long)(uint32_t)X[(size_t)d * xpitch + t] *
+             (1ull + (unsigned long long)d * 65599ull + (unsigned long long)t * 131ull);
+    }
+    unsigned long long tot;
+    (void)block_exclusive_scan<unsigned long long>(s, &tot, sh);
+    if (threadIdx.x == 0) atomicAdd(out, tot);
+}
+
 // Normaliser test hook: mu and sigma from exact moments, as the search computes them.
 __global__ void k_mu_sigma(const int64_t *n, const int64_t *s1, const int64_t *s2, int64_t count,
                            double *mu, double *sigma) {
@@ -670,49 +745,51 @@ __global__ void k_mu_sigma(const int64_t *n, const int64_t *s1, const int64_t *s
 #define SPL_HIP_LAUNCH_CHECK() \
     do { hipError_t e__ = hipGetLastError(); if (e__ != hipSuccess) return e__; } while (0)
 
-template <int DW, int J, int NW>
+template <int DW, int J, int NW, int SV>
 static hipError_t prepare_dedisp_t(size_t lds_bytes, int *blocks_per_cu) {
     if (lds_bytes > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_dedisp<DW, J, NW>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_dedisp<DW, J, NW, SV>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
     }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_dedisp<DW, J, NW>, 64 * NW, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_dedisp<DW, J, NW, SV>, 64 * NW, lds_bytes);
 }
 
-template <int DW, int J, int NW>
+template <int DW, int J, int NW, int SV>
 static hipError_t launch_dedisp_t(const DevBeam *beams, const DedispItem *items, int item_lo, int item_hi,
                                   int *queue, int grid, size_t lds_bytes, hipStream_t s) {
-    hipLaunchKernelGGL((k_dedisp<DW, J, NW>), dim3(grid), dim3(64 * NW), lds_bytes, s, beams, items, item_lo,
+    hipLaunchKernelGGL((k_dedisp<DW, J, NW, SV>), dim3(grid), dim3(64 * NW), lds_bytes, s, beams, items, item_lo,
                        item_hi, queue);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-// The compiled dedispersion shapes (DM trials per wavefront, 256-sample groups per
-// lane, wavefronts per workgroup).
+// The compiled dedispersion shapes: (DM trials per wavefront, 256-sample groups per
+// lane, wavefronts per workgroup, 16-byte vectors staged per lane and row).
 #define SPL_DEDISP_SHAPES(X) \
-    X(2, 2, 8) X(2, 4, 8) X(4, 1, 4) X(4, 2, 4) X(4, 4, 4) X(4, 1, 8) X(4, 2, 8) \
-    X(8, 1, 4) X(8, 2, 4) X(8, 1, 8) X(16, 1, 4)
+    X(2, 2, 8, 1) X(4, 1, 4, 1) X(4, 2, 4, 1) X(4, 1, 8, 1) X(4, 2, 8, 1) X(8, 1, 4, 1) \
+    X(8, 1, 8, 1) X(2, 2, 8, 2) X(4, 1, 4, 2) X(4, 1, 8, 2) X(4, 2, 8, 2)
 
-bool dedisp_shape_supported(int dw, int j, int nw) {
-#define SPL_X(a, b, c) if (dw == a && j == b && nw == c) return true;
+bool dedisp_shape_supported(int dw, int j, int nw, int sv) {
+#define SPL_X(a, b, c, d) if (dw == a && j == b && nw == c && sv == d) return true;
     SPL_DEDISP_SHAPES(SPL_X)
 #undef SPL_X
     return false;
 }
 
-hipError_t prepare_dedisp(int dw, int j, int nw, size_t lds_bytes, int *blocks_per_cu) {
-#define SPL_X(a, b, c) if (dw == a && j == b && nw == c) return prepare_dedisp_t<a, b, c>(lds_bytes, blocks_per_cu);
+hipError_t prepare_dedisp(int dw, int j, int nw, int sv, size_t lds_bytes, int *blocks_per_cu) {
+#define SPL_X(a, b, c, d) \
+    if (dw == a && j == b && nw == c && sv == d) return prepare_dedisp_t<a, b, c, d>(lds_bytes, blocks_per_cu);
     SPL_DEDISP_SHAPES(SPL_X)
 #undef SPL_X
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_dedisp(int dw, int j, int nw, const DevBeam *beams, const DedispItem *items, int item_lo,
+hipError_t launch_dedisp(int dw, int j, int nw, int sv, const DevBeam *beams, const DedispItem *items, int item_lo,
                          int item_hi, int *queue, int grid, size_t lds_bytes, hipStream_t s) {
-#define SPL_X(a, b, c) \
-    if (dw == a && j == b && nw == c) return launch_dedisp_t<a, b, c>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
+#define SPL_X(a, b, c, d)                                                                                     \
+    if (dw == a && j == b && nw == c && sv == d)                                                              \
+        return launch_dedisp_t<a, b, c, d>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
     SPL_DEDISP_SHAPES(SPL_X)
 #undef SPL_X
     return hipErrorInvalidValue;
@@ -819,6 +896,13 @@ hipError_t launch_pass_end(DevRun *run, spl_run_stats *stats, int64_t hit_cap, i
 
 hipError_t launch_finalize(DevRun *run, spl_run_stats *stats, int64_t cand_cap, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, run, stats, cand_cap);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_checksum(const int32_t *X, int ndm, int xpitch, int n_dd, unsigned long long *out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_checksum, dim3(1024), dim3(kThreads), 0, s, X, ndm, xpitch, n_dd, out);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -20,7 +20,7 @@ struct DevBeam {
     int64_t pitch;           // bytes
     const int32_t *dtab;     // LDS byte offset of each delay from its staged row origin,
                              // channel-major [nch][ndm_pad]:
-                             // 4*(s>>1) + (s&1)*lds_half - 2*(tile_base & ~15)
+                             // ((s - b) & ~3) + (s & 3)*lds_quarter, b = tile_base & ~15
     const int32_t *tile_base;// min delay over each DM tile [ndm_tiles][nch]
     int32_t *X;              // DM transform [ndm][xpitch]
     int64_t *S1, *S2;        // [ndm][nseg]
@@ -34,7 +34,7 @@ struct DevBeam {
     int32_t chunk_base;      // global boxcar chunk of (d = 0, k = 0)
     int32_t nchunk_t;        // boxcar chunks per row
     int32_t chan_chunk;      // channels staged in LDS per step (power of two <= 256)
-    int32_t lds_half;        // byte offset of the odd-aligned copy in the LDS
+    int32_t lds_quarter;     // bytes per shifted copy of the staged rows in the LDS
     int32_t tile_dm;         // DM trials per dedispersion tile
     int32_t beam;
     int32_t w_max;
@@ -48,7 +48,7 @@ struct DedispItem {
     int32_t beam;
     int32_t d0;        // first DM trial of the tile
     int32_t t0;        // first output sample of the tile
-    int32_t row_bytes; // LDS bytes per staged channel row of one copy (multiple of 32)
+    int32_t row_bytes; // LDS bytes per staged channel row of one copy (multiple of 16)
 };
 
 // A boxcar hit: one (row, t) above threshold with its best width.

@@ -109,6 +109,7 @@ _sig("spl_batch_get_tiles", [_P, _I32, ctypes.POINTER(_Tiles)])
 _sig("spl_batch_set_tiles", [_P, _I32, ctypes.POINTER(_Tiles)])
 _sig("spl_batch_destroy", [_P], None)
 _sig("spl_batch_set_profiling", [_P, _I32])
+_sig("spl_autotune", [_P, ctypes.POINTER(_P), ctypes.POINTER(_I64), ctypes.c_char_p, _I32, _P])
 _sig("spl_batch_stage_times", [_P, _P, _P, _I32])
 _sig("spl_debug_mu_sigma", [_P, _P, _P, _I64, _P, _P, _P])
 _sig("spl_opt_defaults", [ctypes.POINTER(_OptParams)], None)
@@ -257,6 +258,18 @@ class Batch:
             _check(_lib.spl_batch_run(self._h, ptrs, pitches, cptr, cap, ctypes.c_void_p(stats.data_ptr()),
                                       _stream_handle(stream)))
         return cands, stats
+
+    def autotune(self, blocks, cache_path=None, force=False, stream=None):
+        """Choose the dedispersion tiling of every plan by timing the compiled shapes
+        on `blocks` (see spl_autotune).  Returns the chosen tiles per beam."""
+        if self.ws is None:
+            self.attach()
+        nb = len(self.plans)
+        ptrs = (_P * nb)(*[b.data_ptr() for b in blocks])
+        pitches = (_I64 * nb)(*[b.stride(0) for b in blocks])
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(_lib.spl_autotune(self._h, ptrs, pitches, path, 1 if force else 0, _stream_handle(stream)))
+        return [self.tiles(b) for b in range(nb)]
 
     def set_profiling(self, enable=True):
         _check(_lib.spl_batch_set_profiling(self._h, 1 if enable else 0))

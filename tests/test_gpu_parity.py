@@ -255,3 +255,28 @@ def test_degenerate_shapes(spl):
         g = gpu_run(spl, [p], [x])
         ref, rc = oracle_run([p], [x])
         compare(g, ref, rc)
+
+
+def test_autotune_keeps_results_and_caches(spl, tmp_path):
+    """The autotuner times every compiled shape, verifies identical DM transforms,
+    and caches its choice; the tuned batch still matches the oracle."""
+    pd = W.make_plan(1024, 550.0, 750.0, 1.31072e-3, 4096, 0.0, 1000.0, 256, W.W256)
+    p = make_plan(spl, 0, 0, 0, None, 0, plan_dict=pd)
+    rng = np.random.default_rng(21)
+    x = rng.integers(0, 256, size=(1024, p.info["n_in"]), dtype=np.uint8)
+    ref, rc = oracle_run([p], [x])
+    batch = spl.Batch([p, p], mode=spl.MODE_PERSISTENT_GRAPH)
+    tb = [spl.upload_block(x), spl.upload_block(x)]
+    cache = tmp_path / "tiles.txt"
+    tiles = batch.autotune(tb, cache_path=str(cache))
+    say("tuned", tiles)
+    assert cache.exists() and len(cache.read_text().splitlines()) == 1
+    g = gpu_run(spl, [p, p], [x, x], batch=batch)
+    for b in range(2):
+        assert np.array_equal(g["X"][b], ref[0]["X"])
+    rc2 = np.concatenate([rc, rc.copy()])
+    rc2["beam"][rc.size:] = 1
+    assert np.array_equal(g["cands"], rc2)
+    # a second batch reuses the cached choice
+    b2 = spl.Batch([p])
+    assert b2.autotune([tb[0]], cache_path=str(cache))[0] == tiles[0]
