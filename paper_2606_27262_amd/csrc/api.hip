@@ -785,7 +785,7 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
     HIP_TRY(launch_scan_i32(counts, nullptr, chunk_hi - chunk_lo, block_sums, chunk_off, &run->n_hits, s));
     HIP_TRY(launch_row_start(beams, b_lo, b_hi, row_lo, row_hi, chunk_lo, chunk_off, &run->n_hits, cap, row_start,
                              s));
-    HIP_TRY(launch_boxcar(true, beams, b_lo, b_hi, chunk_lo, chunk_hi, w_max, nullptr, chunk_off, hits, cap, s));
+    HIP_TRY(launch_boxcar(true, beams, b_lo, b_hi, chunk_lo, chunk_hi, w_max, counts, chunk_off, hits, cap, s));
     HIP_TRY(t_bc.stop());
     // 4. peak filters, then ordered compaction into candidate records
     StageTimer t_pk(B, s, SPL_STAGE_PEAKS);

@@ -437,95 +437,170 @@ __global__ __launch_bounds__(kThreads) void k_thresholds(const DevBeam *__restri
 }
 
 // ------------------------------------------------------------------- boxcars
-// Workgroup = one row chunk of kBoxTile owned samples.  P[i] = X[t0] + ... + X[t0+i-1]
-// in wrapping uint32; a window sum P[i+w] - P[i] is exact because every true sum is
-// below 2^31.  Thread k evaluates samples t0 + 4k .. t0 + 4k + 3 so that hits come out
-// in t order.  EMIT = false counts hits per chunk; EMIT = true writes them at the
-// chunk's offset from the exclusive scan of the counts.
+// Workgroup = one row chunk of kBoxTile owned samples.  The LDS holds the inclusive
+// prefix sums S[i] = X[t0] + ... + X[t0+i] at index i + 1 (index 0 holds 0) as wrapping
+// uint32; a window sum S[t+w-1] - S[t-1] is exact because every true sum is below 2^31.
+// Thread k evaluates the 4 consecutive samples 4k + 1024q + {0..3} of each quarter q, so
+// its LDS reads are 16-byte vectors at consecutive addresses across lanes.  Hits of a
+// sample form a bitmask over the widths; only samples with hits evaluate the binary64
+// S/N to pick the best width.  EMIT = false counts hits per chunk; EMIT = true writes them
+// at the chunk's offset (in t order) and skips chunks without hits.
+__device__ __forceinline__ uint32_t lds_u32(const uint32_t *S, int i) { return S[i]; }
+
 template <bool EMIT>
 __global__ __launch_bounds__(kThreads) void k_boxcar(const DevBeam *__restrict__ beams, int beam_lo,
                                                      int beam_hi, int chunk_lo, int32_t *counts,
                                                      const int64_t *offsets, Hit *hits, int64_t cap) {
-    extern __shared__ uint32_t P[];
+    extern __shared__ __align__(16) uint32_t S[];
     __shared__ uint32_t sh32[kThreads / 64];
     __shared__ int64_t sh64[kThreads / 64];
+    constexpr int kQ = kBoxTile / 1024;   // quarters of 1024 samples
     const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+    if (EMIT && counts[blockIdx.x] == 0) return;   // uniform: no hits in this chunk
     const int g = chunk_lo + blockIdx.x;
     const DevBeam &B = beams[beam_of_chunk(beams, beam_lo, beam_hi, g)];
     const int local = g - B.chunk_base;
     const int d = local / B.nchunk_t;
     const int t0 = (local - d * B.nchunk_t) * kBoxTile;
-    const int M = kBoxTile + B.w_max - 1;
-    const int32_t *Xr = B.X + (size_t)d * B.xpitch;
+    const int M = kBoxTile + B.w_max - 1;              // prefix entries needed
+    const int nvalid = min(M, B.n_dd - t0);
+    const int32_t *Xr = B.X + (size_t)d * B.xpitch + t0;
 
-    if (tid == 0) P[0] = 0u;
+    // prefix sums in stripes of 1024 (4 consecutive per thread)
+    if (tid == 0) S[0] = 0u;
     uint32_t carry = 0;
-    for (int base = 0; base < M; base += kThreads) {
-        const int i = base + tid;
-        const uint32_t v = (i < M && t0 + i < B.n_dd) ? (uint32_t)Xr[t0 + i] : 0u;
-        const uint32_t x = wave_inclusive_scan(v);
+    for (int base = 0; base < M; base += 4 * kThreads) {
+        const int i0 = base + 4 * tid;
+        uint32_t v[4];
+        if (i0 + 3 < nvalid) {
+            const int4 q4 = *(const int4 *)(Xr + i0);
+            v[0] = (uint32_t)q4.x; v[1] = (uint32_t)q4.y; v[2] = (uint32_t)q4.z; v[3] = (uint32_t)q4.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = i0 + k < nvalid ? (uint32_t)Xr[i0 + k] : 0u;
+        }
+        v[1] += v[0];
+        v[2] += v[1];
+        v[3] += v[2];
+        const uint32_t x = wave_inclusive_scan(v[3]);
         if (lane == 63) sh32[wave] = x;
         __syncthreads();
-        uint32_t pre = 0, tot = 0;
+        uint32_t pre = carry, tot = 0;
 #pragma unroll
         for (int w = 0; w < kThreads / 64; ++w) {
             if (w < wave) pre += sh32[w];
             tot += sh32[w];
         }
-        if (i < M) P[i + 1] = carry + pre + x;
+        pre += x - v[3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i0 + k < M) S[i0 + k + 1] = pre + v[k];
         carry += tot;
         __syncthreads();
     }
 
+    const int nw = B.nw, L = B.L, nseg = B.nseg;
+    const int tend = min(t0 + kBoxTile, B.n_out);   // owned samples of this chunk: [t0, tend)
     int cnt = 0;
-    int hw[4], hB[4], ht[4];
-    double hs[4];
+    uint32_t mask[kQ][4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int li = 4 * tid + e, t = t0 + li;
-        hw[e] = 0;
-        if (t >= B.n_out) continue;
-        const int sg = t / B.L;
-        const size_t idx = (size_t)d * B.nseg + sg;
-        const double mu = B.mu[idx], sigma = B.sigma[idx];
-        const int32_t *Tp = B.T + idx * B.nw;
-        double best = 0.0;
-        for (int j = 0; j < B.nw; ++j) {
-            const int w = B.widths[j];
-            const int32_t Bw = (int32_t)(P[li + w] - P[li]);
-            if (Bw >= Tp[j]) {
-                const double s = snr_of(Bw, w, mu, sigma);
-                if (hw[e] == 0 || s > best) {
-                    best = s;
-                    hw[e] = w;
-                    hB[e] = Bw;
+    for (int q = 0; q < kQ; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) mask[q][e] = 0u;
+
+    if (tend > t0) {
+        // segments spanned by the chunk (usually one); thresholds of a segment are uniform
+        for (int sg = t0 / L; sg <= (tend - 1) / L; ++sg) {
+            const int s_lo = max(sg * L, t0) - t0, s_hi = min((sg + 1) * L, tend) - t0;
+            const cint32 *Tp = as_const(B.T + ((size_t)d * nseg + sg) * nw);
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int li = 1024 * q + 4 * tid;   // local index of the first of 4 samples
+                const uint4 lo = *(const uint4 *)&S[li];
+                const uint4 nx = *(const uint4 *)&S[li + 4];
+                const uint32_t s0[8] = {lo.x, lo.y, lo.z, lo.w, nx.x, nx.y, nx.z, nx.w};
+                for (int j = 0; j < nw; ++j) {
+                    const int w = B.widths[j];
+                    const int32_t T = Tp[j];
+                    uint32_t hw[4];
+                    if (w < 4) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) hw[e] = w == 1 ? s0[e + 1] : (w == 2 ? s0[e + 2] : s0[e + 3]);
+                    } else if ((w & 3) == 0) {
+                        const uint4 h = *(const uint4 *)&S[li + w];
+                        hw[0] = h.x; hw[1] = h.y; hw[2] = h.z; hw[3] = h.w;
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) hw[e] = lds_u32(S, li + w + e);
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int lt = li + e;
+                        const bool in = lt >= s_lo && lt < s_hi;
+                        if (in && (int32_t)(hw[e] - s0[e]) >= T) mask[q][e] |= 1u << j;
+                    }
                 }
             }
         }
-        if (hw[e]) {
-            hs[e] = best;
-            ht[e] = t;
-            ++cnt;
-        }
     }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cnt += mask[q][e] ? 1 : 0;
+
     if (!EMIT) {
         int64_t tot;
         (void)block_exclusive_scan<int64_t>(cnt, &tot, sh64);
         if (tid == 0) counts[blockIdx.x] = (int32_t)tot;
-    } else {
-        int64_t tot;
-        int64_t pos = offsets[blockIdx.x] + block_exclusive_scan<int64_t>(cnt, &tot, sh64);
-        const int row = B.row_base + d;
+        return;
+    }
+    // hits are emitted in t order: quarter by quarter, thread by thread within a quarter.
+    // The four per-quarter counts (<= 1024 each) are scanned together in 16-bit fields.
+    uint64_t packed = 0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        uint64_t cq = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cq += mask[q][e] ? 1 : 0;
+        packed |= cq << (16 * q);
+    }
+    uint64_t ptot;
+    const uint64_t pex = block_exclusive_scan<uint64_t>(packed, &ptot, (uint64_t *)sh64);
+    const int row = B.row_base + d;
+    int64_t qbase = offsets[blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        int64_t pos = qbase + (int64_t)((pex >> (16 * q)) & 0xFFFFu);
+        qbase += (int64_t)((ptot >> (16 * q)) & 0xFFFFu);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            if (!hw[e]) continue;
+            uint32_t m = mask[q][e];
+            if (!m) continue;
+            const int li = 1024 * q + 4 * tid + e, t = t0 + li;
+            const size_t idx = (size_t)d * nseg + t / L;
+            const double mu = B.mu[idx], sigma = B.sigma[idx];
+            const uint32_t lo = S[li];
+            double best = 0.0;
+            int bw = 0, bB = 0;
+            while (m) {   // widths in ascending order; an equal S/N keeps the smaller width
+                const int j = __builtin_ctz(m);
+                m &= m - 1;
+                const int w = B.widths[j];
+                const int32_t Bw = (int32_t)(S[li + w] - lo);
+                const double sn = snr_of(Bw, w, mu, sigma);
+                if (bw == 0 || sn > best) {
+                    best = sn;
+                    bw = w;
+                    bB = Bw;
+                }
+            }
             if (pos < cap) {
                 Hit h;
                 h.row = row;
-                h.t = ht[e];
-                h.w = hw[e];
-                h.B = hB[e];
-                h.snr = hs[e];
+                h.t = t;
+                h.w = bw;
+                h.B = bB;
+                h.snr = best;
                 hits[pos] = h;
             }
             ++pos;
@@ -817,7 +892,9 @@ hipError_t launch_boxcar(bool emit, const DevBeam *beams, int beam_lo, int beam_
                          hipStream_t s) {
     const int n = chunk_hi - chunk_lo;
     if (n <= 0) return hipSuccess;
-    const size_t lds = (size_t)(kBoxTile + w_max + 1) * sizeof(uint32_t);
+    // both passes read the per-chunk counts; the emitting pass also needs offsets and hits
+    if (!counts || (emit && (!offsets || !hits))) return hipErrorInvalidValue;
+    const size_t lds = (size_t)(kBoxTile + w_max + 8) * sizeof(uint32_t);
     if (emit)
         hipLaunchKernelGGL(k_boxcar<true>, dim3(n), dim3(kThreads), lds, s, beams, beam_lo, beam_hi, chunk_lo,
                            counts, offsets, hits, cap);

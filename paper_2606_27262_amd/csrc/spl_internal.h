@@ -8,7 +8,7 @@ namespace spl {
 
 constexpr int kMaxWidths = 16;
 constexpr int kMaxStencils = 4;
-constexpr int kBoxTile = 1024;        // owned samples per boxcar workgroup
+constexpr int kBoxTile = 4096;        // owned samples per boxcar workgroup (multiple of 1024)
 constexpr int kThreads = 256;         // threads per workgroup of every kernel
 constexpr int kScanPerBlock = 4096;   // elements per block of the device-wide scan
 constexpr int kMaxWmax = 8192;
