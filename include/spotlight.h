@@ -316,6 +316,93 @@ spl_status spl_optimise_plain(const spl_candidate *cands, int64_t n, const doubl
                               int32_t n_beams, const spl_opt_params *params, spl_candidate *out,
                               int64_t capacity, int64_t *n_out);
 
+/* ------------------------------------------------------------ candidate ranker */
+/*
+ * Feature snippets and the CNN that ranks candidates (classification section of the
+ * paper: a learned classifier on the DM-time and frequency-time images of each
+ * candidate; here a small CNN of the same two inputs).
+ *
+ * Snippet of a candidate (beam b, trial d*, sample t*): two 64 x 256 BF16 planes,
+ * [n][2][64][256] row-major, columns t*-128 .. t*+127:
+ *   plane 0 (DM-time): rows d*-32 .. d*+31 of beam b's DM transform, each row
+ *     standardised with the search's own (mu, sigma) of that row's normalisation
+ *     segment containing t*;
+ *   plane 1 (frequency-time): 64 sub-bands of nch/64 adjacent channels, each the sum of
+ *     x[c][t + s[d*][c]] over its channels, standardised over its in-range samples with
+ *     the same exact-moment recipe.
+ * Entries outside [0, ndm) or outside [0, n_dd) are 0, as is every entry of a row with
+ * sigma = 0.  Value = BF16(round-to-nearest-even(float((v - mu)/sigma))), the quotient
+ * in binary64.
+ */
+#define SPL_SNIPPET_ROWS 64
+#define SPL_SNIPPET_COLS 256
+#define SPL_SNIPPET_ELEMS (2 * SPL_SNIPPET_ROWS * SPL_SNIPPET_COLS)
+
+/* Snippets of n device candidate records of the batch's last run (its blocks and DM
+ * transforms must still be resident: the workspace and the blocks given to the last
+ * spl_batch_run).  d_out: device BF16 [n][2][64][256].  Every plan of the batch needs
+ * nchans a multiple of 64 (else SPL_E_UNSUPPORTED).  A record whose beam, dm_index or
+ * t_sample lies outside the batch (t_sample >= n_out) yields two zero planes.
+ * Asynchronous on `stream`. */
+spl_status spl_ranker_snippets(const spl_batch *batch, const spl_candidate *d_cands, int64_t n, uint16_t *d_out,
+                               hipStream_t stream);
+
+/* The network: 4 x [3x3 convolution (zero padding 1) + bias -> ReLU -> 2x2 max pool]
+ * with channels 2 -> 32 -> 32 -> 32 -> 32 (64x256 -> 4x16), flatten in (channel, row,
+ * column) order -> fully connected 2048 -> 64 -> ReLU -> 64 -> 1 = logit; probability
+ * sigmoid(logit); loss = mean binary cross-entropy with logits.  Parameters, FP32, in
+ * this order: c1w [32][2][3][3], c1b [32], c2w [32][32][3][3], c2b, c3w, c3b, c4w, c4b,
+ * f1w [64][2048], f1b [64], f2w [1][64], f2b [1] (159,553 values).  Convolutions and
+ * the first fully connected layer run on BF16 matrix cores with FP32 accumulation;
+ * activations are rounded to BF16 between layers; Adam updates FP32 master weights. */
+#define SPL_RANKER_PARAMS 159553
+
+typedef struct spl_ranker spl_ranker;
+
+typedef struct spl_ranker_opts {
+    int32_t max_batch;  /* candidates per pass, 1 .. 1024 (rounded up to 32 inside)   */
+    int32_t reserved0;
+    float beta1, beta2, eps;  /* Adam; zero selects 0.9, 0.999, 1e-8                 */
+    float reserved1;
+} spl_ranker_opts;
+
+/* New ranker handle (host only; no weights yet). */
+spl_status spl_ranker_create(const spl_ranker_opts *opts, spl_ranker **out);
+
+/* Device workspace bytes (weights, Adam state, activations of max_batch candidates). */
+spl_status spl_ranker_workspace_size(const spl_ranker *r, size_t *bytes);
+
+/* Attach a caller-owned device workspace (256-byte aligned) of at least the size above;
+ * uploads the packing tables (synchronous).  Attaching again forgets the weights. */
+spl_status spl_ranker_set_workspace(spl_ranker *r, void *d_ws, size_t bytes);
+
+/* Host FP32 parameters [SPL_RANKER_PARAMS] in the order above -> device master weights;
+ * resets the Adam moments and step count.  Synchronous. */
+spl_status spl_ranker_set_weights(spl_ranker *r, const float *host_params);
+
+/* Device master weights -> host [SPL_RANKER_PARAMS] (synchronises `stream`). */
+spl_status spl_ranker_get_weights(const spl_ranker *r, float *host_params, hipStream_t stream);
+
+/* Logits of n snippets (device BF16 [n][2][64][256]) into d_logits [n] (device FP32),
+ * in passes of max_batch.  SPL_E_NO_WEIGHTS before spl_ranker_set_weights: the caller
+ * then keeps the plain path (spl_optimise_plain). */
+spl_status spl_ranker_score(spl_ranker *r, const uint16_t *d_snip, int64_t n, float *d_logits, hipStream_t stream);
+
+/* Forward and backward pass of n <= max_batch snippets with labels d_labels [n] (device
+ * FP32, 0 or 1): d_loss [1] receives the mean BCE loss and the gradients of every
+ * parameter are left in the ranker (spl_ranker_grads).  No update. */
+spl_status spl_ranker_backward(spl_ranker *r, const uint16_t *d_snip, const float *d_labels, int64_t n,
+                               float *d_loss, hipStream_t stream);
+
+/* spl_ranker_backward followed by one Adam step with learning rate lr. */
+spl_status spl_ranker_train_step(spl_ranker *r, const uint16_t *d_snip, const float *d_labels, int64_t n, float lr,
+                                 float *d_loss, hipStream_t stream);
+
+/* Device view of the last gradients, FP32 [SPL_RANKER_PARAMS] in parameter order. */
+spl_status spl_ranker_grads(const spl_ranker *r, const float **d_grads);
+
+void spl_ranker_destroy(spl_ranker *r);
+
 /* ------------------------------------------------------------- test hooks */
 /* The normaliser of the search on device, for parity tests: for i < count,
  * mu[i] = S1/n and sigma[i] = sqrt(n*S2 - S1^2)/n (exact 128-bit difference,
@@ -323,6 +410,12 @@ spl_status spl_optimise_plain(const spl_candidate *cands, int64_t n, const doubl
  * arrays n, s1, s2 (n > 0, s1 >= 0, s2 >= 0) into double device arrays. */
 spl_status spl_debug_mu_sigma(const int64_t *d_n, const int64_t *d_s1, const int64_t *d_s2, int64_t count,
                               double *d_mu, double *d_sigma, hipStream_t stream);
+
+/* The ranker's matrix-core product on device, for parity tests: C[M][N] (FP32, row
+ * stride ldc) = A[M][K] * B[N][K]^T with A, B BF16 bit patterns (row strides lda, ldb
+ * multiples of 8, 16-byte aligned), K a multiple of 32.  C is overwritten. */
+spl_status spl_debug_gemm_bf16(const uint16_t *d_a, int64_t lda, const uint16_t *d_b, int64_t ldb, float *d_c,
+                               int64_t ldc, int32_t m, int32_t n, int32_t k, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "ranker.h"
 #include "spl_internal.h"
 #include "spotlight.h"
 
@@ -237,7 +238,7 @@ struct PlanLayout {
     int quarter = 0;                 // bytes per shifted copy of the staged rows
     std::vector<int32_t> tile_base;  // [ntile_d][nch]
     std::vector<int32_t> row_bytes;  // [ntile_d]
-    size_t off_dcm = 0, off_base = 0, off_dms = 0;
+    size_t off_dcm = 0, off_base = 0, off_dms = 0, off_delays = 0;
 };
 
 struct Region {
@@ -499,6 +500,7 @@ static spl_status build_layout(spl_batch *B) {
         L.off_dcm = take((size_t)p.nch * ((p.ndm + 63) / 64 * 64) * sizeof(int32_t));
         L.off_base = take((size_t)((p.ndm + 15) / 16) * p.nch * sizeof(int32_t));
         L.off_dms = take((size_t)p.ndm * sizeof(double));
+        L.off_delays = take(p.delays.size() * sizeof(int32_t));
     }
     B->off_X.assign(nb, 0);
     B->off_S.assign(nb, 0);
@@ -612,6 +614,7 @@ static void fill_host_beams(spl_batch *B) {
         d.pitch = B->cur_pitch[b];
         d.dtab = (const int32_t *)(B->ws + L.off_dcm);
         d.tile_base = (const int32_t *)(B->ws + L.off_base);
+        d.delays = (const int32_t *)(B->ws + L.off_delays);
         d.X = (int32_t *)(B->ws + B->off_X[b]);
         d.S1 = (int64_t *)(B->ws + B->off_S[b]);
         d.S2 = d.S1 + (size_t)p.ndm * p.nseg;
@@ -658,6 +661,8 @@ static spl_status upload_tables(spl_batch *B) {
         HIP_TRY(hipMemcpy(B->ws + L.off_base, L.tile_base.data(), L.tile_base.size() * sizeof(int32_t),
                           hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(B->ws + L.off_dms, L.plan->dms.data(), L.plan->dms.size() * sizeof(double),
+                          hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(B->ws + L.off_delays, L.plan->delays.data(), L.plan->delays.size() * sizeof(int32_t),
                           hipMemcpyHostToDevice));
     }
     if (B->n_items)
@@ -1153,6 +1158,21 @@ extern "C" void spl_batch_destroy(spl_batch *B) {
 }
 
 // ------------------------------------------------------------- test hook
+extern "C" spl_status spl_ranker_snippets(const spl_batch *B, const spl_candidate *d_cands, int64_t n,
+                                          uint16_t *d_out, hipStream_t stream) {
+    if (!B) return fail(SPL_E_INVALID_ARG, "batch is NULL");
+    if (n < 0 || (n > 0 && (!d_cands || !d_out))) return fail(SPL_E_INVALID_ARG, "bad candidate or output buffer");
+    if (!B->tables_uploaded) return fail(SPL_E_INVALID_ARG, "spl_batch_set_workspace was not called");
+    for (int b = 0; b < B->nb; ++b) {
+        if (B->plans[b]->nch % SPL_SNIPPET_ROWS != 0)
+            return fail(SPL_E_UNSUPPORTED, "snippets need nchans a multiple of 64 (beam %d has %d)", b,
+                        B->plans[b]->nch);
+        if (!B->cur_x[b]) return fail(SPL_E_INVALID_ARG, "the batch has not run: no block for beam %d", b);
+    }
+    HIP_TRY(launch_snippets((const DevBeam *)(B->ws + B->off_beams), B->nb, d_cands, n, d_out, stream));
+    return SPL_OK;
+}
+
 extern "C" spl_status spl_debug_mu_sigma(const int64_t *d_n, const int64_t *d_s1, const int64_t *d_s2,
                                          int64_t count, double *d_mu, double *d_sigma, hipStream_t stream) {
     if (count < 0 || (count > 0 && (!d_n || !d_s1 || !d_s2 || !d_mu || !d_sigma)))

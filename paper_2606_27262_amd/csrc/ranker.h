@@ -1,0 +1,31 @@
+// Launchers of the ranker kernels (ranker.hip); each enqueues on stream `s`.
+#pragma once
+
+#include "spl_internal.h"
+#include "spotlight.h"
+
+namespace spl {
+
+hipError_t launch_snippets(const DevBeam *beams, int nbeams, const spl_candidate *cands, int64_t n, uint16_t *out,
+                           hipStream_t s);
+hipError_t launch_gemm(const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb, float *C, int64_t ldc, int M,
+                       int N, int K, int splits, bool accumulate, hipStream_t s);
+hipError_t launch_im2col(const uint16_t *in, int nchw, int N, int nvalid, int H, int W, int Cin, int Kp, int flip,
+                         uint16_t *out, hipStream_t s);
+hipError_t launch_transpose16(const uint16_t *in, int64_t rows, int64_t cols, int64_t ldi, uint16_t *out, int64_t ldo,
+                              hipStream_t s);
+hipError_t launch_conv_epilogue(const float *Z, const float *bias, int N, int H, int W, uint16_t *out, uint8_t *arg,
+                                hipStream_t s);
+hipError_t launch_unpool(const float *dOut, const uint8_t *arg, int N, int H, int W, uint16_t *dZ, uint16_t *dZT,
+                         int64_t ldT, float *dbias, hipStream_t s);
+hipError_t launch_head(const float *Hm, const float *b1, const float *f2w, const float *f2b, int N, int Nb,
+                       float *logits, const float *labels, float *loss, float *g_f2w, float *g_f2b, float *g_b1,
+                       uint16_t *dH, uint16_t *dHT, int64_t ldT, hipStream_t s);
+hipError_t launch_pack_idx(const float *master, const int32_t *idx, int64_t n, uint16_t *out, hipStream_t s);
+hipError_t launch_scatter_idx(const float *in, const int32_t *idx, int64_t n, float *master, hipStream_t s);
+hipError_t launch_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2, float eps,
+                       int64_t t, hipStream_t s);
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
+hipError_t launch_zero_u16(uint16_t *p, int64_t n, hipStream_t s);
+
+}  // namespace spl

@@ -1,0 +1,493 @@
+// Candidate ranker on gfx950: feature snippets of each candidate and a small CNN
+// (4 x [3x3 conv -> ReLU -> 2x2 max pool], 2 -> 32 -> 32 -> 32 -> 32 channels, then
+// 2048 -> 64 -> 1 fully connected), standing in for the paper's FETCH classifier
+// (classification section).  Every convolution and the first fully connected layer,
+// forward and backward, is a GEMM on BF16 MFMA (v_mfma_f32_16x16x32_bf16) with FP32
+// accumulation; activations are stored as BF16 (round to nearest even), weights are kept
+// in FP32 (Adam) and packed to BF16 for the GEMMs.
+//
+// Activation layout: NHWC.  Convolutions use im2col buffers [pixels][K] with
+// K = (ky*3 + kx)*Cin + ci, padded with zeros to a multiple of 32.
+#include <hip/hip_runtime.h>
+
+#include "ranker.h"
+#include "spl_device.h"
+#include "spl_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace spl {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline uint16_t f2bf(float f) {   // round to nearest even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// ----------------------------------------------------------------- snippets
+// One workgroup (256 threads, one per column) per candidate.  Plane 0: rows d*-32..d*+31
+// of the DM transform over t*-128..t*+127, each row standardised by the search's own
+// (mu, sigma) of the segment of t*.  Plane 1: 64 sub-bands of nch/64 adjacent channels
+// summed along the delays of trial d*, each standardised over its valid samples with the
+// same exact-moment recipe.  Values float((v - mu)/sigma) in binary64 -> BF16; entries
+// outside the DM range or outside [0, n_dd) are 0.
+__global__ __launch_bounds__(256) void k_snippets(const DevBeam *__restrict__ beams, int nbeams,
+                                                  const spl_candidate *__restrict__ cands, int64_t n,
+                                                  uint16_t *__restrict__ out) {
+    // 32 sub-bands at a time: 33 KB of LDS (a workgroup may address at most 64 KB)
+    __shared__ int32_t sub[32][256];
+    __shared__ double smu[32], ssg[32];
+    const int col = threadIdx.x, lane = lane_id(), wave = wave_id();
+    for (int64_t c = blockIdx.x; c < n; c += gridDim.x) {
+        const spl_candidate cd = cands[c];
+        uint16_t *o0 = out + (size_t)c * 2 * 64 * 256;
+        uint16_t *o1 = o0 + 64 * 256;
+        // a record that names no (beam, trial, owned sample) of this batch gives zero planes
+        const bool ok = cd.beam >= 0 && cd.beam < nbeams && cd.dm_index >= 0 &&
+                        cd.dm_index < beams[cd.beam < 0 || cd.beam >= nbeams ? 0 : cd.beam].ndm &&
+                        cd.t_sample >= 0 &&
+                        cd.t_sample < beams[cd.beam < 0 || cd.beam >= nbeams ? 0 : cd.beam].n_out;
+        if (!ok) {
+            for (int r = 0; r < 128; ++r) o0[r * 256 + col] = 0;
+            continue;   // uniform across the workgroup: no barrier is skipped by part of it
+        }
+        const DevBeam &B = beams[cd.beam];
+        const int ds = cd.dm_index, ts = cd.t_sample;
+        const int t = ts - 128 + col;
+        const bool valid = t >= 0 && t < B.n_dd;
+        const int seg = ts / B.L;
+        for (int r = 0; r < 64; ++r) {
+            const int d = ds - 32 + r;
+            float v = 0.f;
+            if (valid && d >= 0 && d < B.ndm) {
+                const size_t idx = (size_t)d * B.nseg + seg;
+                const double sg = B.sigma[idx];
+                if (sg > 0.0) v = (float)(((double)B.X[(size_t)d * B.xpitch + t] - B.mu[idx]) / sg);
+            }
+            o0[r * 256 + col] = f2bf(v);
+        }
+        const int per = B.nch / 64;
+        const int32_t *drow = B.delays + (size_t)ds * B.nch;
+        for (int half = 0; half < 2; ++half) {
+            for (int k = 0; k < 32; ++k) {
+                int32_t s = 0;
+                const int k0 = (32 * half + k) * per;
+                if (valid)
+                    for (int ch = k0; ch < k0 + per; ++ch) s += B.x[(size_t)ch * B.pitch + t + drow[ch]];
+                sub[k][col] = s;
+            }
+            __syncthreads();
+            // exact moments of each sub-band over the valid columns (wave w: sub-bands 8w .. 8w+7)
+            for (int k = 8 * wave; k < 8 * wave + 8; ++k) {
+                int64_t s1 = 0, s2 = 0, nv = 0;
+                for (int j = lane; j < 256; j += 64) {
+                    const int tj = ts - 128 + j;
+                    if (tj >= 0 && tj < B.n_dd) {
+                        const int64_t v = sub[k][j];
+                        s1 += v;
+                        s2 += v * v;
+                        nv += 1;
+                    }
+                }
+                s1 = wave_sum(s1);
+                s2 = wave_sum(s2);
+                nv = wave_sum(nv);
+                if (lane == 0) {
+                    double mu = 0.0, sg = 0.0;
+                    if (nv > 0) mu_sigma(nv, s1, s2, mu, sg);
+                    smu[k] = mu;
+                    ssg[k] = sg;
+                }
+            }
+            __syncthreads();
+            for (int k = 0; k < 32; ++k) {
+                float v = 0.f;
+                if (valid && ssg[k] > 0.0) v = (float)(((double)sub[k][col] - smu[k]) / ssg[k]);
+                o1[(32 * half + k) * 256 + col] = f2bf(v);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// --------------------------------------------------------------------- GEMM
+// C[M][N] (FP32, row stride ldc) = (mode 1: C +) A[M][K] * B[N][K]^T with A and B BF16,
+// K contiguous, row strides lda/ldb multiples of 8, K a multiple of 32.  Workgroup =
+// 4 wavefronts; wavefront w computes rows 64*bx + 16w .. +15 and columns 32*by .. +31
+// (two 16x16 tiles); split z of gridDim.z covers K range [z*klen, (z+1)*klen) and adds
+// atomically (mode 1).  MFMA operand lanes: lane l supplies A[l%16][8(l/16) .. +7] and
+// B^T[l%16][8(l/16) .. +7] and receives D[4(l/16) + i][l%16].
+__global__ __launch_bounds__(256) void k_gemm(const uint16_t *__restrict__ A, int64_t lda,
+                                              const uint16_t *__restrict__ Bm, int64_t ldb, float *C, int64_t ldc,
+                                              int M, int N, int K, int klen, int mode) {
+    const int lane = lane_id(), wave = wave_id();
+    const int m_base = blockIdx.x * 64 + wave * 16;
+    const int n_base = blockIdx.y * 32;
+    const int k_lo = blockIdx.z * klen, k_hi = min(K, k_lo + klen);
+    const int arow = m_base + (lane & 15), kq = 8 * (lane >> 4);
+    const int b0 = n_base + (lane & 15), b1 = b0 + 16;
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k0 = k_lo; k0 < k_hi; k0 += 32) {
+        const u16x8 a = arow < M ? *(const u16x8 *)(A + (size_t)arow * lda + k0 + kq) : zero;
+        const u16x8 x0 = b0 < N ? *(const u16x8 *)(Bm + (size_t)b0 * ldb + k0 + kq) : zero;
+        const u16x8 x1 = b1 < N ? *(const u16x8 *)(Bm + (size_t)b1 * ldb + k0 + kq) : zero;
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, x0),
+                                                       acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, x1),
+                                                       acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = m_base + 4 * (lane >> 4) + i;
+        if (m >= M) continue;
+        const int n0 = n_base + (lane & 15), n1 = n0 + 16;
+        if (n0 < N) {
+            if (mode) atomicAdd(&C[(size_t)m * ldc + n0], acc0[i]);
+            else C[(size_t)m * ldc + n0] = acc0[i];
+        }
+        if (n1 < N) {
+            if (mode) atomicAdd(&C[(size_t)m * ldc + n1], acc1[i]);
+            else C[(size_t)m * ldc + n1] = acc1[i];
+        }
+    }
+}
+
+// ------------------------------------------------------------------- im2col
+// out[p][k] for p = (n, h, w), k < Kp: k = (ky*3 + kx)*Cin + ci (zero for k >= 9*Cin); the
+// source pixel is (h + ky - 1, w + kx - 1), or (h - ky + 1, w - kx + 1) with flip (the
+// transposed convolution of the input gradient); zero outside the image.  Input NHWC,
+// or NCHW when nchw = 1; images n >= nvalid read as zero (batch padding).
+__global__ void k_im2col(const uint16_t *__restrict__ in, int nchw, int N, int nvalid, int H, int W, int Cin, int Kp,
+                         int flip, uint16_t *__restrict__ out) {
+    const int64_t P = (int64_t)N * H * W;
+    const int64_t total = P * Kp;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = i / Kp;
+        const int k = (int)(i - p * Kp);
+        uint16_t v = 0;
+        if (k < 9 * Cin) {
+            const int pos = k / Cin, ci = k - pos * Cin;
+            const int ky = pos / 3, kx = pos - ky * 3;
+            const int n = (int)(p / ((int64_t)H * W));
+            const int hw = (int)(p - (int64_t)n * H * W);
+            const int h = hw / W, w = hw - h * W;
+            const int hs = flip ? h - ky + 1 : h + ky - 1, wsrc = flip ? w - kx + 1 : w + kx - 1;
+            if (n < nvalid && hs >= 0 && hs < H && wsrc >= 0 && wsrc < W)
+                v = nchw ? in[(((size_t)n * Cin + ci) * H + hs) * W + wsrc]
+                         : in[(((size_t)n * H + hs) * W + wsrc) * Cin + ci];
+        }
+        out[i] = v;
+    }
+}
+
+// Transpose of a BF16 matrix: out[c][r] = in[r][c] (rows x cols, row strides ldi/ldo).
+__global__ void k_transpose16(const uint16_t *__restrict__ in, int64_t rows, int64_t cols, int64_t ldi,
+                              uint16_t *__restrict__ out, int64_t ldo) {
+    __shared__ uint16_t tile[32][33];
+    const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;   // rows on x (the long side)
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
+    for (int j = ty; j < 32; j += 8) {
+        const int64_t r = r0 + j, c = c0 + tx;
+        tile[j][tx] = (r < rows && c < cols) ? in[r * ldi + c] : (uint16_t)0;
+    }
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) {
+        const int64_t c = c0 + j, r = r0 + tx;
+        if (c < cols && r < rows) out[c * ldo + r] = tile[tx][j];
+    }
+}
+
+// ------------------------------------------------ conv epilogue (bias, ReLU, pool)
+// Z [N*H*W][32] FP32 -> out [N][H/2][W/2][32] BF16 = max over the 2x2 window of
+// ReLU(Z + bias); arg = window position (row-major, first maximum) of a positive maximum,
+// 255 when the pooled value is 0 (no gradient flows back).
+__global__ void k_conv_epilogue(const float *__restrict__ Z, const float *__restrict__ bias, int N, int H, int W,
+                                uint16_t *__restrict__ out, uint8_t *__restrict__ arg) {
+    const int H2 = H / 2, W2 = W / 2;
+    const int64_t total = (int64_t)N * H2 * W2 * 32;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int co = (int)(i & 31);
+        const int64_t q = i >> 5;
+        const int n = (int)(q / ((int64_t)H2 * W2));
+        const int hw = (int)(q - (int64_t)n * H2 * W2);
+        const int h2 = hw / W2, w2 = hw - h2 * W2;
+        float best = 0.f;
+        int ba = 255;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int h = 2 * h2 + (j >> 1), w = 2 * w2 + (j & 1);
+            const float z = Z[(((size_t)n * H + h) * W + w) * 32 + co] + bias[co];
+            if (z > best) {
+                best = z;
+                ba = j;
+            }
+        }
+        out[i] = f2bf(best);
+        arg[i] = (uint8_t)ba;
+    }
+}
+
+// Gradient through pool + ReLU: dZ[p][co] = dOut[pooled][co] at the window's arg position,
+// 0 elsewhere; written as BF16 [P][32] and transposed [32][ldT]; bias gradient accumulated.
+__global__ void k_unpool(const float *__restrict__ dOut, const uint8_t *__restrict__ arg, int N, int H, int W,
+                         uint16_t *__restrict__ dZ, uint16_t *__restrict__ dZT, int64_t ldT,
+                         float *__restrict__ dbias) {
+    __shared__ float sb[32];
+    if (threadIdx.x < 32) sb[threadIdx.x] = 0.f;
+    __syncthreads();
+    const int H2 = H / 2, W2 = W / 2;
+    const int64_t total = (int64_t)N * H2 * W2 * 32;
+    float part = 0.f;
+    const int co = threadIdx.x & 31;   // blockDim is a multiple of 32 and stride keeps co fixed
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = i >> 5;
+        const int n = (int)(q / ((int64_t)H2 * W2));
+        const int hw = (int)(q - (int64_t)n * H2 * W2);
+        const int h2 = hw / W2, w2 = hw - h2 * W2;
+        const int a = arg[i];
+        const float g = dOut[i];
+        if (a != 255) part += g;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int h = 2 * h2 + (j >> 1), w = 2 * w2 + (j & 1);
+            const int64_t p = ((int64_t)n * H + h) * W + w;
+            const uint16_t v = (a == j) ? f2bf(g) : (uint16_t)0;
+            dZ[p * 32 + co] = v;
+            dZT[(int64_t)co * ldT + p] = v;
+        }
+    }
+    atomicAdd(&sb[co], part);
+    __syncthreads();
+    if (threadIdx.x < 32) atomicAdd(&dbias[threadIdx.x], sb[threadIdx.x]);
+}
+
+// --------------------------------------------------- fully connected head (VALU)
+// H [Nb][64] FP32 (GEMM output), b1, f2w, f2b -> logits; with labels: mean BCE loss,
+// gradients of f2w, f2b, b1 and dH (BF16 [Nb][64] and transposed [64][ldT]).  One
+// workgroup of 256 threads; rows n >= N (batch padding) produce zero gradients.
+__global__ __launch_bounds__(256) void k_head(const float *__restrict__ Hm, const float *__restrict__ b1,
+                                              const float *__restrict__ f2w, const float *__restrict__ f2b, int N,
+                                              int Nb, float *__restrict__ logits, const float *__restrict__ labels,
+                                              float *__restrict__ loss, float *__restrict__ g_f2w,
+                                              float *__restrict__ g_f2b, float *__restrict__ g_b1,
+                                              uint16_t *__restrict__ dH, uint16_t *__restrict__ dHT, int64_t ldT) {
+    __shared__ float zl[1024];
+    __shared__ float dl[1024];
+    const int tid = threadIdx.x;
+    for (int n = tid; n < Nb; n += 256) {
+        float z = 0.f;
+        if (n < N) {
+            z = f2b[0];
+            for (int j = 0; j < 64; ++j) {
+                const float h = fmaxf(Hm[(size_t)n * 64 + j] + b1[j], 0.f);
+                z += f2w[j] * h;
+            }
+            logits[n] = z;
+        }
+        zl[n] = z;
+    }
+    if (!labels) return;
+    __syncthreads();
+    for (int n = tid; n < Nb; n += 256) {
+        float g = 0.f, l = 0.f;
+        if (n < N) {
+            const float z = zl[n], y = labels[n];
+            l = fmaxf(z, 0.f) - z * y + log1pf(expf(-fabsf(z)));
+            g = (1.f / (1.f + expf(-z)) - y) / (float)N;
+        }
+        dl[n] = g;
+        zl[n] = l;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float s = 0.f, sg = 0.f;
+        for (int n = 0; n < N; ++n) {
+            s += zl[n];
+            sg += dl[n];
+        }
+        loss[0] = s / (float)N;
+        g_f2b[0] = sg;
+    }
+    if (tid < 64) {
+        const int j = tid;
+        float gw = 0.f, gb = 0.f;
+        for (int n = 0; n < N; ++n) {
+            const float pre = Hm[(size_t)n * 64 + j] + b1[j];
+            const float h = fmaxf(pre, 0.f);
+            gw += dl[n] * h;
+            gb += pre > 0.f ? dl[n] * f2w[j] : 0.f;
+        }
+        g_f2w[j] = gw;
+        g_b1[j] = gb;
+    }
+    for (int i = tid; i < Nb * 64; i += 256) {
+        const int n = i >> 6, j = i & 63;
+        float g = 0.f;
+        if (n < N) {
+            const float pre = Hm[(size_t)n * 64 + j] + b1[j];
+            g = pre > 0.f ? dl[n] * f2w[j] : 0.f;
+        }
+        const uint16_t v = f2bf(g);
+        dH[i] = v;
+        dHT[(size_t)j * ldT + n] = v;
+    }
+}
+
+// Packed BF16 weights: out[i] = bf16(master[idx[i]]), 0 where idx[i] < 0.
+__global__ void k_pack_idx(const float *__restrict__ master, const int32_t *__restrict__ idx, int64_t n,
+                           uint16_t *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = idx[i];
+        out[i] = k >= 0 ? f2bf(master[k]) : (uint16_t)0;
+    }
+}
+
+// Gradients of packed weights back to the master layout: master[idx[i]] = in[i] (idx >= 0;
+// every master index appears at most once).
+__global__ void k_scatter_idx(const float *__restrict__ in, const int32_t *__restrict__ idx, int64_t n,
+                              float *__restrict__ master) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = idx[i];
+        if (k >= 0) master[k] = in[i];
+    }
+}
+
+__global__ void k_zero_u16(uint16_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// Adam on the FP32 master parameters (bias-corrected, step t >= 1).
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+__global__ void k_zero_f32(float *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.f;
+}
+
+// ---------------------------------------------------------------- launchers
+#define SPL_HIP_LAUNCH_CHECK() \
+    do { hipError_t e__ = hipGetLastError(); if (e__ != hipSuccess) return e__; } while (0)
+
+static unsigned grid_1d(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_snippets(const DevBeam *beams, int nbeams, const spl_candidate *cands, int64_t n, uint16_t *out,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned g = (unsigned)(n < 65536 ? n : 65536);
+    hipLaunchKernelGGL(k_snippets, dim3(g), dim3(256), 0, s, beams, nbeams, cands, n, out);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_gemm(const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb, float *C, int64_t ldc, int M,
+                       int N, int K, int splits, bool accumulate, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0 || (K & 31) || (lda & 7) || (ldb & 7)) return hipErrorInvalidValue;
+    if (splits < 1) splits = 1;
+    int klen = (K / 32 + splits - 1) / splits * 32;
+    splits = (K + klen - 1) / klen;
+    dim3 grid((M + 63) / 64, (N + 31) / 32, splits);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, klen,
+                       (accumulate || splits > 1) ? 1 : 0);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_im2col(const uint16_t *in, int nchw, int N, int nvalid, int H, int W, int Cin, int Kp, int flip,
+                         uint16_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_im2col, dim3(grid_1d((int64_t)N * H * W * Kp)), dim3(256), 0, s, in, nchw, N, nvalid, H, W,
+                       Cin, Kp, flip, out);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_transpose16(const uint16_t *in, int64_t rows, int64_t cols, int64_t ldi, uint16_t *out, int64_t ldo,
+                              hipStream_t s) {
+    if ((cols + 31) / 32 > 65535) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((rows + 31) / 32), (unsigned)((cols + 31) / 32));
+    hipLaunchKernelGGL(k_transpose16, grid, dim3(256), 0, s, in, rows, cols, ldi, out, ldo);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_conv_epilogue(const float *Z, const float *bias, int N, int H, int W, uint16_t *out, uint8_t *arg,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_conv_epilogue, dim3(grid_1d((int64_t)N * (H / 2) * (W / 2) * 32)), dim3(256), 0, s, Z, bias,
+                       N, H, W, out, arg);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_unpool(const float *dOut, const uint8_t *arg, int N, int H, int W, uint16_t *dZ, uint16_t *dZT,
+                         int64_t ldT, float *dbias, hipStream_t s) {
+    hipLaunchKernelGGL(k_unpool, dim3(grid_1d((int64_t)N * (H / 2) * (W / 2) * 32)), dim3(256), 0, s, dOut, arg, N, H,
+                       W, dZ, dZT, ldT, dbias);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_head(const float *Hm, const float *b1, const float *f2w, const float *f2b, int N, int Nb,
+                       float *logits, const float *labels, float *loss, float *g_f2w, float *g_f2b, float *g_b1,
+                       uint16_t *dH, uint16_t *dHT, int64_t ldT, hipStream_t s) {
+    if (Nb > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_head, dim3(1), dim3(256), 0, s, Hm, b1, f2w, f2b, N, Nb, logits, labels, loss, g_f2w, g_f2b,
+                       g_b1, dH, dHT, ldT);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_pack_idx(const float *master, const int32_t *idx, int64_t n, uint16_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_idx, dim3(grid_1d(n)), dim3(256), 0, s, master, idx, n, out);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_scatter_idx(const float *in, const int32_t *idx, int64_t n, float *master, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_idx, dim3(grid_1d(n)), dim3(256), 0, s, in, idx, n, master);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_zero_u16(uint16_t *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u16, dim3(grid_1d(n)), dim3(256), 0, s, p, n);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2, float eps,
+                       int64_t t, hipStream_t s) {
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3(grid_1d(n)), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps, c1, c2);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_f32, dim3(grid_1d(n)), dim3(256), 0, s, p, n);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+}  // namespace spl

@@ -22,6 +22,7 @@ struct DevBeam {
                              // channel-major [nch][ndm_pad]:
                              // ((s - b) & ~3) + (s & 3)*lds_quarter, b = tile_base & ~15
     const int32_t *tile_base;// min delay over each DM tile [ndm_tiles][nch]
+    const int32_t *delays;   // delay table in samples [ndm][nch] (snippet extraction)
     int32_t *X;              // DM transform [ndm][xpitch]
     int64_t *S1, *S2;        // [ndm][nseg]
     double *mu, *sigma;      // [ndm][nseg]

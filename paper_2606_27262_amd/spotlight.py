@@ -116,6 +116,30 @@ _sig("spl_opt_defaults", [ctypes.POINTER(_OptParams)], None)
 _sig("spl_optimise_plain", [_P, _I64, _P, _I32, ctypes.POINTER(_OptParams), _P, _I64, ctypes.POINTER(_I64)])
 
 
+class _RankerOpts(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("reserved1", ctypes.c_float)]
+
+
+_F32 = ctypes.c_float
+_sig("spl_ranker_snippets", [_P, _P, _I64, _P, _P])
+_sig("spl_ranker_create", [ctypes.POINTER(_RankerOpts), ctypes.POINTER(_P)])
+_sig("spl_ranker_workspace_size", [_P, ctypes.POINTER(_SZ)])
+_sig("spl_ranker_set_workspace", [_P, _P, _SZ])
+_sig("spl_ranker_set_weights", [_P, _P])
+_sig("spl_ranker_get_weights", [_P, _P, _P])
+_sig("spl_ranker_score", [_P, _P, _I64, _P, _P])
+_sig("spl_ranker_backward", [_P, _P, _P, _I64, _P, _P])
+_sig("spl_ranker_train_step", [_P, _P, _P, _I64, _F32, _P, _P])
+_sig("spl_ranker_grads", [_P, ctypes.POINTER(_P)])
+_sig("spl_ranker_destroy", [_P], None)
+_sig("spl_debug_gemm_bf16", [_P, _I64, _P, _I64, _P, _I64, _I32, _I32, _I32, _P])
+
+SNIPPET_ROWS, SNIPPET_COLS = 64, 256
+SNIPPET_ELEMS = 2 * SNIPPET_ROWS * SNIPPET_COLS
+RANKER_PARAMS = 159553
+
+
 def _check(st):
     if st != SPL_OK:
         raise SplError(st, _lib.spl_last_error().decode())
@@ -372,3 +396,95 @@ def upload_block(x_np, device="cuda", pitch=None):
     t = torch.zeros((nch, p), dtype=torch.uint8, device=device)
     t[:, :n] = torch.from_numpy(np.ascontiguousarray(x_np)).to(device)
     return t
+
+
+def snippets(batch: Batch, cands, n=None, out=None, stream=None):
+    """Feature snippets of device candidate records (int32 [>= n, 8]) of the batch's
+    last run -> int16 tensor [n][2][64][256] holding BF16 bit patterns."""
+    import torch
+    n = cands.shape[0] if n is None else int(n)
+    if out is None:
+        out = torch.empty((n, 2, SNIPPET_ROWS, SNIPPET_COLS), dtype=torch.int16, device=cands.device)
+    _check(_lib.spl_ranker_snippets(batch._h, ctypes.c_void_p(cands.data_ptr()), n, ctypes.c_void_p(out.data_ptr()),
+                                    _stream_handle(stream)))
+    return out
+
+
+class Ranker:
+    """CNN candidate ranker on the library's kernels; the workspace (weights, Adam
+    state, activations) is a torch allocation owned by this object."""
+
+    def __init__(self, max_batch=256, beta1=0.9, beta2=0.999, eps=1e-8, device="cuda"):
+        import torch
+        o = _RankerOpts(int(max_batch), 0, beta1, beta2, eps, 0.0)
+        h = _P()
+        _check(_lib.spl_ranker_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.max_batch = int(max_batch)
+        self.device = device
+        nb = _SZ()
+        _check(_lib.spl_ranker_workspace_size(self._h, ctypes.byref(nb)))
+        self.ws_bytes = int(nb.value)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        self._off = (-base) % 256
+        _check(_lib.spl_ranker_set_workspace(self._h, ctypes.c_void_p(base + self._off), self.ws_bytes))
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+
+    def set_weights(self, params: np.ndarray):
+        v = np.ascontiguousarray(params, np.float32).ravel()
+        assert v.size == RANKER_PARAMS
+        _check(_lib.spl_ranker_set_weights(self._h, v.ctypes.data))
+
+    def get_weights(self, stream=None) -> np.ndarray:
+        v = np.zeros(RANKER_PARAMS, np.float32)
+        _check(_lib.spl_ranker_get_weights(self._h, v.ctypes.data, _stream_handle(stream)))
+        return v
+
+    def score(self, snip, logits=None, stream=None):
+        """Logits float32 [n] of snippets int16 [n][2][64][256] (BF16 bit patterns)."""
+        import torch
+        n = snip.shape[0]
+        if logits is None:
+            logits = torch.empty(n, dtype=torch.float32, device=snip.device)
+        _check(_lib.spl_ranker_score(self._h, ctypes.c_void_p(snip.data_ptr()), n, ctypes.c_void_p(logits.data_ptr()),
+                                     _stream_handle(stream)))
+        return logits
+
+    def backward(self, snip, labels, stream=None):
+        """Loss tensor [1]; gradients stay in the ranker (grads())."""
+        _check(_lib.spl_ranker_backward(self._h, ctypes.c_void_p(snip.data_ptr()), ctypes.c_void_p(labels.data_ptr()),
+                                        snip.shape[0], ctypes.c_void_p(self.loss.data_ptr()), _stream_handle(stream)))
+        return self.loss
+
+    def train_step(self, snip, labels, lr, stream=None):
+        _check(_lib.spl_ranker_train_step(self._h, ctypes.c_void_p(snip.data_ptr()),
+                                          ctypes.c_void_p(labels.data_ptr()), snip.shape[0], float(lr),
+                                          ctypes.c_void_p(self.loss.data_ptr()), _stream_handle(stream)))
+        return self.loss
+
+    def grads(self):
+        """Device view float32 [RANKER_PARAMS] of the last gradients."""
+        import torch
+        p = _P()
+        _check(_lib.spl_ranker_grads(self._h, ctypes.byref(p)))
+        off = p.value - self.ws.data_ptr()
+        assert 0 <= off and off + RANKER_PARAMS * 4 <= self.ws.numel()
+        return self.ws[off:off + RANKER_PARAMS * 4].view(torch.float32)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.spl_ranker_destroy(self._h)
+            self._h = None
+
+
+def debug_gemm_bf16(a, b, stream=None):
+    """C = A * B^T on the ranker's matrix-core kernel (test hook): int16 CUDA tensors
+    A [M][K], B [N][K] of BF16 bit patterns (K a multiple of 32) -> float32 [M][N]."""
+    import torch
+    m, k = a.shape
+    n = b.shape[0]
+    c = torch.empty((m, n), dtype=torch.float32, device=a.device)
+    _check(_lib.spl_debug_gemm_bf16(ctypes.c_void_p(a.data_ptr()), a.stride(0), ctypes.c_void_p(b.data_ptr()),
+                                    b.stride(0), ctypes.c_void_p(c.data_ptr()), n, m, n, k, _stream_handle(stream)))
+    return c

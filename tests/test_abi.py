@@ -150,3 +150,29 @@ def test_plain_path_library_equals_oracle(n_beams):
         got = spl.optimise_plain(c2, ts, n_beams)
         assert np.array_equal(got, ref)
         assert not np.any((got["t_sample"] >= 9000) & (got["t_sample"] < 9006))
+
+
+def test_ranker_handle_validation():
+    """Host-only paths of the ranker ABI: option checks and workspace sizing."""
+    lib = ctypes.CDLL(spl.LIB_PATH)
+    h = ctypes.c_void_p()
+    bad = spl._RankerOpts(2000, 0, 0.9, 0.999, 1e-8, 0.0)
+    assert lib.spl_ranker_create(ctypes.byref(bad), ctypes.byref(h)) == spl.SPL_E_INVALID_ARG
+    bad = spl._RankerOpts(32, 0, 1.5, 0.999, 1e-8, 0.0)
+    assert lib.spl_ranker_create(ctypes.byref(bad), ctypes.byref(h)) == spl.SPL_E_INVALID_ARG
+    sizes = []
+    for mb in (1, 32, 33, 64):
+        o = spl._RankerOpts(mb, 0, 0.0, 0.0, 0.0, 0.0)
+        assert spl._lib.spl_ranker_create(ctypes.byref(o), ctypes.byref(h)) == spl.SPL_OK
+        n = ctypes.c_size_t()
+        assert spl._lib.spl_ranker_workspace_size(h, ctypes.byref(n)) == spl.SPL_OK
+        sizes.append(n.value)
+        # no workspace: every device call is refused before touching the GPU
+        assert spl._lib.spl_ranker_score(h, None, 0, None, None) == spl.SPL_E_INVALID_ARG
+        spl._lib.spl_ranker_destroy(h)
+    # batches are padded to 32 candidates
+    assert sizes[0] == sizes[1] and sizes[2] == sizes[3] and sizes[2] > sizes[1]
+    assert sizes[1] % 256 == 0
+    # about 14.3 MB of activations per candidate plus weights, moments and tables
+    per = (sizes[2] - sizes[1]) / 32
+    assert 13e6 < per < 16e6, per

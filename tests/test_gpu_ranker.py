@@ -1,0 +1,229 @@
+"""GPU parity of the ranker path through the C ABI.
+
+* The matrix-core product against numpy on BF16-representable operands (pins the
+  operand and result lane layout of the MFMA instruction the kernel uses).
+* Snippets bit for bit against the oracle (same binary64 recipe, same BF16 rounding).
+* The CNN's logits, loss and every parameter gradient against the float64 oracle
+  network: BF16 activations and weights allow cosine > 0.999 and relative L2 error
+  < 2e-2 per tensor.
+* Adam against its definition applied to the GPU's own gradients.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cnn
+from paper_2606_27262_amd import synth
+from paper_2606_27262_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_27262_amd import spotlight
+    return spotlight
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def bf16_bits(a):
+    return oracle.f32_to_bf16_bits(np.asarray(a, np.float32))
+
+
+def bf16_vals(bits):
+    return oracle.bf16_bits_to_f32(bits).astype(np.float64)
+
+
+@pytest.mark.parametrize("m,n,k,lda_pad", [(16, 16, 32, 0), (80, 48, 96, 0), (130, 33, 64, 8), (64, 64, 2048, 0)])
+def test_gemm_matches_numpy(spl, m, n, k, lda_pad):
+    say(f"gemm m={m} n={n} k={k} pad={lda_pad}")
+    rng = np.random.default_rng(m * 1000 + n + k)
+    a = bf16_bits(rng.normal(size=(m, k + lda_pad)))
+    b = bf16_bits(rng.normal(size=(n, k)))
+    ta = torch.from_numpy(a.view(np.int16)).cuda()
+    tb = torch.from_numpy(b.view(np.int16)).cuda()
+    c = spl.debug_gemm_bf16(ta[:, :k], tb)
+    torch.cuda.synchronize()
+    got = c.cpu().numpy().astype(np.float64)
+    av, bv = bf16_vals(a)[:, :k], bf16_vals(b)
+    ref = av @ bv.T
+    # BF16 products are exact in FP32; k FP32 additions err by at most k * 2^-24 each of
+    # the magnitude sum.  A lane-layout mistake gives errors of order the sum itself.
+    bound = k * 2.0 ** -23 * (np.abs(av) @ np.abs(bv).T) + 1e-30
+    assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
+
+
+def _search_small(spl, seed=3):
+    nch, n_out, L = 128, 700, 256
+    plan_d = {"nchans": nch, "fch1": 499.609375, "foff": -1.5625, "tsamp": 1.31072e-3, "n_out": n_out,
+              "dm_ranges": [(0.0, 2.0, 70)], "widths": (1, 2, 4, 8), "threshold": 4.0, "norm_window": L}
+    plan = spl.Plan.from_dict(plan_d)
+    info = plan.info
+    pulses = [synth.Pulse(t0=300.0, dm=60.0, fwhm=3.0, snr=25.0), synth.Pulse(t0=20.0, dm=4.0, fwhm=2.0, snr=15.0)]
+    spec = W.block_spec(plan_d, info["n_in"], pulses)
+    x = synth.make_block(spec, seed, 0, plan_d["widths"])[:, :info["n_in"]]
+    batch = spl.Batch([plan])
+    xb = spl.upload_block(x)
+    cands = spl.new_candidates(1 << 14)
+    cands, stats = batch.run([xb], cands)
+    torch.cuda.synchronize()
+    got = spl.candidates_to_numpy(cands, stats)
+    X = batch.dm_transform(0)[:, :info["n_dd"]].cpu().numpy().astype(np.int64)
+    return plan, info, x, X, batch, cands, got
+
+
+def test_snippets_bit_exact(spl):
+    plan, info, x, X, batch, cands, got = _search_small(spl)
+    say(f"snippets: {got.size} candidates")
+    assert got.size >= 3
+    D = plan.delays().astype(np.int64)
+    # append edge records: corners of the plane, and records naming nothing in the batch
+    extra = np.zeros(6, oracle.CAND_DTYPE)
+    ndm, n_out = info["ndm"], info["n_out"]
+    extra["dm_index"] = [0, ndm - 1, 5, ndm - 1, 0, 0]
+    extra["t_sample"] = [0, n_out - 1, 3, 0, n_out, 10]
+    extra["beam"] = [0, 0, 0, 0, 0, 1]
+    recs = np.concatenate([got, extra])
+    dev = torch.from_numpy(recs.view(np.int32).reshape(-1, 8).copy()).cuda()
+    out = spl.snippets(batch, dev)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy().view(np.uint16)
+    for i, r in enumerate(recs):
+        valid = r["beam"] == 0 and 0 <= r["t_sample"] < n_out
+        if valid:
+            ref = oracle.snippets(x, D, X, n_out, info["norm_window"], int(r["dm_index"]), int(r["t_sample"]))
+        else:
+            ref = np.zeros((2, 64, 256), np.uint16)
+        assert np.array_equal(g[i], ref), (i, r)
+
+
+def _random_params(seed):
+    p = cnn.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    for k in p:
+        if k.endswith("b"):
+            p[k] = rng.normal(0, 0.05, p[k].shape)
+    return p
+
+
+def _random_snippets(rng, n):
+    x = rng.normal(0, 1, size=(n, 2, 64, 256)).astype(np.float32)
+    bits = bf16_bits(x)
+    return bits, bf16_vals(bits)
+
+
+def _rel(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30), \
+        float(a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30))
+
+
+@pytest.mark.parametrize("n,max_batch", [(5, 32), (40, 64)])
+def test_ranker_forward_backward_vs_oracle(spl, n, max_batch):
+    say(f"ranker fwd/bwd n={n} max_batch={max_batch}")
+    rng = np.random.default_rng(n)
+    p = _random_params(n)
+    bits, xv = _random_snippets(rng, n)
+    y = (rng.random(n) < 0.5).astype(np.float64)
+    r = spl.Ranker(max_batch=max_batch)
+    r.set_weights(cnn.flatten_params(p).astype(np.float32))
+    snip = torch.from_numpy(bits.view(np.int16)).cuda()
+    logits = r.score(snip)
+    lab = torch.from_numpy(y.astype(np.float32)).cuda()
+    loss = r.backward(snip, lab)
+    torch.cuda.synchronize()
+    gl = logits.cpu().numpy().astype(np.float64)
+    gloss = float(loss.item())
+    grads = cnn.unflatten_params(r.grads().cpu().numpy().astype(np.float64))
+    p32 = cnn.unflatten_params(cnn.flatten_params(p).astype(np.float32).astype(np.float64))
+    ref_logit, cache = cnn.forward(p32, xv)
+    ref_loss, ref_g = cnn.backward(p32, cache, y)
+    e, cos = _rel(gl, ref_logit)
+    say(f"  logits rel {e:.3e} cos {cos:.6f}; loss {gloss:.6f} vs {ref_loss:.6f}")
+    assert e < 2e-2 and cos > 0.999
+    assert abs(gloss - ref_loss) <= 2e-2 * max(1.0, abs(ref_loss))
+    for k in cnn.PARAM_ORDER:
+        e, cos = _rel(grads[k], ref_g[k])
+        say(f"  {k}: rel {e:.3e} cos {cos:.6f}")
+        assert e < 2e-2 and cos > 0.999, k
+
+
+def test_score_in_passes_equals_single_pass(spl):
+    rng = np.random.default_rng(7)
+    p = _random_params(7)
+    bits, _ = _random_snippets(rng, 70)
+    snip = torch.from_numpy(bits.view(np.int16)).cuda()
+    r32 = spl.Ranker(max_batch=32)
+    r32.set_weights(cnn.flatten_params(p).astype(np.float32))
+    r96 = spl.Ranker(max_batch=96)
+    r96.set_weights(cnn.flatten_params(p).astype(np.float32))
+    a = r32.score(snip)
+    b = r96.score(snip)
+    torch.cuda.synchronize()
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    # the same images through the same kernels: only the split-K summation order may differ
+    assert np.allclose(a, b, rtol=1e-4, atol=1e-4)
+
+
+def test_no_weights_is_reported(spl):
+    r = spl.Ranker(max_batch=32)
+    snip = torch.zeros((1, 2, 64, 256), dtype=torch.int16, device="cuda")
+    with pytest.raises(spl.SplError) as ei:
+        r.score(snip)
+    assert ei.value.status == spl.SPL_E_NO_WEIGHTS
+
+
+def test_adam_step_matches_definition(spl):
+    rng = np.random.default_rng(11)
+    p = _random_params(11)
+    w0 = cnn.flatten_params(p).astype(np.float32)
+    bits, _ = _random_snippets(rng, 16)
+    y = (rng.random(16) < 0.5).astype(np.float32)
+    r = spl.Ranker(max_batch=32, beta1=0.9, beta2=0.999, eps=1e-8)
+    r.set_weights(w0)
+    snip = torch.from_numpy(bits.view(np.int16)).cuda()
+    lab = torch.from_numpy(y).cuda()
+    r.backward(snip, lab)
+    g = r.grads().cpu().numpy().astype(np.float64)
+    r.set_weights(w0)   # resets the moments
+    lr = 1e-3
+    r.train_step(snip, lab, lr)
+    w1 = r.get_weights().astype(np.float64)
+    m = 0.1 * g
+    v = 0.001 * g * g
+    ref = w0 - lr * (m / 0.1) / (np.sqrt(v / 0.001) + 1e-8)
+    # gradients of the two passes agree up to the split-K summation order
+    assert np.allclose(w1, ref, rtol=1e-5, atol=2e-6 * lr + 1e-7)
+
+
+def test_training_reduces_loss(spl):
+    """Separable toy task: positives carry a bright diagonal stripe in the DM-time plane."""
+    rng = np.random.default_rng(5)
+    n = 64
+    x = rng.normal(0, 1, size=(n, 2, 64, 256)).astype(np.float32)
+    y = np.zeros(n, np.float32)
+    y[: n // 2] = 1
+    for i in range(n // 2):
+        t0 = rng.integers(40, 200)
+        for r_ in range(64):
+            x[i, 0, r_, t0 + (r_ - 32) // 4: t0 + (r_ - 32) // 4 + 3] += 3.0
+    snip = torch.from_numpy(bf16_bits(x).view(np.int16)).cuda()
+    lab = torch.from_numpy(y).cuda()
+    r = spl.Ranker(max_batch=64)
+    r.set_weights(cnn.flatten_params(cnn.init_params(1)).astype(np.float32))
+    losses = []
+    for it in range(30):
+        losses.append(float(r.train_step(snip, lab, 1e-3).item()))
+    say(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.5 * losses[0]
+    pr = torch.sigmoid(r.score(snip)).cpu().numpy()
+    assert np.mean((pr >= 0.5) == (y == 1)) > 0.95
