@@ -5,9 +5,10 @@ boxcar search, peak filters, candidate compaction) over one block of every beam
 of the workload, with the blocks already resident in HBM.  Prints one JSON line.
 
 Workloads (synthetic stand-ins for uGMRT beam data, seeded):
+  c3  24 beams of the c2 shape (one GPU's share of 2000 beams over 90 GPUs), persistent
+      launch captured in a hipGraph, 10 injected pulses per beam       (default)
   c2  1 beam, 4096 ch 550-750 MHz, 16384 samples at 1.31072 ms, 2048 DM trials 0-2000,
-      widths 1..256, 20 injected pulses, 2% RFI channels            (default)
-  c3  24 beams of the c2 shape, persistent launch captured in a hipGraph
+      widths 1..256, 20 injected pulses, 2% RFI channels
   c4  32 beams alternating 2048 ch 300-500 MHz / 0.65536 ms / 32768 samples / 1024
       trials 0-1000 and 4096 ch 550-750 MHz / 1.31072 ms / 16384 samples / 3072 trials
       0-3000, zero-DM RFI bursts, persistent launch in a hipGraph
@@ -47,23 +48,24 @@ def make_workload(name, spl, W):
         if key not in cache:
             cache[key] = spl.Plan.from_dict(pd)
         plans.append(cache[key])
-    blocks = []
+    blocks, pulses = [], []
     seed = {"c1": 1, "c2": 2, "c3": 3, "c4": 4}[name]
     for b, (pd, p) in enumerate(zip(pds, plans)):
         n_in = p.info["n_in"]
         if name == "c1":
-            _, x = W.c1_block(n_in, seed=seed)
+            spec, x = W.c1_block(n_in, seed=seed)
         elif name == "c2":
-            _, x = W.c2_like_block(pd, n_in, seed, b, 20)
+            spec, x = W.c2_like_block(pd, n_in, seed, b, 20)
         elif name == "c3":
-            _, x = W.c2_like_block(pd, n_in, seed, b, 10)
+            spec, x = W.c2_like_block(pd, n_in, seed, b, 10)
         else:
-            _, x = W.c2_like_block(pd, n_in, seed, b, 10, dm_max_pulse=0.9 * W.dm_max(pd), zero_dm_rate=0.2)
+            spec, x = W.c2_like_block(pd, n_in, seed, b, 10, dm_max_pulse=0.9 * W.dm_max(pd), zero_dm_rate=0.2)
         blocks.append(spl.upload_block(x[:, :n_in]))
+        pulses.append(list(spec.pulses))
         del x
         if b % 8 == 7:
             log(f"generated {b + 1}/{len(pds)} blocks")
-    return pds, plans, blocks
+    return pds, plans, blocks, pulses
 
 
 def cpu_baseline(pd, plan, W, target_s=12.0):
@@ -94,18 +96,116 @@ def cpu_baseline(pd, plan, W, target_s=12.0):
                       f"{i['nchans']}-channel block: dedispersion + boxcar search + peak filters"}
 
 
+def per_beam_comparison(spl, plans, blocks, args, cands, stats):
+    """The same blocks searched beam by beam (plain mode: one launch sequence per beam),
+    for the comparison of the batched form with the per-beam pipeline."""
+    import torch
+    b2 = spl.Batch(plans, mode=spl.MODE_PLAIN_PER_BEAM)
+    b2.attach()
+    if not args.no_autotune:
+        import tempfile
+        b2.autotune(blocks, cache_path=args.tile_cache or os.path.join(tempfile.gettempdir(), "spotlight_tiles.txt"))
+    steps = max(2, args.steps // 4)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b2.run(blocks, cands, stats, stream=s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        for _ in range(steps):
+            b2.run(blocks, cands, stats, stream=s)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    del b2
+    return {"ms_per_step": ms, "steps": steps}
+
+
+def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, args, ms_step, block_s):
+    """Candidate stage on the last run's candidates: the plain optimisation path (host)
+    against the ranker path (optimisation without the S/N cut, then the CNN on device),
+    recall and false alarms on the injected pulses; then the CNN's own throughput in
+    training and inference on batches of 256 snippets."""
+    import numpy as np
+    import torch
+
+    from paper_2606_27262_amd import ranking
+
+    nb = len(plans)
+    with torch.cuda.stream(stream):
+        batch.run(blocks, cands, stats, stream=stream)
+    torch.cuda.synchronize()
+    recs = spl.candidates_to_numpy(cands, stats)
+    tsamp = np.array([pd["tsamp"] for pd in pds], np.float64)
+    ranker = spl.Ranker(max_batch=256)
+    trained = os.path.exists(args.ranker_weights)
+    ranker.set_weights(np.load(args.ranker_weights) if trained else ranking.initial_weights(0))
+    t0 = time.perf_counter()
+    fp = spl.optimise_plain(recs, tsamp, nb)
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    surv = spl.optimise_plain(recs, tsamp, nb, snr_min=0.0)
+    kept, n_scored = surv, 0
+    if surv.size:
+        dev = torch.from_numpy(surv.view(np.int32).reshape(-1, 8).copy()).cuda()
+        lg = ranker.score(spl.snippets(batch, dev)).cpu().numpy()
+        kept, n_scored = surv[lg >= 0], surv.size
+    t_rank = time.perf_counter() - t0
+    pr = ranking.recall_and_false_alarms(fp, pulses, pds)
+    rr = ranking.recall_and_false_alarms(kept, pulses, pds)
+
+    # throughput of the network itself
+    rng = np.random.default_rng(0)
+    n = 256
+    x = torch.from_numpy(rng.normal(0, 1, size=(n, 2, 64, 256)).astype(np.float32)).cuda()
+    snip = (x.view(torch.int32) >> 16).to(torch.int16)   # truncated BF16 patterns are enough here
+    lab = torch.from_numpy((rng.random(n) < 0.5).astype(np.float32)).cuda()
+    probe = spl.Ranker(max_batch=n)
+    probe.set_weights(ranking.initial_weights(1))
+    flop_fwd = 2.0 * (9 * (2 * 32 * 64 * 256 + 32 * 32 * (32 * 128 + 16 * 64 + 8 * 32))) + 2.0 * (2048 * 64 + 64)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    t_inf = timed(lambda: probe.score(snip), 10)
+    t_trn = timed(lambda: probe.train_step(snip, lab, 1e-4), 10)
+    del probe
+    return {
+        "weights": "trained" if trained else "untrained (initial weights)",
+        "plain_path": {**pr, "host_ms": t_plain * 1e3},
+        "ranker_path": {**rr, "scored": int(n_scored), "stage_ms": t_rank * 1e3},
+        "real_time_beams_per_gpu_with_ranker": nb / ((ms_step + t_rank * 1e3) / 1e3 / block_s),
+        "cnn": {"batch": n, "flop_forward_per_candidate": flop_fwd,
+                "inference_ms": t_inf * 1e3, "inference_candidates_per_s": n / t_inf,
+                "inference_tflops": n * flop_fwd / t_inf / 1e12,
+                "train_step_ms": t_trn * 1e3, "train_candidates_per_s": n / t_trn,
+                "train_tflops": 3 * n * flop_fwd / t_trn / 1e12,
+                "mfma_peak_tflops_bf16": 2500.0},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--mode", default="auto", choices=["auto", "plain", "graph"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default dedispersion tiles")
     ap.add_argument("--tile-cache", default=None, help="autotuner cache file (default: a file in $TMPDIR)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (calibrates HBM byte counters)")
+    ap.add_argument("--no-ranker", action="store_true", help="skip the candidate-ranker leg")
+    ap.add_argument("--no-per-beam", action="store_true",
+                    help="skip the comparison run of a multi-beam workload in plain per-beam mode")
+    ap.add_argument("--ranker-weights", default=os.path.join(ROOT, "paper_2606_27262_amd", "data",
+                                                             "ranker_weights.npy"))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs each GPU's share of beams "
@@ -126,7 +226,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    pds, plans, blocks = make_workload(args.workload, spl, W)
+    pds, plans, blocks, pulses = make_workload(args.workload, spl, W)
     nb = len(plans)
     mode = args.mode
     if mode == "auto":
@@ -209,6 +309,13 @@ def main():
                      "traffic": None, "launch_ms": avg_launch_s * 1e3,
                      "adds_per_launch": adds_per_launch},
     }
+    if nb > 1 and not args.no_per_beam and mode == "graph":
+        out["plain_per_beam"] = per_beam_comparison(spl, plans, blocks, args, cands, stats)
+        out["plain_per_beam"]["real_time_beams_per_gpu"] = nb / (out["plain_per_beam"]["ms_per_step"] / 1e3 / block_s)
+    if not args.no_ranker and all(pd["nchans"] % 64 == 0 for pd in pds):
+        log("ranker leg")
+        out["ranker"] = ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, args, ms_step,
+                                   block_s)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(pds[0], plans[0], W)

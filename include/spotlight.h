@@ -316,6 +316,20 @@ spl_status spl_optimise_plain(const spl_candidate *cands, int64_t n, const doubl
                               int32_t n_beams, const spl_opt_params *params, spl_candidate *out,
                               int64_t capacity, int64_t *n_out);
 
+/* ------------------------------------------------------------------ corner turn */
+/*
+ * Filterbank files hold one spectrum after another (time-major: all channels of
+ * sample 0, then of sample 1, ...; the paper's beams arrive this way, the
+ * observation-overview section), while the search reads one row of samples per
+ * channel.  out[c][t] = in[t][c] for t < n_t, c < nch: d_in device [n_t][in_stride]
+ * bytes, d_out device [nch][pitch] bytes; bytes t >= n_t of each output row are left
+ * unchanged.  nch a multiple of 16 (else SPL_E_UNSUPPORTED); in_stride >= nch and
+ * pitch >= n_t, both multiples of 16; both buffers 16-byte aligned and not
+ * overlapping.  Channel order is kept.  Asynchronous on `stream`.
+ */
+spl_status spl_corner_turn(const uint8_t *d_in, int64_t n_t, int32_t nch, int64_t in_stride, uint8_t *d_out,
+                           int64_t pitch, hipStream_t stream);
+
 /* ------------------------------------------------------------ candidate ranker */
 /*
  * Feature snippets and the CNN that ranks candidates (classification section of the

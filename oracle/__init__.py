@@ -111,6 +111,17 @@ def sizes(delays: np.ndarray, n_out: int, widths) -> dict:
 # --------------------------------------------------------------------------
 # Search stages
 # --------------------------------------------------------------------------
+def corner_turn(x_tc: np.ndarray) -> np.ndarray:
+    """Channel-major copy of a time-major block: out[c][t] = x_tc[t][c] (the search
+    reads one row per channel; filterbank data arrive one spectrum per sample)."""
+    x_tc = np.asarray(x_tc, dtype=np.uint8)
+    n_t, nch = x_tc.shape
+    out = np.empty((nch, n_t), dtype=np.uint8)
+    for c in range(nch):
+        out[c, :] = x_tc[:, c]
+    return out
+
+
 def dedisperse(x: np.ndarray, delays: np.ndarray, n_dd: int) -> np.ndarray:
     """X[d][t] = sum_c x[c][t + delay[d][c]], t < n_dd (int64)."""
     x = np.ascontiguousarray(x, dtype=np.uint8)

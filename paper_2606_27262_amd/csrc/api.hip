@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "corner_turn.h"
 #include "kernels.h"
 #include "ranker.h"
 #include "spl_internal.h"
@@ -1158,6 +1159,22 @@ extern "C" void spl_batch_destroy(spl_batch *B) {
 }
 
 // ------------------------------------------------------------- test hook
+extern "C" spl_status spl_corner_turn(const uint8_t *d_in, int64_t n_t, int32_t nch, int64_t in_stride,
+                                      uint8_t *d_out, int64_t pitch, hipStream_t stream) {
+    if (n_t < 0 || nch < 1) return fail(SPL_E_INVALID_ARG, "spl_corner_turn: need n_t >= 0 and nch >= 1");
+    if (n_t == 0) return SPL_OK;
+    if (!d_in || !d_out) return fail(SPL_E_INVALID_ARG, "spl_corner_turn: NULL buffer");
+    if (nch % 16 != 0) return fail(SPL_E_UNSUPPORTED, "spl_corner_turn: nch must be a multiple of 16 (got %d)", nch);
+    if (in_stride < nch || in_stride % 16 != 0)
+        return fail(SPL_E_INVALID_ARG, "spl_corner_turn: in_stride must be a multiple of 16 and >= nch");
+    if (pitch < n_t || pitch % 16 != 0)
+        return fail(SPL_E_INVALID_ARG, "spl_corner_turn: pitch must be a multiple of 16 and >= n_t");
+    if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 15))
+        return fail(SPL_E_INVALID_ARG, "spl_corner_turn: buffers must be 16-byte aligned");
+    HIP_TRY(launch_corner_turn(d_in, in_stride, n_t, nch, d_out, pitch, stream));
+    return SPL_OK;
+}
+
 extern "C" spl_status spl_ranker_snippets(const spl_batch *B, const spl_candidate *d_cands, int64_t n,
                                           uint16_t *d_out, hipStream_t stream) {
     if (!B) return fail(SPL_E_INVALID_ARG, "batch is NULL");

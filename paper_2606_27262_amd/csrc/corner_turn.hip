@@ -1,0 +1,78 @@
+// Corner turn of a filterbank block: time-major samples [n_t][nch] (the SIGPROC order,
+// one byte per sample) to the channel-major rows [nch][pitch] the dedispersion reads.
+// Pure data movement, bound by HBM: each byte is read once and written once.
+//
+// A workgroup moves a tile of 64 samples x 256 channels through the LDS: 16-byte global
+// loads along channels, then each thread gathers 16 consecutive samples of one channel
+// and writes them with one 16-byte store; four neighbouring threads cover a row's 64
+// samples, so every output row segment is written in full 64-byte pieces.  The LDS row
+// stride of 260 bytes (65 dwords) puts the four 16-sample groups of a wave's gather on
+// distinct banks.
+#include <hip/hip_runtime.h>
+
+#include "corner_turn.h"
+
+namespace spl {
+
+namespace {
+constexpr int kTT = 64;       // samples per tile
+constexpr int kTC = 256;      // channels per tile
+constexpr int kStride = 260;  // LDS bytes per sample row of the tile
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_corner_turn(const uint8_t *__restrict__ in, int64_t in_stride, int64_t n_t,
+                                                     int nch, uint8_t *__restrict__ out, int64_t pitch) {
+    __shared__ __align__(16) uint8_t tile[kTT * kStride];
+    const int tid = threadIdx.x;
+    const int64_t t0 = (int64_t)blockIdx.x * kTT;
+    const int c0 = blockIdx.y * kTC;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int idx = q * 256 + tid;
+        const int r = idx >> 4, c16 = (idx & 15) * 16;
+        const int64_t t = t0 + r;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (t < n_t && c0 + c16 < nch) v = *(const u32x4 *)(in + t * in_stride + c0 + c16);
+        uint32_t *d = (uint32_t *)(tile + r * kStride + c16);
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int idx = q * 256 + tid;
+        const int part = idx & 3, c = idx >> 2;
+        if (c0 + c >= nch) continue;
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint8_t *s = tile + (part * 16 + 4 * k) * kStride + c;
+            w[k] = (uint32_t)s[0] | ((uint32_t)s[kStride] << 8) | ((uint32_t)s[2 * kStride] << 16) |
+                   ((uint32_t)s[3 * kStride] << 24);
+        }
+        const int64_t t = t0 + part * 16;
+        uint8_t *dst = out + (int64_t)(c0 + c) * pitch + t;
+        if (t + 16 <= n_t) {
+            const u32x4 v = {w[0], w[1], w[2], w[3]};
+            *(u32x4 *)dst = v;
+        } else {
+            for (int j = 0; t + j < n_t; ++j) dst[j] = (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
+        }
+    }
+}
+
+hipError_t launch_corner_turn(const uint8_t *in, int64_t in_stride, int64_t n_t, int nch, uint8_t *out, int64_t pitch,
+                              hipStream_t s) {
+    if (n_t <= 0 || nch <= 0) return hipSuccess;
+    const int64_t gx = (n_t + kTT - 1) / kTT;
+    const int gy = (nch + kTC - 1) / kTC;
+    if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_corner_turn, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, in, in_stride, n_t, nch, out,
+                       pitch);
+    return hipGetLastError();
+}
+
+}  // namespace spl

@@ -122,6 +122,7 @@ class _RankerOpts(ctypes.Structure):
 
 
 _F32 = ctypes.c_float
+_sig("spl_corner_turn", [_P, _I64, _I32, _I64, _P, _I64, _P])
 _sig("spl_ranker_snippets", [_P, _P, _I64, _P, _P])
 _sig("spl_ranker_create", [ctypes.POINTER(_RankerOpts), ctypes.POINTER(_P)])
 _sig("spl_ranker_workspace_size", [_P, ctypes.POINTER(_SZ)])
@@ -396,6 +397,20 @@ def upload_block(x_np, device="cuda", pitch=None):
     t = torch.zeros((nch, p), dtype=torch.uint8, device=device)
     t[:, :n] = torch.from_numpy(np.ascontiguousarray(x_np)).to(device)
     return t
+
+
+def corner_turn(x_tc, out=None, pitch=None, stream=None):
+    """Time-major uint8 CUDA tensor [n_t][nch] (row stride a multiple of 16) ->
+    channel-major [nch][pitch] (pitch a multiple of 256 by default)."""
+    import torch
+    n_t, nch = x_tc.shape
+    assert x_tc.dtype == torch.uint8 and x_tc.stride(1) == 1
+    if out is None:
+        p = pitch or (n_t + 255) // 256 * 256
+        out = torch.empty((nch, p), dtype=torch.uint8, device=x_tc.device)
+    _check(_lib.spl_corner_turn(ctypes.c_void_p(x_tc.data_ptr()), n_t, nch, x_tc.stride(0),
+                                ctypes.c_void_p(out.data_ptr()), out.stride(0), _stream_handle(stream)))
+    return out
 
 
 def snippets(batch: Batch, cands, n=None, out=None, stream=None):

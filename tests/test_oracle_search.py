@@ -268,3 +268,18 @@ def test_nms_matches_brute_force_with_ties():
         for i in range(sd.size):
             for j in range(i + 1, sd.size):
                 assert abs(int(sd[i]) - int(sd[j])) > 5 or abs(int(st[i]) - int(st[j])) > 5
+
+
+def test_corner_turn_small_worked_example():
+    """Two spectra of three channels: the rows of the output are the channels."""
+    x_tc = np.array([[1, 2, 3], [4, 5, 6]], np.uint8)
+    assert oracle.corner_turn(x_tc).tolist() == [[1, 4], [2, 5], [3, 6]]
+
+
+def test_corner_turn_feeds_the_dm0_sum():
+    """The DM-0 row of the channel-major block equals the per-spectrum channel sum."""
+    rng = np.random.default_rng(3)
+    x_tc = rng.integers(0, 256, size=(50, 16), dtype=np.uint8)
+    x = oracle.corner_turn(x_tc)
+    X = oracle.dedisperse(x, np.zeros((1, 16), np.int64), 50)
+    assert np.array_equal(X[0], x_tc.astype(np.int64).sum(axis=1))
