@@ -122,7 +122,8 @@ def per_beam_comparison(spl, plans, blocks, args, cands, stats):
 
 def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, args, ms_step, block_s):
     """Candidate stage on the last run's candidates: the plain optimisation path (host)
-    against the ranker path (optimisation without the S/N cut, then the CNN on device),
+    against the ranker path (optimisation with the CNN in place of the density test and
+    the S/N cut, the CNN on device),
     recall and false alarms on the injected pulses; then the CNN's own throughput in
     training and inference on batches of 256 snippets."""
     import numpy as np
@@ -143,7 +144,7 @@ def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, arg
     fp = spl.optimise_plain(recs, tsamp, nb)
     t_plain = time.perf_counter() - t0
     t0 = time.perf_counter()
-    surv = spl.optimise_plain(recs, tsamp, nb, snr_min=0.0)
+    surv = spl.optimise_plain(recs, tsamp, nb, **ranking.RANKER_OPT)
     kept, n_scored = surv, 0
     if surv.size:
         dev = torch.from_numpy(surv.view(np.int32).reshape(-1, 8).copy()).cuda()

@@ -425,6 +425,13 @@ void spl_ranker_destroy(spl_ranker *r);
 spl_status spl_debug_mu_sigma(const int64_t *d_n, const int64_t *d_s1, const int64_t *d_s2, int64_t count,
                               double *d_mu, double *d_sigma, hipStream_t stream);
 
+/* Device view of the max-pool decisions of conv layer `layer` (0..3) of the ranker's
+ * last pass, for parity tests: bytes [Nb][H/2][W/2][32] (Nb = max_batch rounded up to
+ * 32; H x W the layer's input size: 64x256, 32x128, 16x64, 8x32), each the window
+ * position (row-major 0..3) of the first maximum of ReLU(conv + bias), or 255 when that
+ * maximum is 0 (no gradient flows through the window). */
+spl_status spl_ranker_debug_pool_args(const spl_ranker *r, int32_t layer, const uint8_t **d_arg);
+
 /* The ranker's matrix-core product on device, for parity tests: C[M][N] (FP32, row
  * stride ldc) = A[M][K] * B[N][K]^T with A, B BF16 bit patterns (row strides lda, ldb
  * multiples of 8, 16-byte aligned), K a multiple of 32.  C is overwritten. */

@@ -103,19 +103,41 @@ def maxpool2(x):
 
 def maxpool2_backward(gout, arg, shape):
     n, c, h, w = shape
-    g = np.zeros((n, c, h // 2, w // 2, 4))
-    np.put_along_axis(g, arg[..., None], gout[..., None], axis=-1)
+    g = np.zeros((n, c, h // 2, w // 2, 5))   # slot 4 collects windows marked 255
+    a = np.where(np.asarray(arg) == 255, 4, arg).astype(np.int64)
+    np.put_along_axis(g, a[..., None], gout[..., None], axis=-1)
+    g = g[..., :4]
     return g.reshape(n, c, h // 2, w // 2, 2, 2).transpose(0, 1, 2, 4, 3, 5).reshape(n, c, h, w)
 
 
-def forward(p: dict, x: np.ndarray):
-    """x [N][2][64][256] -> logits [N] and the saved activations."""
+def pool_given(r, arg):
+    """2x2 max pool whose window choices are given: arg (0..3, row-major) picks the
+    element, 255 gives 0 and marks a window through which no gradient flows."""
+    n, c, h, w = r.shape
+    win = r.reshape(n, c, h // 2, 2, w // 2, 2).transpose(0, 1, 2, 4, 3, 5).reshape(n, c, h // 2, w // 2, 4)
+    a = np.asarray(arg).astype(np.int64)
+    out = np.take_along_axis(win, np.minimum(a, 3)[..., None], axis=-1)[..., 0]
+    out[a == 255] = 0.0
+    return out
+
+
+def forward(p: dict, x: np.ndarray, pool_args=None):
+    """x [N][2][64][256] -> logits [N] and the saved activations.
+
+    pool_args (optional): the max-pool window choices of each layer, [N][32][H/2][W/2]
+    (0..3, or 255 for a window without a positive element), for comparing with an
+    implementation whose near-tied maxima were decided in another precision; the
+    arg-max is a discrete decision, so both sides must take the same one."""
     cache = {"x0": np.asarray(x, np.float64)}
     a = cache["x0"]
     for k in range(1, 5):
         z = conv3x3(a, p[f"c{k}w"], p[f"c{k}b"])
         r = np.maximum(z, 0.0)
-        a, arg = maxpool2(r)
+        if pool_args is None:
+            a, arg = maxpool2(r)
+        else:
+            arg = np.asarray(pool_args[k - 1])
+            a = pool_given(r, arg)
         cache[f"z{k}"], cache[f"arg{k}"], cache[f"x{k}"] = z, arg, a
     f = a.reshape(a.shape[0], -1)
     h = f @ p["f1w"].T + p["f1b"]

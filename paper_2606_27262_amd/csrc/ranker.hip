@@ -39,7 +39,7 @@ __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b <<
 __global__ __launch_bounds__(256) void k_snippets(const DevBeam *__restrict__ beams, int nbeams,
                                                   const spl_candidate *__restrict__ cands, int64_t n,
                                                   uint16_t *__restrict__ out) {
-    // 32 sub-bands at a time: 33 KB of LDS (a workgroup may address at most 64 KB)
+    // 32 sub-bands at a time (33 KB of LDS, so that several workgroups share a CU)
     __shared__ int32_t sub[32][256];
     __shared__ double smu[32], ssg[32];
     const int col = threadIdx.x, lane = lane_id(), wave = wave_id();

@@ -411,6 +411,14 @@ extern "C" spl_status spl_ranker_grads(const spl_ranker *R, const float **d_grad
 
 extern "C" void spl_ranker_destroy(spl_ranker *R) { delete R; }
 
+extern "C" spl_status spl_ranker_debug_pool_args(const spl_ranker *R, int32_t layer, const uint8_t **d_arg) {
+    spl_status st = check_ready(R);
+    if (st != SPL_OK) return st;
+    if (layer < 0 || layer >= kLayers || !d_arg) return failf(SPL_E_INVALID_ARG, "bad layer or NULL argument");
+    *d_arg = R->at<uint8_t>(R->off_arg[layer]);
+    return SPL_OK;
+}
+
 extern "C" spl_status spl_debug_gemm_bf16(const uint16_t *d_a, int64_t lda, const uint16_t *d_b, int64_t ldb,
                                           float *d_c, int64_t ldc, int32_t m, int32_t n, int32_t k,
                                           hipStream_t stream) {

@@ -24,6 +24,11 @@ from . import workloads as W
 
 DISPERSION_CONSTANT = 4148.8064239   # MHz^2 pc^-1 cm^3 s, Eq. (1)
 
+# Optimisation parameters of the ranker path: every NMS candidate is its own core point
+# (min_pts 1), so DBSCAN only merges neighbours into one representative, and there is no
+# S/N cut; the DM, width and anti-coincidence tests stay.  The CNN decides the rest.
+RANKER_OPT = {"min_pts": 1, "snr_min": 0.0}
+
 
 def band_delay_per_dm(pd) -> float:
     """Delay in samples across the band (outer channel centres) per unit DM."""
@@ -114,10 +119,12 @@ class Stage:
     def plain(self, cands, **kw):
         return self.spl.optimise_plain(cands, self.tsamp, len(self.pds), **kw)
 
-    def ranked(self, cands, ranker, snr_min=0.0, **kw):
-        """Optimisation path without the S/N cut, then the CNN keeps probability >= 0.5."""
+    def ranked(self, cands, ranker, **kw):
+        """The ranker path: the optimisation stage with the CNN in place of the density
+        test and the S/N cut (RANKER_OPT: DBSCAN groups neighbours but keeps single
+        points), then the CNN keeps probability >= 0.5."""
         import torch
-        surv = self.plain(cands, snr_min=snr_min, **kw)
+        surv = self.plain(cands, **{**RANKER_OPT, **kw})
         if surv.size == 0:
             return surv, np.zeros(0, np.float32)
         logits = ranker.score(self.snippets(surv))

@@ -135,6 +135,7 @@ _sig("spl_ranker_train_step", [_P, _P, _P, _I64, _F32, _P, _P])
 _sig("spl_ranker_grads", [_P, ctypes.POINTER(_P)])
 _sig("spl_ranker_destroy", [_P], None)
 _sig("spl_debug_gemm_bf16", [_P, _I64, _P, _I64, _P, _I64, _I32, _I32, _I32, _P])
+_sig("spl_ranker_debug_pool_args", [_P, _I32, ctypes.POINTER(_P)])
 
 SNIPPET_ROWS, SNIPPET_COLS = 64, 256
 SNIPPET_ELEMS = 2 * SNIPPET_ROWS * SNIPPET_COLS
@@ -486,6 +487,18 @@ class Ranker:
         off = p.value - self.ws.data_ptr()
         assert 0 <= off and off + RANKER_PARAMS * 4 <= self.ws.numel()
         return self.ws[off:off + RANKER_PARAMS * 4].view(torch.float32)
+
+    def pool_args(self, layer):
+        """Device view uint8 [Nb][H/2][W/2][32] of conv layer `layer`'s pooling decisions."""
+        import torch
+        p = _P()
+        _check(_lib.spl_ranker_debug_pool_args(self._h, int(layer), ctypes.byref(p)))
+        nb = (self.max_batch + 31) // 32 * 32
+        h, w = (32, 16, 8, 4)[layer], (128, 64, 32, 16)[layer]
+        n = nb * h * w * 32
+        off = p.value - self.ws.data_ptr()
+        assert 0 <= off and off + n <= self.ws.numel()
+        return self.ws[off:off + n].view(nb, h, w, 32)
 
     def __del__(self):
         if getattr(self, "_h", None):

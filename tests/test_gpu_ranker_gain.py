@@ -1,0 +1,43 @@
+"""What the trained ranker gains over the plain optimisation path.
+
+Fresh blocks (seeds never used in training) with injected bursts, RFI channels and
+zero-DM bursts common to the beams are searched; the plain path (DBSCAN with >= 5
+points, S/N >= 10, DM >= 10, width <= 100 ms, anti-coincidence) and the ranker path
+(the same stage with the CNN in place of the density test and the S/N cut) are scored
+against the injections.  The trained weights are the ones the training driver wrote
+(paper_2606_27262_amd/data/ranker_weights.npy)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2606_27262_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2606_27262_amd",
+                       "data", "ranker_weights.npy")
+
+
+@pytest.fixture(scope="module")
+def spl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_27262_amd import spotlight
+    return spotlight
+
+
+def test_trained_ranker_beats_plain_path(spl):
+    from paper_2606_27262_amd import ranking
+    assert os.path.exists(WEIGHTS), "trained ranker weights are missing"
+    r = spl.Ranker(max_batch=256)
+    r.set_weights(np.load(WEIGHTS))
+    pds = [W.plan_c2() for _ in range(8)]
+    res = ranking.evaluate(spl, pds, r, 1, 91000, log=lambda *a: print(*a, flush=True))
+    print(res, flush=True)
+    sys.stdout.flush()
+    p, q = res["plain"], res["ranker"]
+    assert q["recall"] >= p["recall"] + 0.05, (p, q)
+    assert q["false_alarms_per_beam_block"] <= p["false_alarms_per_beam_block"] + 0.5, (p, q)

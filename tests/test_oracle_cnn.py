@@ -72,3 +72,32 @@ def test_maxpool_tie_goes_to_first():
     assert arg[0, 0, 0, 0] == 0
     g = cnn.maxpool2_backward(np.ones((1, 1, 1, 1)), arg, x.shape)
     assert g[0, 0, 0, 0] == 1 and g.sum() == 1
+
+
+def test_given_pool_decisions_reproduce_own_pass():
+    """Feeding the forward pass its own arg-max decisions changes nothing; marking a
+    window 255 zeroes its pooled value and its gradient."""
+    rng = np.random.default_rng(4)
+    p = cnn.init_params(4)
+    for k in p:
+        if k.endswith("b"):
+            p[k] = rng.normal(0, 0.1, p[k].shape)
+    x = rng.normal(0, 1, size=(2, 2, 64, 256))
+    y = np.array([1.0, 0.0])
+    l0, c0 = cnn.forward(p, x)
+    args = [c0[f"arg{k}"] for k in range(1, 5)]
+    l1, c1 = cnn.forward(p, x, pool_args=args)
+    assert np.array_equal(l0, l1)
+    _, g0 = cnn.backward(p, c0, y)
+    _, g1 = cnn.backward(p, c1, y)
+    for k in g0:
+        assert np.array_equal(g0[k], g1[k]), k
+    # one window of layer 4 marked as having no positive element
+    a4 = args[3].copy()
+    a4[0, 5, 1, 2] = 255
+    l2, c2 = cnn.forward(p, x, pool_args=args[:3] + [a4])
+    assert c2["x4"][0, 5, 1, 2] == 0.0
+    _, g2 = cnn.backward(p, c2, y)
+    z4 = c2["z4"]
+    gr = cnn.maxpool2_backward(np.ones_like(c2["x4"]), a4, z4.shape)
+    assert gr[0, 5, 2:4, 4:6].sum() == 0.0 and gr.sum() == c2["x4"].size - 1
