@@ -96,6 +96,29 @@ def cpu_baseline(pd, plan, W, target_s=12.0):
                       f"{i['nchans']}-channel block: dedispersion + boxcar search + peak filters"}
 
 
+def corner_turn_leg(spl, plan, reps=10):
+    """Corner turn of one block of the workload's first plan (time-major spectra in,
+    channel-major rows out): HIP-event time per launch and the achieved bytes/s, with
+    2 bytes per sample (one read, one write) as the algorithmic traffic."""
+    import torch
+    n_t, nch = plan.info["n_in"], plan.info["nchans"]
+    src = torch.randint(0, 256, (n_t, nch), dtype=torch.uint8, device="cuda")
+    dst = torch.empty((nch, (n_t + 255) // 256 * 256), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    spl.corner_turn(src, out=dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        spl.corner_turn(src, out=dst)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbps = 2.0 * n_t * nch / (ms / 1e3) / 1e9
+    del src, dst
+    return {"samples": n_t * nch, "launch_ms": ms, "achieved_GBps": gbps, "peak_GBps": 8000.0,
+            "frac": gbps / 8000.0}
+
+
 def per_beam_comparison(spl, plans, blocks, args, cands, stats):
     """The same blocks searched beam by beam (plain mode: one launch sequence per beam),
     for the comparison of the batched form with the per-beam pipeline."""
@@ -313,6 +336,8 @@ def main():
     if nb > 1 and not args.no_per_beam and mode == "graph":
         out["plain_per_beam"] = per_beam_comparison(spl, plans, blocks, args, cands, stats)
         out["plain_per_beam"]["real_time_beams_per_gpu"] = nb / (out["plain_per_beam"]["ms_per_step"] / 1e3 / block_s)
+    if all(pd["nchans"] % 16 == 0 for pd in pds):
+        out["corner_turn"] = corner_turn_leg(spl, plans[0])
     if not args.no_ranker and all(pd["nchans"] % 64 == 0 for pd in pds):
         log("ranker leg")
         out["ranker"] = ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, args, ms_step,

@@ -432,6 +432,11 @@ spl_status spl_debug_mu_sigma(const int64_t *d_n, const int64_t *d_s1, const int
  * maximum is 0 (no gradient flows through the window). */
 spl_status spl_ranker_debug_pool_args(const spl_ranker *r, int32_t layer, const uint8_t **d_arg);
 
+/* Device view of the first fully connected layer's output before its bias, FP32
+ * [Nb][64], of the ranker's last pass, for parity tests: the hidden unit j of candidate
+ * n is active when (float)(h[n][j] + f1b[j]) > 0. */
+spl_status spl_ranker_debug_fc_preact(const spl_ranker *r, const float **d_h);
+
 /* The ranker's matrix-core product on device, for parity tests: C[M][N] (FP32, row
  * stride ldc) = A[M][K] * B[N][K]^T with A, B BF16 bit patterns (row strides lda, ldb
  * multiples of 8, 16-byte aligned), K a multiple of 32.  C is overwritten. */

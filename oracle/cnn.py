@@ -112,7 +112,8 @@ def maxpool2_backward(gout, arg, shape):
 
 def pool_given(r, arg):
     """2x2 max pool whose window choices are given: arg (0..3, row-major) picks the
-    element, 255 gives 0 and marks a window through which no gradient flows."""
+    element, 255 gives 0 and marks a window through which no gradient flows.  A given
+    choice 0..3 also decides the ReLU gate: the gradient passes to that element."""
     n, c, h, w = r.shape
     win = r.reshape(n, c, h // 2, 2, w // 2, 2).transpose(0, 1, 2, 4, 3, 5).reshape(n, c, h // 2, w // 2, 4)
     a = np.asarray(arg).astype(np.int64)
@@ -121,14 +122,18 @@ def pool_given(r, arg):
     return out
 
 
-def forward(p: dict, x: np.ndarray, pool_args=None):
+def forward(p: dict, x: np.ndarray, pool_args=None, fc_gate=None):
     """x [N][2][64][256] -> logits [N] and the saved activations.
 
     pool_args (optional): the max-pool window choices of each layer, [N][32][H/2][W/2]
     (0..3, or 255 for a window without a positive element), for comparing with an
-    implementation whose near-tied maxima were decided in another precision; the
-    arg-max is a discrete decision, so both sides must take the same one."""
-    cache = {"x0": np.asarray(x, np.float64)}
+    implementation that decided near-tied maxima, or the sign of a near-zero
+    pre-activation, in another precision: the arg-max and the ReLU gate are discrete
+    decisions, so both sides must take the same ones.  With given choices the gradient
+    passes to the chosen element of every window not marked 255.
+    fc_gate (optional): bool [N][64], the given ReLU gates of the hidden layer (open:
+    the unit's value and gradient pass; closed: both are 0)."""
+    cache = {"x0": np.asarray(x, np.float64), "given": pool_args is not None}
     a = cache["x0"]
     for k in range(1, 5):
         z = conv3x3(a, p[f"c{k}w"], p[f"c{k}b"])
@@ -141,7 +146,9 @@ def forward(p: dict, x: np.ndarray, pool_args=None):
         cache[f"z{k}"], cache[f"arg{k}"], cache[f"x{k}"] = z, arg, a
     f = a.reshape(a.shape[0], -1)
     h = f @ p["f1w"].T + p["f1b"]
-    hr = np.maximum(h, 0.0)
+    gate = (h > 0) if fc_gate is None else np.asarray(fc_gate, bool)
+    hr = np.where(gate, np.maximum(h, 0.0), 0.0)
+    cache["gate"] = gate
     logit = (hr @ p["f2w"].T + p["f2b"])[:, 0]
     cache.update(f=f, h=h, hr=hr)
     return logit, cache
@@ -165,7 +172,7 @@ def backward(p: dict, cache: dict, y: np.ndarray) -> tuple[float, dict]:
     g["f2w"] = gz[None, :] @ hr
     g["f2b"] = np.array([gz.sum()])
     ghr = gz[:, None] * p["f2w"]
-    gh = ghr * (h > 0)
+    gh = ghr * cache.get("gate", h > 0)
     g["f1w"] = gh.T @ f
     g["f1b"] = gh.sum(axis=0)
     gf = gh @ p["f1w"]
@@ -173,7 +180,7 @@ def backward(p: dict, cache: dict, y: np.ndarray) -> tuple[float, dict]:
     for k in range(4, 0, -1):
         z = cache[f"z{k}"]
         gr = maxpool2_backward(ga, cache[f"arg{k}"], z.shape)
-        gzk = gr * (z > 0)
+        gzk = gr if cache.get("given") else gr * (z > 0)
         xin = cache[f"x{k - 1}"]
         ga, g[f"c{k}w"], g[f"c{k}b"] = conv3x3_backward(xin, p[f"c{k}w"], gzk)
     return loss, g

@@ -419,6 +419,14 @@ extern "C" spl_status spl_ranker_debug_pool_args(const spl_ranker *R, int32_t la
     return SPL_OK;
 }
 
+extern "C" spl_status spl_ranker_debug_fc_preact(const spl_ranker *R, const float **d_h) {
+    spl_status st = check_ready(R);
+    if (st != SPL_OK) return st;
+    if (!d_h) return failf(SPL_E_INVALID_ARG, "NULL argument");
+    *d_h = R->at<float>(R->off_Hm);
+    return SPL_OK;
+}
+
 extern "C" spl_status spl_debug_gemm_bf16(const uint16_t *d_a, int64_t lda, const uint16_t *d_b, int64_t ldb,
                                           float *d_c, int64_t ldc, int32_t m, int32_t n, int32_t k,
                                           hipStream_t stream) {

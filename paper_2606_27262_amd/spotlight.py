@@ -136,6 +136,7 @@ _sig("spl_ranker_grads", [_P, ctypes.POINTER(_P)])
 _sig("spl_ranker_destroy", [_P], None)
 _sig("spl_debug_gemm_bf16", [_P, _I64, _P, _I64, _P, _I64, _I32, _I32, _I32, _P])
 _sig("spl_ranker_debug_pool_args", [_P, _I32, ctypes.POINTER(_P)])
+_sig("spl_ranker_debug_fc_preact", [_P, ctypes.POINTER(_P)])
 
 SNIPPET_ROWS, SNIPPET_COLS = 64, 256
 SNIPPET_ELEMS = 2 * SNIPPET_ROWS * SNIPPET_COLS
@@ -499,6 +500,16 @@ class Ranker:
         off = p.value - self.ws.data_ptr()
         assert 0 <= off and off + n <= self.ws.numel()
         return self.ws[off:off + n].view(nb, h, w, 32)
+
+    def fc_preact(self):
+        """Device view float32 [Nb][64] of FC1's output before its bias (last pass)."""
+        import torch
+        p = _P()
+        _check(_lib.spl_ranker_debug_fc_preact(self._h, ctypes.byref(p)))
+        nb = (self.max_batch + 31) // 32 * 32
+        off = p.value - self.ws.data_ptr()
+        assert 0 <= off and off + nb * 64 * 4 <= self.ws.numel()
+        return self.ws[off:off + nb * 64 * 4].view(torch.float32).view(nb, 64)
 
     def __del__(self):
         if getattr(self, "_h", None):

@@ -85,8 +85,13 @@ def test_given_pool_decisions_reproduce_own_pass():
     x = rng.normal(0, 1, size=(2, 2, 64, 256))
     y = np.array([1.0, 0.0])
     l0, c0 = cnn.forward(p, x)
-    args = [c0[f"arg{k}"] for k in range(1, 5)]
-    l1, c1 = cnn.forward(p, x, pool_args=args)
+    args = []
+    for k in range(1, 5):   # the given convention: 255 where no element is positive
+        a = c0[f"arg{k}"].copy()
+        a[c0[f"x{k}"] <= 0] = 255
+        args.append(a)
+    assert any(np.any(a == 255) for a in args)
+    l1, c1 = cnn.forward(p, x, pool_args=args, fc_gate=c0["h"] > 0)
     assert np.array_equal(l0, l1)
     _, g0 = cnn.backward(p, c0, y)
     _, g1 = cnn.backward(p, c1, y)
@@ -100,4 +105,19 @@ def test_given_pool_decisions_reproduce_own_pass():
     _, g2 = cnn.backward(p, c2, y)
     z4 = c2["z4"]
     gr = cnn.maxpool2_backward(np.ones_like(c2["x4"]), a4, z4.shape)
-    assert gr[0, 5, 2:4, 4:6].sum() == 0.0 and gr.sum() == c2["x4"].size - 1
+    assert gr[0, 5, 2:4, 4:6].sum() == 0.0 and gr.sum() == np.sum(a4 != 255)
+
+
+def test_given_fc_gate_closes_a_unit():
+    rng = np.random.default_rng(6)
+    p = cnn.init_params(6)
+    x = rng.normal(0, 1, size=(1, 2, 64, 256))
+    y = np.array([1.0])
+    l0, c0 = cnn.forward(p, x)
+    gate = c0["h"] > 0
+    j = int(np.argmax(c0["h"][0]))
+    gate[0, j] = False
+    l1, c1 = cnn.forward(p, x, fc_gate=gate)
+    assert np.isclose(l0[0] - l1[0], c0["h"][0, j] * p["f2w"][0, j], rtol=1e-12, atol=1e-12)
+    _, g1 = cnn.backward(p, c1, y)
+    assert g1["f1b"][j] == 0.0 and np.all(g1["f1w"][j] == 0.0)
