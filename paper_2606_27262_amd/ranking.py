@@ -164,7 +164,8 @@ def mine(spl, pds, n_batches, seed0, neg_ratio=1.0, log=print, **burst_kw):
 
 
 def train(ranker, x, y, epochs=20, batch=256, lr=1e-3, val_frac=0.1, seed=0, log=print):
-    """Adam on shuffled minibatches; returns the history of (epoch, train loss, val acc)."""
+    """Adam on shuffled minibatches; the weights of the epoch with the best validation
+    accuracy are kept.  Returns the history of (epoch, train loss, val acc)."""
     import torch
     n = x.shape[0]
     rng = np.random.default_rng(seed)
@@ -173,6 +174,7 @@ def train(ranker, x, y, epochs=20, batch=256, lr=1e-3, val_frac=0.1, seed=0, log
     val, tr = perm[:n_val], perm[n_val:]
     yd = torch.from_numpy(y).cuda()
     hist = []
+    best_acc, best_w = -1.0, None
     for ep in range(epochs):
         order = rng.permutation(tr)
         tot, cnt = 0.0, 0
@@ -188,6 +190,10 @@ def train(ranker, x, y, epochs=20, batch=256, lr=1e-3, val_frac=0.1, seed=0, log
             acc = float(np.mean((lg >= 0) == (y[val] >= 0.5)))
         hist.append((ep, tot / max(1, cnt), acc))
         log(f"epoch {ep + 1}/{epochs}: train loss {tot / max(1, cnt):.4f}, val acc {acc:.4f}")
+        if n_val and acc > best_acc:
+            best_acc, best_w = acc, ranker.get_weights()
+    if best_w is not None:
+        ranker.set_weights(best_w)
     return hist
 
 
@@ -195,7 +201,7 @@ def evaluate(spl, pds, ranker, n_batches, seed0, log=print, **burst_kw):
     """Recall and false alarms of the plain path and of the ranker path on fresh blocks."""
     import torch
     st = Stage(spl, pds)
-    plain_all, rank_all, pulses_all, cand_all = [], [], [], 0
+    plain_all, rank_all, pulses_all, cand_all, scored_all, logit_all = [], [], [], 0, [], []
     t_rank = 0.0
     for i in range(n_batches):
         blocks, pulses = burst_batch(pds, seed0 + i, n_in=st.n_in, **burst_kw)
@@ -204,14 +210,21 @@ def evaluate(spl, pds, ranker, n_batches, seed0, log=print, **burst_kw):
         cand_all += cands.size
         fp = st.plain(cands)
         t0 = time.time()
-        fr, _ = st.ranked(cands, ranker) if ranker is not None else (fp, None)
+        if ranker is not None:
+            surv = st.plain(cands, **RANKER_OPT)
+            lg = ranker.score(st.snippets(surv)).cpu().numpy() if surv.size else np.zeros(0, np.float32)
+            fr = surv[lg >= 0.0]
+        else:
+            surv, lg, fr = fp.copy(), np.zeros(fp.size, np.float32), fp.copy()
         torch.cuda.synchronize()
         t_rank += time.time() - t0
         off = len(pulses_all)
-        for arr in (fp, fr):
+        for arr in (fp, fr, surv):
             arr["beam"] += off
         plain_all.append(fp)
         rank_all.append(fr)
+        scored_all.append(surv)
+        logit_all.append(lg)
         pulses_all.extend(pulses)
         log(f"eval batch {i + 1}/{n_batches}: {cands.size} candidates, plain keeps {fp.size}, ranker keeps {fr.size}")
     pds_all = [pds[b % len(pds)] for b in range(len(pulses_all))]
@@ -223,6 +236,24 @@ def evaluate(spl, pds, ranker, n_batches, seed0, log=print, **burst_kw):
            "ranker_stage_s": t_rank}
     for k in ("plain", "ranker"):
         res[k]["false_alarms_per_beam_block"] = res[k]["false_alarms"] / max(1, len(pulses_all))
+    # the ranker at the plain path's false-alarm rate: the lowest logit threshold whose
+    # false alarms do not exceed the plain path's
+    scored = np.concatenate(scored_all)
+    logits = np.concatenate(logit_all)
+    target = res["plain"]["false_alarms"]
+    m = match(scored, pulses_all, pds_all)
+    n_inj = res["plain"]["injected"]
+    best = None
+    for tau in np.unique(np.concatenate([logits, [np.inf]])):
+        keep = logits >= tau
+        fa = int(np.sum(keep & (m < 0)))
+        if fa <= target:
+            found = {(int(scored[i]["beam"]), int(m[i])) for i in np.nonzero(keep & (m >= 0))[0]}
+            best = {"threshold_logit": float(tau), "recall": len(found) / max(1, n_inj), "recovered": len(found),
+                    "false_alarms": fa, "false_alarms_per_beam_block": fa / max(1, len(pulses_all)),
+                    "kept": int(keep.sum())}
+            break
+    res["ranker_at_plain_false_alarms"] = best
     return res
 
 

@@ -38,6 +38,8 @@ def test_trained_ranker_beats_plain_path(spl):
     res = ranking.evaluate(spl, pds, r, 1, 91000, log=lambda *a: print(*a, flush=True))
     print(res, flush=True)
     sys.stdout.flush()
-    p, q = res["plain"], res["ranker"]
+    p, q, m = res["plain"], res["ranker"], res["ranker_at_plain_false_alarms"]
+    # at its own operating point (probability >= 0.5) the ranker path finds more bursts
     assert q["recall"] >= p["recall"] + 0.05, (p, q)
-    assert q["false_alarms_per_beam_block"] <= p["false_alarms_per_beam_block"] + 0.5, (p, q)
+    # and at the plain path's false-alarm count it finds at least as many
+    assert m is not None and m["false_alarms"] <= p["false_alarms"] and m["recall"] >= p["recall"], (p, m)
