@@ -96,20 +96,23 @@ def cpu_baseline(pd, plan, W, target_s=12.0):
                       f"{i['nchans']}-channel block: dedispersion + boxcar search + peak filters"}
 
 
-def corner_turn_leg(spl, plan, reps=10):
-    """Corner turn of one block of the workload's first plan (time-major spectra in,
+def corner_turn_leg(spl, plan, reps=12, nbuf=4):
+    """Corner turn of blocks of the workload's first plan (time-major spectra in,
     channel-major rows out): HIP-event time per launch and the achieved bytes/s, with
-    2 bytes per sample (one read, one write) as the algorithmic traffic."""
+    2 bytes per sample (one read, one write) as the algorithmic traffic.  The launches
+    rotate over nbuf block pairs (0.86 GB for 4096 x 26305 samples), more than the
+    256 MB last-level cache, so the figure is an HBM rate."""
     import torch
     n_t, nch = plan.info["n_in"], plan.info["nchans"]
-    src = torch.randint(0, 256, (n_t, nch), dtype=torch.uint8, device="cuda")
-    dst = torch.empty((nch, (n_t + 255) // 256 * 256), dtype=torch.uint8, device="cuda")
+    src = [torch.randint(0, 256, (n_t, nch), dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
+    dst = [torch.empty((nch, (n_t + 255) // 256 * 256), dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
     s = torch.cuda.current_stream()
-    spl.corner_turn(src, out=dst)
+    for i in range(nbuf):
+        spl.corner_turn(src[i], out=dst[i])
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
-    for _ in range(reps):
-        spl.corner_turn(src, out=dst)
+    for r in range(reps):
+        spl.corner_turn(src[r % nbuf], out=dst[r % nbuf])
     e1.record(s)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -203,7 +206,14 @@ def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, arg
         "weights": "trained" if trained else "untrained (initial weights)",
         "plain_path": {**pr, "host_ms": t_plain * 1e3},
         "ranker_path": {**rr, "scored": int(n_scored), "stage_ms": t_rank * 1e3},
-        "real_time_beams_per_gpu_with_ranker": nb / ((ms_step + t_rank * 1e3) / 1e3 / block_s),
+        # the candidate stage after the search of the same block (serial), or overlapped
+        # with the search of the next block (the stage runs on the host and the GPU's
+        # snippets and CNN take a few ms)
+        "real_time_beams_per_gpu": {
+            "plain_serial": nb / ((ms_step + t_plain * 1e3) / 1e3 / block_s),
+            "plain_overlapped": nb / (max(ms_step, t_plain * 1e3) / 1e3 / block_s),
+            "ranker_serial": nb / ((ms_step + t_rank * 1e3) / 1e3 / block_s),
+            "ranker_overlapped": nb / (max(ms_step, t_rank * 1e3) / 1e3 / block_s)},
         "cnn": {"batch": n, "flop_forward_per_candidate": flop_fwd,
                 "inference_ms": t_inf * 1e3, "inference_candidates_per_s": n / t_inf,
                 "inference_tflops": n * flop_fwd / t_inf / 1e12,

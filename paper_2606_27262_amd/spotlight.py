@@ -16,6 +16,10 @@ LIB_PATH = os.path.join(_HERE, "libspotlight.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2606_27262_amd.build.build() "
                       "(or __graft_entry__.build()) before using the search")
+# torch is loaded first so that the library's libamdhip64.so.7 resolves to the HIP runtime
+# torch already holds: device memory and streams come from torch, and a second HIP/HSA
+# runtime in the same process would not see the device.
+import torch  # noqa: E402,F401
 _lib = ctypes.CDLL(LIB_PATH)
 
 STAGES = ("dedisp", "thresholds", "boxcar", "peaks")

@@ -35,6 +35,8 @@ def main(argv=None):
     ap.add_argument("--eval-seed", type=int, default=7000)
     ap.add_argument("--out", default="ranker_weights.npy")
     ap.add_argument("--json", default=None)
+    ap.add_argument("--eval-only", default=None, metavar="WEIGHTS",
+                    help="skip training: evaluate these weights (.npy) against the plain path")
     a = ap.parse_args(argv)
 
     import numpy as np
@@ -47,6 +49,16 @@ def main(argv=None):
     assert torch.cuda.is_available(), "training runs on the GPU"
     t_start = time.time()
     ranker = spl.Ranker(max_batch=a.max_batch)
+    if a.eval_only:
+        ranker.set_weights(np.load(a.eval_only))
+        pde = [W.plan_c2() for _ in range(a.eval_beams)]
+        res = ranking.evaluate(spl, pde, ranker, a.eval_batches, a.eval_seed, log=log, n_pulses=a.pulses)
+        line = json.dumps({"eval": res, "weights": os.path.abspath(a.eval_only), "wall_s": time.time() - t_start})
+        print(line, flush=True)
+        if a.json:
+            with open(a.json, "w") as f:
+                f.write(line + "\n")
+        return
     ranker.set_weights(ranking.initial_weights(a.seed))
     pds = [W.plan_c2() for _ in range(a.beams)]
     x, y = ranking.mine(spl, pds, a.train_batches, a.seed * 100000, log=log, n_pulses=a.pulses)
