@@ -170,12 +170,13 @@ def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, arg
     fp = spl.optimise_plain(recs, tsamp, nb)
     t_plain = time.perf_counter() - t0
     t0 = time.perf_counter()
-    surv = spl.optimise_plain(recs, tsamp, nb, **ranking.RANKER_OPT)
-    kept, n_scored = surv, 0
-    if surv.size:
-        dev = torch.from_numpy(surv.view(np.int32).reshape(-1, 8).copy()).cuda()
-        lg = ranker.score(spl.snippets(batch, dev)).cpu().numpy()
-        kept, n_scored = surv[lg >= 0], surv.size
+
+    def score(r):
+        dev = torch.from_numpy(np.ascontiguousarray(r).view(np.int32).reshape(-1, 8).copy()).cuda()
+        return ranker.score(spl.snippets(batch, dev)).cpu().numpy()
+
+    kept, surv, _ = ranking.ranker_path(spl, recs, tsamp, nb, score)
+    n_scored = surv.size
     t_rank = time.perf_counter() - t0
     pr = ranking.recall_and_false_alarms(fp, pulses, pds)
     rr = ranking.recall_and_false_alarms(kept, pulses, pds)

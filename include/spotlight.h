@@ -417,6 +417,20 @@ spl_status spl_ranker_grads(const spl_ranker *r, const float **d_grads);
 
 void spl_ranker_destroy(spl_ranker *r);
 
+/*
+ * The anti-coincidence step of the plain path on its own, for pipelines that put
+ * another stage (the ranker) between the thresholds and this filter: with at least
+ * params->coinc_min_beams beams, a record is dropped when more than
+ * params->coinc_frac * n_beams beams hold a record (of `cands`) within
+ * params->coinc_dt_s of its arrival time t_sample * tsamp_of_beam[beam].  Survivors
+ * are written to `out` sorted by (beam, dm_index, t_sample); *n_out receives their
+ * number; SPL_E_CAPACITY if it exceeds `capacity`.  Host records; params NULL selects
+ * the defaults.
+ */
+spl_status spl_anti_coincidence(const spl_candidate *cands, int64_t n, const double *tsamp_of_beam,
+                                int32_t n_beams, const spl_opt_params *params, spl_candidate *out,
+                                int64_t capacity, int64_t *n_out);
+
 /* ------------------------------------------------------------- test hooks */
 /* The normaliser of the search on device, for parity tests: for i < count,
  * mu[i] = S1/n and sigma[i] = sqrt(n*S2 - S1^2)/n (exact 128-bit difference,

@@ -270,13 +270,24 @@ def plain_optimise(cands: np.ndarray, tsamp_of_beam, n_beams: int, **kw) -> np.n
     ok = ((c["snr"] >= np.float32(p["snr_min"])) & (c["dm"].astype(np.float64) >= p["dm_min"]) &
           (c["width"].astype(np.float64) * ts <= p["width_max_s"]))
     c = c[ok]
-    if n_beams >= p["coinc_min_beams"] and c.size:
+    return anti_coincidence(c, tsamp_of_beam, n_beams, **{k: p[k] for k in
+                                                          ("coinc_dt_s", "coinc_frac", "coinc_min_beams")})
+
+
+def anti_coincidence(c: np.ndarray, tsamp_of_beam, n_beams: int, coinc_dt_s=0.05, coinc_frac=0.5,
+                     coinc_min_beams=3) -> np.ndarray:
+    """Anti-coincidence across the batch's beams (candidate optimisation section): with
+    at least coinc_min_beams beams, drop a candidate when more than coinc_frac of the
+    beams hold a candidate within coinc_dt_s of its arrival time.  Sorted by (beam, d, t)."""
+    tsamp_of_beam = np.asarray(tsamp_of_beam, np.float64)
+    c = np.asarray(c, CAND_DTYPE)
+    if n_beams >= coinc_min_beams and c.size:
         tabs = c["t_sample"].astype(np.float64) * tsamp_of_beam[c["beam"]]
         drop = np.zeros(c.size, bool)
         for i in range(c.size):
-            near = np.abs(tabs - tabs[i]) <= p["coinc_dt_s"]
+            near = np.abs(tabs - tabs[i]) <= coinc_dt_s
             nb = np.unique(c["beam"][near]).size
-            drop[i] = nb > p["coinc_frac"] * n_beams
+            drop[i] = nb > coinc_frac * n_beams
         c = c[~drop]
     order = np.lexsort((c["t_sample"], c["dm_index"], c["beam"]))
     return c[order]

@@ -108,7 +108,65 @@ std::vector<int> dbscan(const std::vector<Pt> &pts, double eps, int min_pts) {
     return label;
 }
 
+// Candidates that survive the anti-coincidence filter (any order in, same order out).
+std::vector<spl_candidate> anti_coincidence(const std::vector<spl_candidate> &thr, const double *tsamp_of_beam,
+                                            int n_beams, const spl_opt_params &P) {
+    if (!(n_beams >= P.coinc_min_beams) || thr.empty()) return thr;
+    std::vector<spl_candidate> fin;
+    std::vector<double> tabs(thr.size());
+    for (size_t i = 0; i < thr.size(); ++i) tabs[i] = (double)thr[i].t_sample * tsamp_of_beam[thr[i].beam];
+    std::vector<size_t> order(thr.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t c) { return tabs[a] < tabs[c]; });
+    std::vector<char> seen(n_beams, 0);
+    for (size_t i = 0; i < thr.size(); ++i) {
+        std::fill(seen.begin(), seen.end(), 0);
+        int nb = 0;
+        // candidates within coinc_dt_s, found by scanning the time-sorted list
+        auto lo = std::lower_bound(order.begin(), order.end(), tabs[i] - P.coinc_dt_s - 1.0,
+                                   [&](size_t a, double v) { return tabs[a] < v; });
+        for (auto it = lo; it != order.end() && tabs[*it] <= tabs[i] + P.coinc_dt_s + 1.0; ++it) {
+            if (std::fabs(tabs[*it] - tabs[i]) <= P.coinc_dt_s && !seen[thr[*it].beam]) {
+                seen[thr[*it].beam] = 1;
+                ++nb;
+            }
+        }
+        if (!((double)nb > P.coinc_frac * (double)n_beams)) fin.push_back(thr[i]);
+    }
+    return fin;
+}
+
+void sort_records(std::vector<spl_candidate> &v) {
+    std::sort(v.begin(), v.end(), [](const spl_candidate &a, const spl_candidate &c) {
+        if (a.beam != c.beam) return a.beam < c.beam;
+        if (a.dm_index != c.dm_index) return a.dm_index < c.dm_index;
+        return a.t_sample < c.t_sample;
+    });
+}
+
 }  // namespace
+
+extern "C" spl_status spl_anti_coincidence(const spl_candidate *cands, int64_t n, const double *tsamp_of_beam,
+                                           int32_t n_beams, const spl_opt_params *params, spl_candidate *out,
+                                           int64_t capacity, int64_t *n_out) {
+    if (n < 0 || (n > 0 && !cands) || !tsamp_of_beam || n_beams < 1 || !n_out || capacity < 0 ||
+        (capacity > 0 && !out))
+        return spl_internal_fail(SPL_E_INVALID_ARG, "spl_anti_coincidence: bad argument");
+    spl_opt_params P;
+    if (params) P = *params; else spl_opt_defaults(&P);
+    for (int64_t i = 0; i < n; ++i)
+        if (cands[i].beam < 0 || cands[i].beam >= n_beams)
+            return spl_internal_fail(SPL_E_INVALID_ARG, "spl_anti_coincidence: candidate beam out of range");
+    std::vector<spl_candidate> in(cands, cands + n);
+    std::vector<spl_candidate> fin = anti_coincidence(in, tsamp_of_beam, n_beams, P);
+    sort_records(fin);
+    *n_out = (int64_t)fin.size();
+    const int64_t m = std::min<int64_t>(capacity, (int64_t)fin.size());
+    if (m > 0) std::memcpy(out, fin.data(), (size_t)m * sizeof(spl_candidate));
+    if ((int64_t)fin.size() > capacity)
+        return spl_internal_fail(SPL_E_CAPACITY, "spl_anti_coincidence: more survivors than capacity");
+    return SPL_OK;
+}
 
 extern "C" spl_status spl_optimise_plain(const spl_candidate *cands, int64_t n, const double *tsamp_of_beam,
                                          int32_t n_beams, const spl_opt_params *params, spl_candidate *out,
@@ -161,36 +219,8 @@ extern "C" spl_status spl_optimise_plain(const spl_candidate *cands, int64_t n, 
             thr.push_back(c);
     }
     // anti-coincidence across the batch's beams
-    std::vector<spl_candidate> fin;
-    if (n_beams >= P.coinc_min_beams && !thr.empty()) {
-        std::vector<double> tabs(thr.size());
-        for (size_t i = 0; i < thr.size(); ++i) tabs[i] = (double)thr[i].t_sample * tsamp_of_beam[thr[i].beam];
-        std::vector<size_t> order(thr.size());
-        std::iota(order.begin(), order.end(), 0);
-        std::sort(order.begin(), order.end(), [&](size_t a, size_t c) { return tabs[a] < tabs[c]; });
-        std::vector<char> seen(n_beams, 0);
-        for (size_t i = 0; i < thr.size(); ++i) {
-            std::fill(seen.begin(), seen.end(), 0);
-            int nb = 0;
-            // candidates within coinc_dt_s, found by scanning the time-sorted list
-            auto lo = std::lower_bound(order.begin(), order.end(), tabs[i] - P.coinc_dt_s - 1.0,
-                                       [&](size_t a, double v) { return tabs[a] < v; });
-            for (auto it = lo; it != order.end() && tabs[*it] <= tabs[i] + P.coinc_dt_s + 1.0; ++it) {
-                if (std::fabs(tabs[*it] - tabs[i]) <= P.coinc_dt_s && !seen[thr[*it].beam]) {
-                    seen[thr[*it].beam] = 1;
-                    ++nb;
-                }
-            }
-            if (!((double)nb > P.coinc_frac * (double)n_beams)) fin.push_back(thr[i]);
-        }
-    } else {
-        fin = thr;
-    }
-    std::sort(fin.begin(), fin.end(), [](const spl_candidate &a, const spl_candidate &c) {
-        if (a.beam != c.beam) return a.beam < c.beam;
-        if (a.dm_index != c.dm_index) return a.dm_index < c.dm_index;
-        return a.t_sample < c.t_sample;
-    });
+    std::vector<spl_candidate> fin = anti_coincidence(thr, tsamp_of_beam, n_beams, P);
+    sort_records(fin);
     *n_out = (int64_t)fin.size();
     const int64_t m = std::min<int64_t>(capacity, (int64_t)fin.size());
     if (m > 0) std::memcpy(out, fin.data(), (size_t)m * sizeof(spl_candidate));

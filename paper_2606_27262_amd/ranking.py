@@ -33,10 +33,24 @@ from . import workloads as W
 
 DISPERSION_CONSTANT = 4148.8064239   # MHz^2 pc^-1 cm^3 s, Eq. (1)
 
-# Optimisation parameters of the ranker path: every NMS candidate is its own core point
-# (min_pts 1), so DBSCAN only merges neighbours into one representative, and there is no
-# S/N cut; the DM, width and anti-coincidence tests stay.  The CNN decides the rest.
-RANKER_OPT = {"min_pts": 1, "snr_min": 0.0}
+# Optimisation parameters of the ranker path before the CNN: every NMS candidate is its
+# own core point (min_pts 1), so DBSCAN only merges neighbours into one representative;
+# no S/N cut; the DM and width cuts stay; the anti-coincidence filter is left for after
+# the CNN (it must count only the candidates the CNN keeps: noise peaks in every beam
+# would otherwise make every arrival time look coincident).
+RANKER_OPT = {"min_pts": 1, "snr_min": 0.0, "coinc_min_beams": 1 << 30}
+
+
+def ranker_path(spl, cands, tsamp, n_beams, score_fn, threshold=0.0):
+    """Optimisation with RANKER_OPT, the CNN (score_fn: records -> logits), then the
+    anti-coincidence filter on the records whose logit is >= threshold.  Returns
+    (final records, scored records, their logits)."""
+    surv = spl.optimise_plain(cands, tsamp, n_beams, **RANKER_OPT)
+    if surv.size == 0:
+        return surv, surv, np.zeros(0, np.float32)
+    lg = score_fn(surv)
+    final = spl.anti_coincidence(surv[lg >= threshold], tsamp, n_beams)
+    return final, surv, lg
 
 
 def band_delay_per_dm(pd) -> float:
@@ -148,18 +162,12 @@ class Stage:
     def plain(self, cands, **kw):
         return self.spl.optimise_plain(cands, self.tsamp, len(self.pds), **kw)
 
-    def ranked(self, cands, ranker, **kw):
+    def ranked(self, cands, ranker):
         """The ranker path: the optimisation stage with the CNN in place of the density
-        test and the S/N cut (RANKER_OPT: DBSCAN groups neighbours but keeps single
-        points), then the CNN keeps probability >= 0.5."""
-        import torch
-        surv = self.plain(cands, **{**RANKER_OPT, **kw})
-        if surv.size == 0:
-            return surv, np.zeros(0, np.float32)
-        logits = ranker.score(self.snippets(surv))
-        torch.cuda.synchronize()
-        lg = logits.cpu().numpy()
-        return surv[lg >= 0.0], lg
+        test and the S/N cut, the CNN keeping probability >= 0.5 before the
+        anti-coincidence filter.  Returns (final, scored records, logits)."""
+        return ranker_path(self.spl, cands, self.tsamp, len(self.pds),
+                           lambda recs: ranker.score(self.snippets(recs)).cpu().numpy())
 
 
 def mine(spl, pds, n_batches, seed0, neg_ratio=1.0, log=print, **burst_kw):
@@ -240,9 +248,7 @@ def evaluate(spl, pds, ranker, n_batches, seed0, log=print, **burst_kw):
         fp = st.plain(cands)
         t0 = time.time()
         if ranker is not None:
-            surv = st.plain(cands, **RANKER_OPT)
-            lg = ranker.score(st.snippets(surv)).cpu().numpy() if surv.size else np.zeros(0, np.float32)
-            fr = surv[lg >= 0.0]
+            fr, surv, lg = st.ranked(cands, ranker)
         else:
             surv, lg, fr = fp.copy(), np.zeros(fp.size, np.float32), fp.copy()
         torch.cuda.synchronize()
@@ -272,16 +278,33 @@ def evaluate(spl, pds, ranker, n_batches, seed0, log=print, **burst_kw):
     target = res["plain"]["false_alarms"]
     m = match(scored, pulses_all, pds_all)
     fa_mask = (m < 0) & ~on_track(scored, pulses_all, pds_all)
+    key = {(int(r["beam"]), int(r["dm_index"]), int(r["t_sample"])): i for i, r in enumerate(scored)}
+    tsamp_all = np.array([pd["tsamp"] for pd in pds_all], np.float64)
     n_inj = res["plain"]["injected"]
     best = None
-    for tau in np.unique(np.concatenate([logits, [np.inf]])):
-        keep = logits >= tau
-        fa = int(np.sum(keep & fa_mask))
+    taus = np.unique(np.concatenate([np.quantile(logits, np.linspace(0.0, 1.0, 401)) if logits.size else [],
+                                     [np.inf]]))
+    nbb = len(pds)   # beams per batch: the filter runs within each batch
+
+    def filtered(sel):
+        out = []
+        for b0 in range(0, len(pulses_all), nbb):
+            part = sel[(sel["beam"] >= b0) & (sel["beam"] < b0 + nbb)].copy()
+            part["beam"] -= b0
+            f = spl.anti_coincidence(part, tsamp_all[b0:b0 + nbb], nbb)
+            f["beam"] += b0
+            out.append(f)
+        return np.concatenate(out) if out else sel[:0]
+
+    for tau in taus:
+        fin = filtered(scored[logits >= tau]) if np.isfinite(tau) else scored[:0]
+        idx = np.array([key[(int(r["beam"]), int(r["dm_index"]), int(r["t_sample"]))] for r in fin], np.int64)
+        fa = int(np.sum(fa_mask[idx])) if idx.size else 0
         if fa <= target:
-            found = {(int(scored[i]["beam"]), int(m[i])) for i in np.nonzero(keep & (m >= 0))[0]}
+            found = {(int(scored[i]["beam"]), int(m[i])) for i in idx if m[i] >= 0}
             best = {"threshold_logit": float(tau), "recall": len(found) / max(1, n_inj), "recovered": len(found),
                     "false_alarms": fa, "false_alarms_per_beam_block": fa / max(1, len(pulses_all)),
-                    "kept": int(keep.sum())}
+                    "kept": int(idx.size)}
             break
     res["ranker_at_plain_false_alarms"] = best
     return res

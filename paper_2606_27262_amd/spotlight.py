@@ -118,6 +118,7 @@ _sig("spl_batch_stage_times", [_P, _P, _P, _I32])
 _sig("spl_debug_mu_sigma", [_P, _P, _P, _I64, _P, _P, _P])
 _sig("spl_opt_defaults", [ctypes.POINTER(_OptParams)], None)
 _sig("spl_optimise_plain", [_P, _I64, _P, _I32, ctypes.POINTER(_OptParams), _P, _I64, ctypes.POINTER(_I64)])
+_sig("spl_anti_coincidence", [_P, _I64, _P, _I32, ctypes.POINTER(_OptParams), _P, _I64, ctypes.POINTER(_I64)])
 
 
 class _RankerOpts(ctypes.Structure):
@@ -381,6 +382,18 @@ def optimise_plain(cands: np.ndarray, tsamp_of_beam, n_beams: int, **kw) -> np.n
     p = opt_params(**kw)
     _check(_lib.spl_optimise_plain(c.ctypes.data if c.size else None, c.size, ts.ctypes.data, int(n_beams),
                                    ctypes.byref(p), out.ctypes.data, out.size, ctypes.byref(n_out)))
+    return out[:n_out.value].copy()
+
+
+def anti_coincidence(cands: np.ndarray, tsamp_of_beam, n_beams: int, **kw) -> np.ndarray:
+    """The plain path's anti-coincidence filter alone, on host records."""
+    c = np.ascontiguousarray(cands, dtype=CAND_DTYPE)
+    ts = np.ascontiguousarray(tsamp_of_beam, np.float64)
+    out = np.zeros(max(1, c.size), CAND_DTYPE)
+    n_out = _I64()
+    p = opt_params(**kw)
+    _check(_lib.spl_anti_coincidence(c.ctypes.data if c.size else None, c.size, ts.ctypes.data, int(n_beams),
+                                     ctypes.byref(p), out.ctypes.data, out.size, ctypes.byref(n_out)))
     return out[:n_out.value].copy()
 
 

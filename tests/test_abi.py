@@ -176,3 +176,29 @@ def test_ranker_handle_validation():
     # about 14.3 MB of activations per candidate plus weights, moments and tables
     per = (sizes[2] - sizes[1]) / 32
     assert 13e6 < per < 16e6, per
+
+
+def test_anti_coincidence_equals_oracle():
+    """The library's anti-coincidence step alone equals the oracle's on random records
+    crowded in time, across the beam-count threshold and the 50% rule."""
+    rng = np.random.default_rng(17)
+    for n_beams, n in ((2, 40), (3, 60), (8, 200), (24, 500)):
+        c = np.zeros(n, oracle.CAND_DTYPE)
+        c["beam"] = rng.integers(0, n_beams, n)
+        c["dm_index"] = rng.integers(0, 100, n)
+        c["t_sample"] = rng.integers(0, 16384, n)
+        # interference events: records in about 70% of the beams at nearly the same time
+        for e in range(5):
+            T = int(rng.integers(100, 16000))
+            idx = rng.choice(n, size=n // 10, replace=False)
+            c["t_sample"][idx] = T + rng.integers(-10, 11, idx.size)
+            c["beam"][idx] = rng.choice(n_beams, size=idx.size, replace=True) if n_beams > 3 else c["beam"][idx]
+        c["dm"] = c["dm_index"] * 1.0
+        c["snr"] = rng.uniform(6, 20, n).astype(np.float32)
+        c["width"] = 1
+        ts = np.full(n_beams, 1.31072e-3)
+        ref = oracle.anti_coincidence(c, ts, n_beams)
+        got = spl.anti_coincidence(c.astype(spl.CAND_DTYPE), ts, n_beams)
+        assert np.array_equal(got.view(np.int32), ref.view(np.int32)), n_beams
+        if n_beams >= 3:
+            assert 0 < ref.size < c.size   # the filter acted
