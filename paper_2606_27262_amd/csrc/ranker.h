@@ -10,8 +10,14 @@ hipError_t launch_snippets(const DevBeam *beams, int nbeams, const spl_candidate
                            hipStream_t s);
 hipError_t launch_gemm(const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb, float *C, int64_t ldc, int M,
                        int N, int K, int splits, bool accumulate, hipStream_t s);
-hipError_t launch_im2col(const uint16_t *in, int nchw, int N, int nvalid, int H, int W, int Cin, int Kp, int flip,
-                         uint16_t *out, hipStream_t s);
+// Implicit-GEMM convolution (mode 0: first layer, NCHW 2 channels; 1: forward, NHWC 32
+// channels; 2: input gradient, NHWC 32 channels, flipped taps) into C [N*H*W][32] FP32.
+hipError_t launch_conv(int mode, const uint16_t *X, int N, int nvalid, int H, int W, const uint16_t *Wt, int ldw,
+                       float *C, hipStream_t s);
+// Weight gradient partials part[nparts][K][32] (mode 0: K = 32, first layer; 1: K = 288).
+hipError_t launch_wgrad(int mode, const uint16_t *X, int N, int nvalid, int H, int W, const uint16_t *dZ, float *part,
+                        int nparts, hipStream_t s);
+hipError_t launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s);
 hipError_t launch_transpose16(const uint16_t *in, int64_t rows, int64_t cols, int64_t ldi, uint16_t *out, int64_t ldo,
                               hipStream_t s);
 hipError_t launch_conv_epilogue(const float *Z, const float *bias, int N, int H, int W, uint16_t *out, uint8_t *arg,

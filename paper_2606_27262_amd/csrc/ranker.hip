@@ -6,8 +6,8 @@
 // accumulation; activations are stored as BF16 (round to nearest even), weights are kept
 // in FP32 (Adam) and packed to BF16 for the GEMMs.
 //
-// Activation layout: NHWC.  Convolutions use im2col buffers [pixels][K] with
-// K = (ky*3 + kx)*Cin + ci, padded with zeros to a multiple of 32.
+// Activation layout: NHWC.  Convolutions are implicit GEMMs over K = (ky*3 + kx)*Cin + ci
+// (padded with zeros to a multiple of 32), reading the activation directly.
 #include <hip/hip_runtime.h>
 
 #include "ranker.h"
@@ -158,31 +158,175 @@ __global__ __launch_bounds__(256) void k_gemm(const uint16_t *__restrict__ A, in
     }
 }
 
-// ------------------------------------------------------------------- im2col
-// out[p][k] for p = (n, h, w), k < Kp: k = (ky*3 + kx)*Cin + ci (zero for k >= 9*Cin); the
-// source pixel is (h + ky - 1, w + kx - 1), or (h - ky + 1, w - kx + 1) with flip (the
-// transposed convolution of the input gradient); zero outside the image.  Input NHWC,
-// or NCHW when nchw = 1; images n >= nvalid read as zero (batch padding).
-__global__ void k_im2col(const uint16_t *__restrict__ in, int nchw, int N, int nvalid, int H, int W, int Cin, int Kp,
-                         int flip, uint16_t *__restrict__ out) {
+// ------------------------------------------------------- implicit-GEMM convolution
+// Z[p][co] (FP32 [P][32]) = sum over taps t = ky*3 + kx and input channels ci of
+// X[src(p, t)][ci] * Wt[co][t*32 + ci], without an im2col buffer: with 32 input channels
+// each K-step of 32 is one tap, so the MFMA A operand of lane l is the 16 bytes of
+// channels 8(l/16) .. +7 of one source pixel, read straight from the NHWC activation.
+// MODE 0: the first layer: input NCHW with 2 channels (the snippet planes), K = 18 padded
+//         to one K-step of 32 (k = t*2 + ci), images n >= nvalid read as zero.
+// MODE 1: 32 input channels, NHWC, src = (h + ky - 1, w + kx - 1)   (forward).
+// MODE 2: 32 input channels, NHWC, src = (h - ky + 1, w - kx + 1)   (input gradient: the
+//         input is dZ and Wt the weights repacked as [ci][t*32 + co]).
+// Workgroup = 4 wavefronts x 16 pixels; each wavefront computes all 32 columns.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, int N, int nvalid, int H, int W,
+                                              const uint16_t *__restrict__ Wt, int ldw, float *__restrict__ C) {
+    const int lane = lane_id(), wave = wave_id();
     const int64_t P = (int64_t)N * H * W;
-    const int64_t total = P * Kp;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = i / Kp;
-        const int k = (int)(i - p * Kp);
-        uint16_t v = 0;
-        if (k < 9 * Cin) {
-            const int pos = k / Cin, ci = k - pos * Cin;
-            const int ky = pos / 3, kx = pos - ky * 3;
+    const int64_t m_base = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int64_t p = m_base + (lane & 15);
+    const int kq = 8 * (lane >> 4);
+    const int n = (int)(p / ((int64_t)H * W));
+    const int hw = (int)(p - (int64_t)n * H * W);
+    const int h = hw / W, w = hw - (hw / W) * W;
+    const bool row_ok = p < P && n < nvalid;
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint16_t *b0p = Wt + (size_t)(lane & 15) * ldw + kq;
+    const uint16_t *b1p = b0p + (size_t)16 * ldw;
+    if constexpr (MODE == 0) {
+        u16x8 a = zero;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = kq + j;
+            if (k < 18 && row_ok) {
+                const int t = k >> 1, ci = k & 1;
+                const int hs = h + t / 3 - 1, ws = w + t % 3 - 1;
+                if (hs >= 0 && hs < H && ws >= 0 && ws < W) a[j] = X[(((size_t)n * 2 + ci) * H + hs) * W + ws];
+            }
+        }
+        const u16x8 x0 = *(const u16x8 *)b0p, x1 = *(const u16x8 *)b1p;
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, x0),
+                                                       acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, x1),
+                                                       acc1, 0, 0, 0);
+    } else {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ky = t / 3, kx = t % 3;
+            const int hs = MODE == 1 ? h + ky - 1 : h - ky + 1;
+            const int ws = MODE == 1 ? w + kx - 1 : w - kx + 1;
+            u16x8 a = zero;
+            if (row_ok && hs >= 0 && hs < H && ws >= 0 && ws < W)
+                a = *(const u16x8 *)(X + (((size_t)n * H + hs) * W + ws) * 32 + kq);
+            const u16x8 x0 = *(const u16x8 *)(b0p + 32 * t), x1 = *(const u16x8 *)(b1p + 32 * t);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                           __builtin_bit_cast(bf16x8, x0), acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                           __builtin_bit_cast(bf16x8, x1), acc1, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t m = m_base + 4 * (lane >> 4) + i;
+        if (m >= P) continue;
+        C[m * 32 + (lane & 15)] = acc0[i];
+        C[m * 32 + 16 + (lane & 15)] = acc1[i];
+    }
+}
+
+// ------------------------------------------------------- weight gradient (LDS)
+// part[blockIdx.x][k][co] (FP32 [gridDim.x][K][32]) = sum over the pixels p of the
+// workgroup's slabs of A[p][k] * dZ[p][co], A the (implicit) im2col of the layer input:
+// k = t*32 + ci (MODE 1, K = 288, NHWC input) or k = t*2 + ci (MODE 0, K = 32 with 18
+// used, NCHW input of 2 channels, images n >= nvalid read as zero).  A slab is 32
+// consecutive pixels (the MFMA K-step); its dZ and the 9 shifted input tiles are staged
+// transposed in LDS ([channel][pixel]) so that MFMA operands are 16-byte LDS reads.
+// Tiles of the 288 x 32 result (9 taps x 2 x 2 of 16 x 16) are spread over the 4 waves.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ X, int N, int nvalid, int H, int W,
+                                               const uint16_t *__restrict__ dZ, float *__restrict__ part) {
+    constexpr int kTiles = MODE == 0 ? 4 : 36;           // 16x16 tiles of the K x 32 result
+    constexpr int kPerWave = (kTiles + 3) / 4;
+    constexpr int kRows = MODE == 0 ? 32 : 9 * 32;       // staged A^T rows
+    constexpr int kLd = 40;                              // LDS row stride (elements), 80 bytes
+    __shared__ __align__(16) uint16_t sA[kRows * kLd];
+    __shared__ __align__(16) uint16_t sZ[32 * kLd];
+    const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+    const int64_t P = (int64_t)N * H * W;
+    const int64_t nslab = P / 32;   // P is a multiple of 32
+    f32x4 acc[kPerWave];
+#pragma unroll
+    for (int i = 0; i < kPerWave; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kq = 8 * (lane >> 4);
+    for (int64_t sl = blockIdx.x; sl < nslab; sl += gridDim.x) {
+        const int64_t p0 = sl * 32;
+        // dZ^T: thread -> (pixel tid/8, channels 4*(tid%8) .. +3)
+        {
+            const int px = tid >> 3, c4 = (tid & 7) * 4;
+            const uint64_t v = *(const uint64_t *)(dZ + (p0 + px) * 32 + c4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sZ[(c4 + i) * kLd + px] = (uint16_t)(v >> (16 * i));
+        }
+        if constexpr (MODE == 1) {
+            const int px = tid >> 3, c4 = (tid & 7) * 4;
+            const int64_t p = p0 + px;
             const int n = (int)(p / ((int64_t)H * W));
             const int hw = (int)(p - (int64_t)n * H * W);
-            const int h = hw / W, w = hw - h * W;
-            const int hs = flip ? h - ky + 1 : h + ky - 1, wsrc = flip ? w - kx + 1 : w + kx - 1;
-            if (n < nvalid && hs >= 0 && hs < H && wsrc >= 0 && wsrc < W)
-                v = nchw ? in[(((size_t)n * Cin + ci) * H + hs) * W + wsrc]
-                         : in[(((size_t)n * H + hs) * W + wsrc) * Cin + ci];
+            const int h = hw / W, w = hw - (hw / W) * W;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int hs = h + t / 3 - 1, ws = w + t % 3 - 1;
+                uint64_t v = 0;
+                if (hs >= 0 && hs < H && ws >= 0 && ws < W)
+                    v = *(const uint64_t *)(X + (((size_t)n * H + hs) * W + ws) * 32 + c4);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sA[(t * 32 + c4 + i) * kLd + px] = (uint16_t)(v >> (16 * i));
+            }
+        } else {
+            // rows k = t*2 + ci (18 used, 14 zero) x 32 pixels: 1024 entries, 4 per thread
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int idx = tid + 256 * e;
+                const int k = idx >> 5, px = idx & 31;
+                uint16_t v = 0;
+                if (k < 18) {
+                    const int64_t p = p0 + px;
+                    const int n = (int)(p / ((int64_t)H * W));
+                    const int hw = (int)(p - (int64_t)n * H * W);
+                    const int h = hw / W, w = hw - (hw / W) * W;
+                    const int t = k >> 1, ci = k & 1;
+                    const int hs = h + t / 3 - 1, ws = w + t % 3 - 1;
+                    if (n < nvalid && hs >= 0 && hs < H && ws >= 0 && ws < W)
+                        v = X[(((size_t)n * 2 + ci) * H + hs) * W + ws];
+                }
+                sA[k * kLd + px] = v;
+            }
         }
-        out[i] = v;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kPerWave; ++i) {
+            const int tile = wave + 4 * i;
+            if (tile >= kTiles) break;
+            const int it = tile >> 1, jt = tile & 1;   // A^T row tile (16 rows of k), dZ^T row tile (co)
+            const u16x8 a = *(const u16x8 *)(sA + (it * 16 + (lane & 15)) * kLd + kq);
+            const u16x8 b = *(const u16x8 *)(sZ + (jt * 16 + (lane & 15)) * kLd + kq);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                             __builtin_bit_cast(bf16x8, b), acc[i], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    float *out = part + (size_t)blockIdx.x * kRows * 32;
+#pragma unroll
+    for (int i = 0; i < kPerWave; ++i) {
+        const int tile = wave + 4 * i;
+        if (tile >= kTiles) break;
+        const int it = tile >> 1, jt = tile & 1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = it * 16 + 4 * (lane >> 4) + r;
+            out[(size_t)k * 32 + jt * 16 + (lane & 15)] = acc[i][r];
+        }
+    }
+}
+
+// out[i] = sum over parts j of part[j][i], i < n (fixed order: deterministic).
+__global__ void k_sum_parts(const float *__restrict__ part, int nparts, int64_t n, float *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int j = 0; j < nparts; ++j) s += part[(size_t)j * n + i];
+        out[i] = s;
     }
 }
 
@@ -259,7 +403,7 @@ __global__ void k_unpool(const float *__restrict__ dOut, const uint8_t *__restri
             const int64_t p = ((int64_t)n * H + h) * W + w;
             const uint16_t v = (a == j) ? f2bf(g) : (uint16_t)0;
             dZ[p * 32 + co] = v;
-            dZT[(int64_t)co * ldT + p] = v;
+            if (dZT) dZT[(int64_t)co * ldT + p] = v;
         }
     }
     atomicAdd(&sb[co], part);
@@ -414,10 +558,30 @@ hipError_t launch_gemm(const uint16_t *A, int64_t lda, const uint16_t *B, int64_
     return hipSuccess;
 }
 
-hipError_t launch_im2col(const uint16_t *in, int nchw, int N, int nvalid, int H, int W, int Cin, int Kp, int flip,
-                         uint16_t *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_im2col, dim3(grid_1d((int64_t)N * H * W * Kp)), dim3(256), 0, s, in, nchw, N, nvalid, H, W,
-                       Cin, Kp, flip, out);
+hipError_t launch_conv(int mode, const uint16_t *X, int N, int nvalid, int H, int W, const uint16_t *Wt, int ldw,
+                       float *C, hipStream_t s) {
+    const int64_t P = (int64_t)N * H * W;
+    if (P <= 0 || (ldw & 7)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((P + 63) / 64));
+    if (mode == 0) hipLaunchKernelGGL(k_conv<0>, grid, dim3(256), 0, s, X, N, nvalid, H, W, Wt, ldw, C);
+    else if (mode == 1) hipLaunchKernelGGL(k_conv<1>, grid, dim3(256), 0, s, X, N, nvalid, H, W, Wt, ldw, C);
+    else hipLaunchKernelGGL(k_conv<2>, grid, dim3(256), 0, s, X, N, nvalid, H, W, Wt, ldw, C);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_wgrad(int mode, const uint16_t *X, int N, int nvalid, int H, int W, const uint16_t *dZ, float *part,
+                        int nparts, hipStream_t s) {
+    const int64_t P = (int64_t)N * H * W;
+    if (P <= 0 || (P & 31) || nparts < 1) return hipErrorInvalidValue;
+    if (mode == 0) hipLaunchKernelGGL(k_wgrad<0>, dim3(nparts), dim3(256), 0, s, X, N, nvalid, H, W, dZ, part);
+    else hipLaunchKernelGGL(k_wgrad<1>, dim3(nparts), dim3(256), 0, s, X, N, nvalid, H, W, dZ, part);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_parts, dim3(grid_1d(n)), dim3(256), 0, s, part, nparts, n, out);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -6,14 +6,13 @@
 // candidates pads with zero images whose gradients are zero):
 //   layer k = 1..4, input H_k x W_k (64x256, 32x128, 16x64, 8x32), Cin_k (2, 32, 32, 32),
 //   P_k = Nb*H_k*W_k output pixels, K_k = 9*Cin_k padded to a multiple of 32 (32, 288):
-//     A_k   = im2col(X_{k-1})                       [P_k][K_k]  BF16 (kept for backward)
-//     Z     = A_k * Wp_k^T                          [P_k][32]   FP32
+//     Z     = conv(X_{k-1}, Wp_k)                   [P_k][32]   FP32 (implicit GEMM)
 //     X_k   = maxpool(ReLU(Z + b_k)), arg_k          NHWC BF16
 //   Hm = X_4 [Nb][2048 (h,w,c)] * Wf1p^T            [Nb][64]    FP32, then the VALU head.
 // Backward, layer k = 4..1, from dX = dLoss/dX_k (FP32):
-//     dZ, dZ^T = unpool(dX, arg_k); db_k += sums
-//     dW_k^T [K_k][32] = A_k^T * dZ^T^T              (split-K over pixels)
-//     dX = im2col_flipped(dZ) * Wd_k^T               (k > 1), Wd_k[ci][(ky*3+kx)*32+co]
+//     dZ = unpool(dX, arg_k); db_k += sums
+//     dW_k^T [K_k][32] = sum over pixel slabs of A^T dZ (LDS-staged partials, then summed)
+//     dX = conv_flipped(dZ, Wd_k)                    (k > 1), Wd_k[ci][(ky*3+kx)*32+co]
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -58,6 +57,7 @@ constexpr int kW[kLayers] = {256, 128, 64, 32};
 constexpr int kCin[kLayers] = {2, 32, 32, 32};
 constexpr int kKp[kLayers] = {32, 288, 288, 288};
 constexpr int kFcIn = 2048, kFcHidden = 64;
+constexpr int kWgradParts = 512;   // workgroups (and partial sums) of a weight-gradient pass
 
 // Offsets of the parameters in their fixed order.
 struct ParamOffsets {
@@ -101,9 +101,9 @@ struct spl_ranker {
     int64_t pk_wp[kLayers] = {}, pk_wd[kLayers] = {}, pk_f1 = 0, pk_f1t = 0;  // element offsets in packed
     int64_t gc_w[kLayers] = {}, gc_f1 = 0;                                   // element offsets in gc
     // per-pass buffers
-    size_t off_A[kLayers] = {}, off_X[kLayers] = {}, off_arg[kLayers] = {};
+    size_t off_X[kLayers] = {}, off_arg[kLayers] = {};
     size_t off_Z = 0, off_Hm = 0, off_logits = 0, off_dH = 0, off_dHT = 0, off_X4T = 0, off_dX = 0;
-    size_t off_dZ = 0, off_dZT = 0, off_Aflip = 0, off_AT = 0;
+    size_t off_dZ = 0, off_part = 0;
     std::vector<int32_t> pack_idx, gc_idx;
 
     template <class T>
@@ -189,17 +189,12 @@ void layout(spl_ranker *R) {
     R->off_gc = take(R->n_gc * 4);
     R->off_gc_idx = take(R->n_gc * 4);
     const int64_t nb = R->nb;
-    int64_t max_aflip = 0, max_at = 0, max_dz = 0, max_dx = nb * kFcIn;
+    int64_t max_dz = 0, max_dx = nb * kFcIn;
     for (int k = 0; k < kLayers; ++k) {
-        R->off_A[k] = take((size_t)R->P(k) * kKp[k] * 2);
         R->off_X[k] = take((size_t)(R->P(k) / 4) * kCout * 2);
         R->off_arg[k] = take((size_t)(R->P(k) / 4) * kCout);
-        max_at = std::max(max_at, R->P(k) * kKp[k]);
         max_dz = std::max(max_dz, R->P(k) * kCout);
-        if (k > 0) {
-            max_aflip = std::max(max_aflip, R->P(k) * 288);
-            max_dx = std::max(max_dx, R->P(k) * kCout);
-        }
+        if (k > 0) max_dx = std::max(max_dx, R->P(k) * kCout);
     }
     R->off_Z = take((size_t)R->P(0) * kCout * 4);
     R->off_Hm = take((size_t)nb * kFcHidden * 4);
@@ -209,9 +204,7 @@ void layout(spl_ranker *R) {
     R->off_X4T = take((size_t)nb * kFcIn * 2);
     R->off_dX = take((size_t)max_dx * 4);
     R->off_dZ = take((size_t)max_dz * 2);
-    R->off_dZT = take((size_t)max_dz * 2);
-    R->off_Aflip = take((size_t)max_aflip * 2);
-    R->off_AT = take((size_t)max_at * 2);
+    R->off_part = take((size_t)kWgradParts * 288 * kCout * 4);
     R->ws_bytes = align256(off);
 }
 
@@ -238,10 +231,8 @@ spl_status forward(spl_ranker *R, const uint16_t *snip, int n, hipStream_t s) {
     const float *master = R->at<float>(R->off_master);
     float *Z = R->at<float>(R->off_Z);
     for (int k = 0; k < kLayers; ++k) {
-        uint16_t *A = R->at<uint16_t>(R->off_A[k]);
         const uint16_t *in = k == 0 ? snip : R->at<uint16_t>(R->off_X[k - 1]);
-        RK_TRY(launch_im2col(in, k == 0 ? 1 : 0, nb, k == 0 ? n : nb, kH[k], kW[k], kCin[k], kKp[k], 0, A, s));
-        RK_TRY(gemm(A, kKp[k], packed + R->pk_wp[k], kKp[k], Z, kCout, (int)R->P(k), kCout, kKp[k], s));
+        RK_TRY(launch_conv(k == 0 ? 0 : 1, in, nb, k == 0 ? n : nb, kH[k], kW[k], packed + R->pk_wp[k], kKp[k], Z, s));
         RK_TRY(launch_conv_epilogue(Z, master + R->po.cb[k], nb, kH[k], kW[k], R->at<uint16_t>(R->off_X[k]),
                                     R->at<uint8_t>(R->off_arg[k]), s));
     }
@@ -250,17 +241,17 @@ spl_status forward(spl_ranker *R, const uint16_t *snip, int n, hipStream_t s) {
     return SPL_OK;
 }
 
-spl_status backward(spl_ranker *R, int n, const float *labels, float *loss, hipStream_t s) {
+spl_status backward(spl_ranker *R, const uint16_t *snip, int n, const float *labels, float *loss, hipStream_t s) {
     const int nb = R->nb;
     const uint16_t *packed = R->at<uint16_t>(R->off_packed);
     const float *master = R->at<float>(R->off_master);
     float *G = R->at<float>(R->off_g);
     float *gc = R->at<float>(R->off_gc);
+    float *part = R->at<float>(R->off_part);
     const ParamOffsets &po = R->po;
     uint16_t *dH = R->at<uint16_t>(R->off_dH), *dHT = R->at<uint16_t>(R->off_dHT);
     float *dX = R->at<float>(R->off_dX);
-    uint16_t *dZ = R->at<uint16_t>(R->off_dZ), *dZT = R->at<uint16_t>(R->off_dZT);
-    uint16_t *AT = R->at<uint16_t>(R->off_AT), *Aflip = R->at<uint16_t>(R->off_Aflip);
+    uint16_t *dZ = R->at<uint16_t>(R->off_dZ);
     RK_TRY(launch_zero_f32(G, po.total, s));
     RK_TRY(launch_head(R->at<float>(R->off_Hm), master + po.f1b, master + po.f2w, master + po.f2b, n, nb,
                        R->at<float>(R->off_logits), labels, loss, G + po.f2w, G + po.f2b, G + po.f1b, dH, dHT, nb, s));
@@ -271,13 +262,12 @@ spl_status backward(spl_ranker *R, int n, const float *labels, float *loss, hipS
     RK_TRY(gemm(dH, kFcHidden, packed + R->pk_f1t, kFcHidden, dX, kFcIn, nb, kFcIn, kFcHidden, s));
     for (int k = kLayers - 1; k >= 0; --k) {
         const int64_t P = R->P(k);
-        RK_TRY(launch_unpool(dX, R->at<uint8_t>(R->off_arg[k]), nb, kH[k], kW[k], dZ, dZT, P, G + po.cb[k], s));
-        RK_TRY(launch_transpose16(R->at<uint16_t>(R->off_A[k]), P, kKp[k], kKp[k], AT, P, s));
-        RK_TRY(gemm(AT, P, dZT, P, gc + R->gc_w[k], kCout, kKp[k], kCout, (int)P, s));
-        if (k > 0) {
-            RK_TRY(launch_im2col(dZ, 0, nb, nb, kH[k], kW[k], kCout, 288, 1, Aflip, s));
-            RK_TRY(gemm(Aflip, 288, packed + R->pk_wd[k], 288, dX, kCout, (int)P, kCin[k], 288, s));
-        }
+        const uint16_t *in = k == 0 ? snip : R->at<uint16_t>(R->off_X[k - 1]);
+        RK_TRY(launch_unpool(dX, R->at<uint8_t>(R->off_arg[k]), nb, kH[k], kW[k], dZ, nullptr, 0, G + po.cb[k], s));
+        const int parts = (int)std::min<int64_t>(kWgradParts, P / 32);
+        RK_TRY(launch_wgrad(k == 0 ? 0 : 1, in, nb, k == 0 ? n : nb, kH[k], kW[k], dZ, part, parts, s));
+        RK_TRY(launch_sum_parts(part, parts, (int64_t)kKp[k] * kCout, gc + R->gc_w[k], s));
+        if (k > 0) RK_TRY(launch_conv(2, dZ, nb, nb, kH[k], kW[k], packed + R->pk_wd[k], 288, dX, s));
     }
     RK_TRY(launch_scatter_idx(gc, R->at<int32_t>(R->off_gc_idx), R->n_gc, G, s));
     return SPL_OK;
@@ -385,7 +375,7 @@ extern "C" spl_status spl_ranker_backward(spl_ranker *R, const uint16_t *d_snip,
     if (!d_snip || !d_labels || !d_loss) return failf(SPL_E_INVALID_ARG, "NULL argument");
     st = forward(R, d_snip, (int)n, stream);
     if (st != SPL_OK) return st;
-    return backward(R, (int)n, d_labels, d_loss, stream);
+    return backward(R, d_snip, (int)n, d_labels, d_loss, stream);
 }
 
 extern "C" spl_status spl_ranker_train_step(spl_ranker *R, const uint16_t *d_snip, const float *d_labels, int64_t n,

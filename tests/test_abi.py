@@ -173,9 +173,9 @@ def test_ranker_handle_validation():
     # batches are padded to 32 candidates
     assert sizes[0] == sizes[1] and sizes[2] == sizes[3] and sizes[2] > sizes[1]
     assert sizes[1] % 256 == 0
-    # about 14.3 MB of activations per candidate plus weights, moments and tables
+    # about 4.2 MB of activations per candidate plus weights, moments and tables
     per = (sizes[2] - sizes[1]) / 32
-    assert 13e6 < per < 16e6, per
+    assert 3.5e6 < per < 5e6, per
 
 
 def test_anti_coincidence_equals_oracle():
