@@ -186,11 +186,14 @@ def test_c2_full_size(spl, mode):
     assert np.array_equal(g["cands"], rc)
 
 
-def test_tile_shapes_give_identical_results(spl):
-    pd = W.make_plan(512, 300.0, 500.0, 1.31072e-3, 3000, 0.0, 300.0, 100, W.W64)
+@pytest.mark.parametrize("nch", [512, 37])
+def test_tile_shapes_give_identical_results(spl, nch):
+    """Every compiled tile shape and staging depth gives the oracle's results (37
+    channels: odd chunks, padded with the zero row)."""
+    pd = W.make_plan(nch, 300.0, 500.0, 1.31072e-3, 3000, 0.0, 300.0, 100, W.W64)
     p = make_plan(spl, 0, 0, 0, None, 0, plan_dict=pd)
     rng = np.random.default_rng(3)
-    x = rng.integers(0, 256, size=(512, p.info["n_in"]), dtype=np.uint8)
+    x = rng.integers(0, 256, size=(nch, p.info["n_in"]), dtype=np.uint8)
     ref, rc = oracle_run([p], [x])
     batch = spl.Batch([p])
     shapes = ((2, 2, 8), (2, 4, 8), (4, 1, 4), (4, 2, 4), (4, 4, 4), (4, 1, 8), (4, 2, 8), (8, 1, 4),
