@@ -96,6 +96,27 @@ def cpu_baseline(pd, plan, W, target_s=12.0):
                       f"{i['nchans']}-channel block: dedispersion + boxcar search + peak filters"}
 
 
+def counter_traffic(workload, tiles):
+    """HBM bytes per dedispersion launch from the committed rocprofv3 counter summary of
+    this workload (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy), or None when
+    there is none, or the kernel source or the tile shape differ from those the counters
+    were taken with."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"dedisp_{workload}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"^counters: workload=(\S+) kernel=k_dedisp tiles=(\d+),(\d+),(\d+),(\d+) grid=\d+ "
+                  r"fetch_bytes=(\d+) write_bytes=(\d+) kernels_hip_sha256=([0-9a-f]{64})$", open(path).read(), re.M)
+    src = os.path.join(ROOT, "paper_2606_27262_amd", "csrc", "kernels.hip")
+    if not m or m.group(1) != workload or hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(8):
+        return None
+    shape = tuple(int(m.group(i)) for i in range(2, 6))
+    if any((t["dm_per_wave"], t["time_groups"], t["waves"], t["chan_chunk"]) != shape for t in tiles):
+        return None
+    return {"fetch_bytes": int(m.group(6)), "write_bytes": int(m.group(7))}
+
+
 def corner_turn_leg(spl, plan, reps=12, nbuf=4):
     """Corner turn of blocks of the workload's first plan (time-major spectra in,
     channel-major rows out): HIP-event time per launch and the achieved bytes/s, with
@@ -344,6 +365,14 @@ def main():
                      "traffic": None, "launch_ms": avg_launch_s * 1e3,
                      "adds_per_launch": adds_per_launch},
     }
+    tr = counter_traffic(args.workload, [batch.tiles(b) for b in range(nb)])
+    if tr is not None and launches_per_step == 1:
+        out["roofline"]["traffic"] = tr["fetch_bytes"] + tr["write_bytes"]
+        out["roofline"]["traffic_detail"] = {
+            "unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)", **tr,
+            "algorithmic_bytes": sum(p.info["nchans"] * p.info["n_in"] + 4 * p.info["ndm"] * p.info["n_dd"]
+                                     for p in plans),
+            "achieved_GBps": (tr["fetch_bytes"] + tr["write_bytes"]) / avg_launch_s / 1e9}
     if nb > 1 and not args.no_per_beam and mode == "graph":
         out["plain_per_beam"] = per_beam_comparison(spl, plans, blocks, args, cands, stats)
         out["plain_per_beam"]["real_time_beams_per_gpu"] = nb / (out["plain_per_beam"]["ms_per_step"] / 1e3 / block_s)
