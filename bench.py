@@ -30,8 +30,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_workload(name, spl, W):
+def make_workload(name, spl, W, keep_host=False):
     import numpy as np
+    host = []
     if name == "c1":
         pds = [W.plan_c1()]
     elif name == "c2":
@@ -62,10 +63,48 @@ def make_workload(name, spl, W):
             spec, x = W.c2_like_block(pd, n_in, seed, b, 10, dm_max_pulse=0.9 * W.dm_max(pd), zero_dm_rate=0.2)
         blocks.append(spl.upload_block(x[:, :n_in]))
         pulses.append(list(spec.pulses))
+        if keep_host:
+            import torch
+            h = torch.empty(tuple(blocks[-1].shape), dtype=torch.uint8, pin_memory=True)
+            h[:, :n_in] = torch.from_numpy(np.ascontiguousarray(x[:, :n_in]))
+            host.append(h)
         del x
         if b % 8 == 7:
             log(f"generated {b + 1}/{len(pds)} blocks")
-    return pds, plans, blocks, pulses
+    return pds, plans, blocks, pulses, host
+
+
+def end_to_end_leg(spl, pds, host, pulses, args, n_blocks=8, warmup=2):
+    """Sustained stream of blocks (paper_2606_27262_amd.streaming): pinned host-to-device
+    copy of the next block and the candidate stage of the previous block overlap the
+    search of the current one.  The stream repeats the workload's blocks."""
+    import tempfile
+
+    import numpy as np
+
+    from paper_2606_27262_amd import ranking, streaming
+    block_s = max(pd["n_out"] * pd["tsamp"] for pd in pds)
+    ss = streaming.StreamingSearch(spl, pds)
+    ss.attach(tile_cache=None if args.no_autotune else
+              (args.tile_cache or os.path.join(tempfile.gettempdir(), "spotlight_tiles.txt")))
+    out = {"blocks": n_blocks, "warmup": warmup,
+           "h2d_bytes_per_block": int(sum(h.numel() for h in host)),
+           "h2d_GBps_alone": ss.copy_rate(host) / 1e9}
+    legs = [("plain", None)]
+    if not args.no_ranker and all(pd["nchans"] % 64 == 0 for pd in pds):
+        r = spl.Ranker(max_batch=256)
+        r.set_weights(np.load(args.ranker_weights) if os.path.exists(args.ranker_weights)
+                      else ranking.initial_weights(0))
+        legs.append(("ranker", r))
+    for name, ranker in legs:
+        ss.ranker = ranker
+        wall, res = ss.run([host], n_blocks, warmup,
+                           on_block=lambda k, f, nc: ranking.recall_and_false_alarms(f, pulses, pds))
+        out[name] = {"ms_per_block": wall * 1e3, "real_time_beams_per_gpu": len(pds) * block_s / wall,
+                     "recall": float(np.mean([q["recall"] for q in res])),
+                     "false_alarms_per_beam_block": float(np.mean([q["false_alarms"] for q in res])) / len(pds)}
+    del ss
+    return out
 
 
 def cpu_baseline(pd, plan, W, target_s=12.0):
@@ -258,6 +297,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (calibrates HBM byte counters)")
     ap.add_argument("--no-ranker", action="store_true", help="skip the candidate-ranker leg")
+    ap.add_argument("--e2e-blocks", type=int, default=8,
+                    help="blocks of the end-to-end stream leg of a multi-beam workload (0: skip)")
     ap.add_argument("--no-per-beam", action="store_true",
                     help="skip the comparison run of a multi-beam workload in plain per-beam mode")
     ap.add_argument("--ranker-weights", default=os.path.join(ROOT, "paper_2606_27262_amd", "data",
@@ -282,7 +323,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    pds, plans, blocks, pulses = make_workload(args.workload, spl, W)
+    e2e = args.e2e_blocks > 0 and args.workload in ("c3", "c4")
+    pds, plans, blocks, pulses, host = make_workload(args.workload, spl, W, keep_host=e2e)
     nb = len(plans)
     mode = args.mode
     if mode == "auto":
@@ -382,6 +424,10 @@ def main():
         log("ranker leg")
         out["ranker"] = ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, args, ms_step,
                                    block_s)
+    if e2e:
+        log("end-to-end stream")
+        del batch
+        out["end_to_end"] = end_to_end_leg(spl, pds, host, pulses, args, n_blocks=args.e2e_blocks)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(pds[0], plans[0], W)
