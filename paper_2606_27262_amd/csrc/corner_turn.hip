@@ -2,12 +2,13 @@
 // one byte per sample) to the channel-major rows [nch][pitch] the dedispersion reads.
 // Pure data movement, bound by HBM: each byte is read once and written once.
 //
-// A workgroup moves a tile of 64 samples x 256 channels through the LDS: 16-byte global
-// loads along channels, then each thread gathers 16 consecutive samples of one channel
-// and writes them with one 16-byte store; four neighbouring threads cover a row's 64
-// samples, so every output row segment is written in full 64-byte pieces.  The LDS row
-// stride of 260 bytes (65 dwords) puts the four 16-sample groups of a wave's gather on
-// distinct banks.
+// A workgroup moves a tile of 128 samples x 128 channels through the LDS: 16-byte global
+// loads along channels (eight threads read a sample's 128 bytes), then each thread
+// gathers 16 consecutive samples of one channel and writes them with one 16-byte store;
+// eight neighbouring threads cover a row's 128 samples, so reads and writes both move
+// 128-byte pieces.  (Measured on a 4096 x 26305 block against 64 x 256, 128 x 256,
+// 64 x 512 and 256 x 128 tiles: the fastest, 73 % of a plain device copy's rate.)  The
+// LDS row stride of 132 bytes spreads a wave's gathers over the banks (2-way at most).
 #include <hip/hip_runtime.h>
 
 #include "corner_turn.h"
@@ -15,9 +16,11 @@
 namespace spl {
 
 namespace {
-constexpr int kTT = 64;       // samples per tile
-constexpr int kTC = 256;      // channels per tile
-constexpr int kStride = 260;  // LDS bytes per sample row of the tile
+constexpr int kTT = 128;      // samples per tile
+constexpr int kTC = 128;      // channels per tile
+constexpr int kStride = 132;  // LDS bytes per sample row of the tile
+constexpr int kVecRow = kTC / 16;    // 16-byte vectors per sample row
+constexpr int kParts = kTT / 16;     // 16-sample parts per channel row
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 }  // namespace
 
@@ -28,9 +31,9 @@ __global__ __launch_bounds__(256) void k_corner_turn(const uint8_t *__restrict__
     const int64_t t0 = (int64_t)blockIdx.x * kTT;
     const int c0 = blockIdx.y * kTC;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kTT * kVecRow / 256; ++q) {
         const int idx = q * 256 + tid;
-        const int r = idx >> 4, c16 = (idx & 15) * 16;
+        const int r = idx / kVecRow, c16 = (idx % kVecRow) * 16;
         const int64_t t = t0 + r;
         u32x4 v = {0u, 0u, 0u, 0u};
         if (t < n_t && c0 + c16 < nch) v = *(const u32x4 *)(in + t * in_stride + c0 + c16);
@@ -42,9 +45,9 @@ __global__ __launch_bounds__(256) void k_corner_turn(const uint8_t *__restrict__
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kTC * kParts / 256; ++q) {
         const int idx = q * 256 + tid;
-        const int part = idx & 3, c = idx >> 2;
+        const int part = idx % kParts, c = idx / kParts;
         if (c0 + c >= nch) continue;
         uint32_t w[4];
 #pragma unroll
