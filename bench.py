@@ -238,6 +238,24 @@ def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, arg
     kept, surv, _ = ranking.ranker_path(spl, recs, tsamp, nb, score)
     n_scored = surv.size
     t_rank = time.perf_counter() - t0
+    snip_leg = None
+    if surv.size:
+        # the snippet kernel alone on the scored records: bytes it must move per candidate
+        # = 64 DM-transform rows x 256 int32 + nch x 256 block bytes read, 64 KiB written
+        dev = torch.from_numpy(np.ascontiguousarray(surv).view(np.int32).reshape(-1, 8).copy()).cuda()
+        buf = torch.empty((surv.size, 2, 64, 256), dtype=torch.int16, device="cuda")
+        spl.snippets(batch, dev, out=buf)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            spl.snippets(batch, dev, out=buf)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        nch = [p.info["nchans"] for p in plans]
+        per_cand = [64 * 256 * 4 + nch[int(b)] * 256 + 2 * 64 * 256 * 2 for b in surv["beam"]]
+        snip_leg = {"candidates": int(surv.size), "launch_ms": ms, "bytes": int(sum(per_cand)),
+                    "achieved_GBps": sum(per_cand) / (ms / 1e3) / 1e9, "peak_GBps": 8000.0}
     pr = ranking.recall_and_false_alarms(fp, pulses, pds)
     rr = ranking.recall_and_false_alarms(kept, pulses, pds)
 
@@ -267,6 +285,7 @@ def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, arg
         "weights": "trained" if trained else "untrained (initial weights)",
         "plain_path": {**pr, "host_ms": t_plain * 1e3},
         "ranker_path": {**rr, "scored": int(n_scored), "stage_ms": t_rank * 1e3},
+        "snippets": snip_leg,
         # the candidate stage after the search of the same block (serial), or overlapped
         # with the search of the next block (the stage runs on the host and the GPU's
         # snippets and CNN take a few ms)

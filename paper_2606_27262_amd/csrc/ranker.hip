@@ -30,19 +30,25 @@ __device__ inline uint16_t f2bf(float f) {   // round to nearest even (finite in
 __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // ----------------------------------------------------------------- snippets
-// One workgroup (256 threads, one per column) per candidate.  Plane 0: rows d*-32..d*+31
-// of the DM transform over t*-128..t*+127, each row standardised by the search's own
-// (mu, sigma) of the segment of t*.  Plane 1: 64 sub-bands of nch/64 adjacent channels
-// summed along the delays of trial d*, each standardised over its valid samples with the
-// same exact-moment recipe.  Values float((v - mu)/sigma) in binary64 -> BF16; entries
-// outside the DM range or outside [0, n_dd) are 0.
+// One workgroup (256 threads) per candidate.  Plane 0: rows d*-32..d*+31 of the DM
+// transform over t*-128..t*+127 (thread = column), each row standardised by the search's
+// own (mu, sigma) of the segment of t*.  Plane 1: 64 sub-bands of nch/64 adjacent
+// channels summed along the delays of trial d*, each standardised over its valid samples
+// with the same exact-moment recipe.  Values float((v - mu)/sigma) in binary64 -> BF16;
+// entries outside the DM range or outside [0, n_dd) are 0.
+// Plane 1 work split: thread (g = tid / 16, q = tid % 16) adds samples 16q .. 16q+15 of
+// channels g, g+16, ... of a sub-band, reading each channel's 16 bytes as five aligned
+// dwords and accumulating them as 16-bit pairs (as the dedispersion kernel does); the 16
+// channel groups are then summed through the LDS.
 __global__ __launch_bounds__(256) void k_snippets(const DevBeam *__restrict__ beams, int nbeams,
                                                   const spl_candidate *__restrict__ cands, int64_t n,
                                                   uint16_t *__restrict__ out) {
-    // 32 sub-bands at a time (33 KB of LDS, so that several workgroups share a CU)
-    __shared__ int32_t sub[32][256];
-    __shared__ double smu[32], ssg[32];
+    constexpr uint32_t kSelEven = 0x0C020C00u;   // bytes 0, 2 -> 16-bit fields
+    constexpr uint32_t kSelOdd = 0x0C030C01u;    // bytes 1, 3 -> 16-bit fields
+    __shared__ int32_t red[16][256];
+    __shared__ int64_t sh[3][4];
     const int col = threadIdx.x, lane = lane_id(), wave = wave_id();
+    const int g = col >> 4, q = col & 15;
     for (int64_t c = blockIdx.x; c < n; c += gridDim.x) {
         const spl_candidate cd = cands[c];
         uint16_t *o0 = out + (size_t)c * 2 * 64 * 256;
@@ -73,45 +79,76 @@ __global__ __launch_bounds__(256) void k_snippets(const DevBeam *__restrict__ be
         }
         const int per = B.nch / 64;
         const int32_t *drow = B.delays + (size_t)ds * B.nch;
-        for (int half = 0; half < 2; ++half) {
-            for (int k = 0; k < 32; ++k) {
-                int32_t s = 0;
-                const int k0 = (32 * half + k) * per;
-                if (valid)
-                    for (int ch = k0; ch < k0 + per; ++ch) s += B.x[(size_t)ch * B.pitch + t + drow[ch]];
-                sub[k][col] = s;
-            }
-            __syncthreads();
-            // exact moments of each sub-band over the valid columns (wave w: sub-bands 8w .. 8w+7)
-            for (int k = 8 * wave; k < 8 * wave + 8; ++k) {
-                int64_t s1 = 0, s2 = 0, nv = 0;
-                for (int j = lane; j < 256; j += 64) {
-                    const int tj = ts - 128 + j;
-                    if (tj >= 0 && tj < B.n_dd) {
-                        const int64_t v = sub[k][j];
-                        s1 += v;
-                        s2 += v * v;
-                        nv += 1;
+        const int ta = ts - 128 + 16 * q;   // the thread's first sample of plane 1
+        const bool all_valid = ta >= 0 && ta + 15 < B.n_dd;
+        const bool any_valid = ta + 15 >= 0 && ta < B.n_dd;
+        for (int k = 0; k < 64; ++k) {
+            uint32_t ae[4] = {0u, 0u, 0u, 0u}, ao[4] = {0u, 0u, 0u, 0u};
+            if (any_valid) {
+                for (int ch = k * per + g; ch < (k + 1) * per; ch += 16) {
+                    const uint8_t *row = B.x + (size_t)ch * B.pitch;
+                    const int64_t off = (int64_t)ta + drow[ch];
+                    uint32_t d4[4];
+                    if (all_valid && (off & ~(int64_t)3) + 20 <= B.pitch) {
+                        const uint32_t *w = (const uint32_t *)(row + (off & ~(int64_t)3));
+                        const uint32_t w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3], w4 = w[4];
+                        const uint32_t sa = (uint32_t)(off & 3);
+                        d4[0] = __builtin_amdgcn_alignbyte(w1, w0, sa);
+                        d4[1] = __builtin_amdgcn_alignbyte(w2, w1, sa);
+                        d4[2] = __builtin_amdgcn_alignbyte(w3, w2, sa);
+                        d4[3] = __builtin_amdgcn_alignbyte(w4, w3, sa);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            uint32_t v = 0u;
+#pragma unroll
+                            for (int b = 0; b < 4; ++b) {
+                                const int tj = ta + 4 * i + b;
+                                if (tj >= 0 && tj < B.n_dd) v |= (uint32_t)row[off + 4 * i + b] << (8 * b);
+                            }
+                            d4[i] = v;
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        ae[i] += __builtin_amdgcn_perm(d4[i], d4[i], kSelEven);
+                        ao[i] += __builtin_amdgcn_perm(d4[i], d4[i], kSelOdd);
                     }
                 }
-                s1 = wave_sum(s1);
-                s2 = wave_sum(s2);
-                nv = wave_sum(nv);
-                if (lane == 0) {
-                    double mu = 0.0, sg = 0.0;
-                    if (nv > 0) mu_sigma(nv, s1, s2, mu, sg);
-                    smu[k] = mu;
-                    ssg[k] = sg;
-                }
+            }
+            __syncthreads();   // the previous sub-band's partial sums are no longer read
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                red[g][16 * q + 4 * i + 0] = (int32_t)(ae[i] & 0xFFFFu);
+                red[g][16 * q + 4 * i + 2] = (int32_t)(ae[i] >> 16);
+                red[g][16 * q + 4 * i + 1] = (int32_t)(ao[i] & 0xFFFFu);
+                red[g][16 * q + 4 * i + 3] = (int32_t)(ao[i] >> 16);
             }
             __syncthreads();
-            for (int k = 0; k < 32; ++k) {
-                float v = 0.f;
-                if (valid && ssg[k] > 0.0) v = (float)(((double)sub[k][col] - smu[k]) / ssg[k]);
-                o1[(32 * half + k) * 256 + col] = f2bf(v);
+            int32_t sv = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) sv += red[j][col];
+            // exact moments of the sub-band over the valid columns
+            int64_t s1 = valid ? (int64_t)sv : 0, s2 = valid ? (int64_t)sv * sv : 0, nv = valid ? 1 : 0;
+            s1 = wave_sum(s1);
+            s2 = wave_sum(s2);
+            nv = wave_sum(nv);
+            if (lane == 0) {
+                sh[0][wave] = s1;
+                sh[1][wave] = s2;
+                sh[2][wave] = nv;
             }
             __syncthreads();
+            const int64_t S1 = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+            const int64_t S2 = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+            const int64_t NV = sh[2][0] + sh[2][1] + sh[2][2] + sh[2][3];
+            double mu = 0.0, sg = 0.0;
+            if (NV > 0) mu_sigma(NV, S1, S2, mu, sg);
+            float v = 0.f;
+            if (valid && sg > 0.0) v = (float)(((double)sv - mu) / sg);
+            o1[k * 256 + col] = f2bf(v);
         }
+        __syncthreads();   // sh and red are reused by the next candidate
     }
 }
 
