@@ -13,6 +13,8 @@ Workloads (synthetic stand-ins for uGMRT beam data, seeded):
       trials 0-1000 and 4096 ch 550-750 MHz / 1.31072 ms / 16384 samples / 3072 trials
       0-3000, zero-DM RFI bursts, persistent launch in a hipGraph
   c1  1 beam, 256 ch 300-500 MHz, 8192 samples, 128 trials 0-500, widths 1..64
+  c2s, c3s  as c2 / c3 searched to DM 2000 with smearing-limited sub-ranges (5157 trials
+      in steps 0.25, 0.5 and 1: spl_plan_smearing_ranges, 10% S/N loss half a step off)
 """
 import argparse
 import json
@@ -41,6 +43,11 @@ def make_workload(name, spl, W, keep_host=False):
         pds = W.batch_c3_plans()
     elif name == "c4":
         pds = W.batch_c4_plans()
+    elif name in ("c2s", "c3s"):
+        # the 4096-channel band searched to DM 2000 with smearing-limited sub-ranges
+        pd = W.plan_c2()
+        pd["dm_ranges"] = spl.smearing_ranges(pd["nchans"], pd["fch1"], pd["foff"], pd["tsamp"], 0.0, 2000.0, 0.1)
+        pds = [pd] if name == "c2s" else [dict(pd) for _ in range(24)]
     else:
         raise SystemExit(f"unknown workload {name}")
     plans, cache = [], {}
@@ -50,14 +57,14 @@ def make_workload(name, spl, W, keep_host=False):
             cache[key] = spl.Plan.from_dict(pd)
         plans.append(cache[key])
     blocks, pulses = [], []
-    seed = {"c1": 1, "c2": 2, "c3": 3, "c4": 4}[name]
+    seed = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c2s": 2, "c3s": 3}[name]
     for b, (pd, p) in enumerate(zip(pds, plans)):
         n_in = p.info["n_in"]
         if name == "c1":
             spec, x = W.c1_block(n_in, seed=seed)
-        elif name == "c2":
+        elif name in ("c2", "c2s"):
             spec, x = W.c2_like_block(pd, n_in, seed, b, 20)
-        elif name == "c3":
+        elif name in ("c3", "c3s"):
             spec, x = W.c2_like_block(pd, n_in, seed, b, 10)
         else:
             spec, x = W.c2_like_block(pd, n_in, seed, b, 10, dm_max_pulse=0.9 * W.dm_max(pd), zero_dm_rate=0.2)
@@ -156,12 +163,180 @@ def cpu_baseline(pd, plan, W, target_s=12.0):
     return out
 
 
+def counter_traffic(workload, tiles):
+    """HBM bytes per dedispersion launch from the committed rocprofv3 counter summary of
+    this workload (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy), or None when
+    there is none, or the kernel source or the tile shape differ from those the counters
+    were taken with."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"dedisp_{workload}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"^counters: workload=(\S+) kernel=k_dedisp tiles=(\d+),(\d+),(\d+),(\d+) grid=\d+ "
+                  r"fetch_bytes=(\d+) write_bytes=(\d+) kernels_hip_sha256=([0-9a-f]{64})$", open(path).read(), re.M)
+    src = os.path.join(ROOT, "paper_2606_27262_amd", "csrc", "kernels.hip")
+    if not m or m.group(1) != workload or hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(8):
+        return None
+    shape = tuple(int(m.group(i)) for i in range(2, 6))
+    if any((t["dm_per_wave"], t["time_groups"], t["waves"], t["chan_chunk"]) != shape for t in tiles):
+        return None
+    return {"fetch_bytes": int(m.group(6)), "write_bytes": int(m.group(7))}
+
+
+def corner_turn_leg(spl, plan, reps=12, nbuf=4):
+    """Corner turn of blocks of the workload's first plan (time-major spectra in,
+    channel-major rows out): HIP-event time per launch and the achieved bytes/s, with
+    2 bytes per sample (one read, one write) as the algorithmic traffic.  The launches
+    rotate over nbuf block pairs (0.86 GB for 4096 x 26305 samples), more than the
+    256 MB last-level cache, so the figure is an HBM rate."""
+    import torch
+    n_t, nch = plan.info["n_in"], plan.info["nchans"]
+    src = [torch.randint(0, 256, (n_t, nch), dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
+    dst = [torch.empty((nch, (n_t + 255) // 256 * 256), dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
+    s = torch.cuda.current_stream()
+    for i in range(nbuf):
+        spl.corner_turn(src[i], out=dst[i])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for r in range(reps):
+        spl.corner_turn(src[r % nbuf], out=dst[r % nbuf])
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbps = 2.0 * n_t * nch / (ms / 1e3) / 1e9
+    del src, dst
+    return {"samples": n_t * nch, "launch_ms": ms, "achieved_GBps": gbps, "peak_GBps": 8000.0,
+            "frac": gbps / 8000.0}
+
+
+def per_beam_comparison(spl, plans, blocks, args, cands, stats):
+    """The same blocks searched beam by beam (plain mode: one launch sequence per beam),
+    for the comparison of the batched form with the per-beam pipeline."""
+    import torch
+    b2 = spl.Batch(plans, mode=spl.MODE_PLAIN_PER_BEAM)
+    b2.attach()
+    if not args.no_autotune:
+        import tempfile
+        b2.autotune(blocks, cache_path=args.tile_cache or os.path.join(tempfile.gettempdir(), "spotlight_tiles.txt"))
+    steps = max(2, args.steps // 4)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b2.run(blocks, cands, stats, stream=s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        for _ in range(steps):
+            b2.run(blocks, cands, stats, stream=s)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    del b2
+    return {"ms_per_step": ms, "steps": steps}
+
+
+def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, args, ms_step, block_s):
+    """Candidate stage on the last run's candidates: the plain optimisation path (host)
+    against the ranker path (optimisation with the CNN in place of the density test and
+    the S/N cut, the CNN on device),
+    recall and false alarms on the injected pulses; then the CNN's own throughput in
+    training and inference on batches of 256 snippets."""
+    import numpy as np
+    import torch
+
+    from paper_2606_27262_amd import ranking
+
+    nb = len(plans)
+    with torch.cuda.stream(stream):
+        batch.run(blocks, cands, stats, stream=stream)
+    torch.cuda.synchronize()
+    recs = spl.candidates_to_numpy(cands, stats)
+    tsamp = np.array([pd["tsamp"] for pd in pds], np.float64)
+    ranker = spl.Ranker(max_batch=256)
+    trained = os.path.exists(args.ranker_weights)
+    ranker.set_weights(np.load(args.ranker_weights) if trained else ranking.initial_weights(0))
+    t0 = time.perf_counter()
+    fp = spl.optimise_plain(recs, tsamp, nb)
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+
+    def score(r):
+        dev = torch.from_numpy(np.ascontiguousarray(r).view(np.int32).reshape(-1, 8).copy()).cuda()
+        return ranker.score(spl.snippets(batch, dev)).cpu().numpy()
+
+    kept, surv, _ = ranking.ranker_path(spl, recs, tsamp, nb, score)
+    n_scored = surv.size
+    t_rank = time.perf_counter() - t0
+    snip_leg = None
+    if surv.size:
+        # the snippet kernel alone on the scored records: bytes it must move per candidate
+        # = 64 DM-transform rows x 256 int32 + nch x 256 block bytes read, 64 KiB written
+        dev = torch.from_numpy(np.ascontiguousarray(surv).view(np.int32).reshape(-1, 8).copy()).cuda()
+        buf = torch.empty((surv.size, 2, 64, 256), dtype=torch.int16, device="cuda")
+        spl.snippets(batch, dev, out=buf)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            spl.snippets(batch, dev, out=buf)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        nch = [p.info["nchans"] for p in plans]
+        per_cand = [64 * 256 * 4 + nch[int(b)] * 256 + 2 * 64 * 256 * 2 for b in surv["beam"]]
+        snip_leg = {"candidates": int(surv.size), "launch_ms": ms, "bytes": int(sum(per_cand)),
+                    "achieved_GBps": sum(per_cand) / (ms / 1e3) / 1e9, "peak_GBps": 8000.0}
+    pr = ranking.recall_and_false_alarms(fp, pulses, pds)
+    rr = ranking.recall_and_false_alarms(kept, pulses, pds)
+
+    # throughput of the network itself
+    rng = np.random.default_rng(0)
+    n = 256
+    x = torch.from_numpy(rng.normal(0, 1, size=(n, 2, 64, 256)).astype(np.float32)).cuda()
+    snip = (x.view(torch.int32) >> 16).to(torch.int16)   # truncated BF16 patterns are enough here
+    lab = torch.from_numpy((rng.random(n) < 0.5).astype(np.float32)).cuda()
+    probe = spl.Ranker(max_batch=n)
+    probe.set_weights(ranking.initial_weights(1))
+    flop_fwd = 2.0 * (9 * (2 * 32 * 64 * 256 + 32 * 32 * (32 * 128 + 16 * 64 + 8 * 32))) + 2.0 * (2048 * 64 + 64)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    t_inf = timed(lambda: probe.score(snip), 10)
+    t_trn = timed(lambda: probe.train_step(snip, lab, 1e-4), 10)
+    del probe
+    return {
+        "weights": "trained" if trained else "untrained (initial weights)",
+        "plain_path": {**pr, "host_ms": t_plain * 1e3},
+        "ranker_path": {**rr, "scored": int(n_scored), "stage_ms": t_rank * 1e3},
+        "snippets": snip_leg,
+        # the candidate stage after the search of the same block (serial), or overlapped
+        # with the search of the next block (the stage runs on the host and the GPU's
+        # snippets and CNN take a few ms)
+        "real_time_beams_per_gpu": {
+            "plain_serial": nb / ((ms_step + t_plain * 1e3) / 1e3 / block_s),
+            "plain_overlapped": nb / (max(ms_step, t_plain * 1e3) / 1e3 / block_s),
+            "ranker_serial": nb / ((ms_step + t_rank * 1e3) / 1e3 / block_s),
+            "ranker_overlapped": nb / (max(ms_step, t_rank * 1e3) / 1e3 / block_s)},
+        "cnn": {"batch": n, "flop_forward_per_candidate": flop_fwd,
+                "inference_ms": t_inf * 1e3, "inference_candidates_per_s": n / t_inf,
+                "inference_tflops": n * flop_fwd / t_inf / 1e12,
+                "train_step_ms": t_trn * 1e3, "train_candidates_per_s": n / t_trn,
+                "train_tflops": 3 * n * flop_fwd / t_trn / 1e12,
+                "mfma_peak_tflops_bf16": 2500.0},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c2s", "c3s"])
     ap.add_argument("--mode", default="auto", choices=["auto", "plain", "graph"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default dedispersion tiles")
@@ -195,7 +370,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    e2e = args.e2e_blocks > 0 and args.workload in ("c3", "c4")
+    e2e = args.e2e_blocks > 0 and args.workload in ("c3", "c4", "c3s")
     pds, plans, blocks, pulses, host = make_workload(args.workload, spl, W, keep_host=e2e)
     nb = len(plans)
     mode = args.mode

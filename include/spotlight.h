@@ -119,6 +119,32 @@ typedef struct spl_plan_info {
 } spl_plan_info;
 
 /*
+ * DM sub-ranges whose trial spacing keeps the dispersive smearing small (dedispersion
+ * section: a plan divides the DM range into sub-ranges whose spacing depends on the
+ * sampling time, the channel width and the bandwidth).  The S/N kept by a Gaussian pulse
+ * of FWHM W dedispersed dDM off its DM is (sqrt(pi)/2) erf(z)/z with
+ * z = 6.91e-3 * dDM * B_MHz / (W_ms * nu_GHz^3) (Eq. snrloss and Eq. zetadef; B the
+ * bandwidth nchans*|foff|, nu the centre frequency); the narrowest pulse a trial at DM can
+ * see has W_ms = sqrt(w_min_ms^2 + tsamp_ms^2 + t_chan^2), t_chan = 8.3e-3 * DM *
+ * |foff| / nu_lo_GHz^3 ms the smearing within one channel at the lowest channel centre.
+ * A step s is allowed at DM when the pulse half a step off keeps at least
+ * 1 - max_loss of its S/N.  Steps are powers of two: the first the largest allowed at
+ * dm_min; a sub-range ends at the first of its trials (after the first) where twice its
+ * step is allowed, and the next starts there with the doubled step; trials continue
+ * until the first one >= dm_max.  All in binary64 in this order.
+ */
+typedef struct spl_smearing_opts {
+    double dm_min, dm_max;  /* 0 <= dm_min < dm_max                                  */
+    double max_loss;        /* fraction of S/N a pulse half a step off may lose, (0, 1) */
+    double w_min_s;         /* narrowest intrinsic pulse width considered (>= 0, s)    */
+} spl_smearing_opts;
+
+/* Writes up to `capacity` sub-ranges to `out` and their number to *n_out
+ * (SPL_E_CAPACITY if more are needed). */
+spl_status spl_plan_smearing_ranges(const spl_band *band, const spl_smearing_opts *opts, spl_dm_range *out,
+                                    int32_t capacity, int32_t *n_out);
+
+/*
  * Build a plan: DM trials from the sub-ranges, the integer delay table
  *   delay[d][c] = round-half-away( ((D * DM_d) * (1/f_c^2 - 1/f_ref^2)) / tsamp )
  * of Eq. (1) with D = 4148.8064239 MHz^2 pc^-1 cm^3 s evaluated in binary64 in

@@ -12,6 +12,7 @@ Nothing here is shared with the HIP path.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -89,6 +90,55 @@ def dm_trials(ranges) -> np.ndarray:
     for start, step, n in ranges:
         out.extend(float(start) + float(d) * float(step) for d in range(int(n)))
     return np.asarray(out, dtype=np.float64)
+
+
+def snr_kept(ddm: float, width_ms: float, bw_mhz: float, nu_ghz: float) -> float:
+    """S/N fraction kept by a Gaussian pulse of FWHM width_ms dedispersed ddm off its DM:
+    (sqrt(pi)/2) erf(z)/z with z = 6.91e-3 ddm B / (W nu^3) (Eq. snrloss, Eq. zetadef)."""
+    z = 6.91e-3 * ddm * bw_mhz / (width_ms * (nu_ghz * nu_ghz * nu_ghz))
+    if z == 0.0:
+        return 1.0
+    return (math.sqrt(math.pi) / 2.0) * math.erf(z) / z
+
+
+def smearing_ranges(nch: int, fch1: float, foff: float, tsamp: float, dm_min: float, dm_max: float,
+                    max_loss: float, w_min_s: float = 0.0) -> list:
+    """DM sub-ranges (start, step, n) whose step keeps a pulse half a step off above
+    1 - max_loss of its S/N, for the narrowest pulse a trial at DM can see: FWHM
+    sqrt(w_min^2 + tsamp^2 + t_chan(DM)^2), t_chan = 8.3e-3 DM |foff| / nu_lo^3 ms (the
+    smearing within one channel at the lowest channel centre; Cordes & McLaughlin).
+    The plan is the dedispersion section's: sub-ranges of growing spacing.  Steps are
+    powers of two; a sub-range ends at the first of its trials (not its first) where
+    twice its step is allowed, and trials run to the first one >= dm_max."""
+    edge = [fch1, fch1 + (nch - 1) * foff]
+    lo, hi = min(edge), max(edge)
+    tsamp_ms, w_ms, chan = tsamp * 1e3, w_min_s * 1e3, abs(foff)
+    nu_lo = lo / 1e3
+    nu_c = (0.5 * (lo + hi)) / 1e3
+    bw = nch * abs(foff)
+
+    def ok(step, dm):
+        tc = 8.3e-3 * dm * chan / (nu_lo * nu_lo * nu_lo)
+        width = math.sqrt(w_ms * w_ms + tsamp_ms * tsamp_ms + tc * tc)
+        return snr_kept(0.5 * step, width, bw, nu_c) >= 1.0 - max_loss
+
+    e = 20
+    while not ok(math.ldexp(1.0, e), dm_min):
+        e -= 1
+    ranges = []
+    start, step, i = dm_min, math.ldexp(1.0, e), 0
+    while True:
+        dm = start + i * step
+        if dm >= dm_max:
+            ranges.append((start, step, i + 1))
+            return ranges
+        if i >= 1 and ok(2.0 * step, dm):
+            ranges.append((start, step, i))
+            start, step, i = dm, 2.0 * step, 0
+            if start >= dm_max:
+                ranges.append((start, step, 1))
+                return ranges
+        i += 1
 
 
 def delay_table(nch: int, fch1: float, foff: float, tsamp: float, dms) -> tuple[np.ndarray, int]:

@@ -71,6 +71,11 @@ class _Tiles(ctypes.Structure):
                 ("chan_chunk", ctypes.c_int32), ("waves", ctypes.c_int32)]
 
 
+class _SmearingOpts(ctypes.Structure):
+    _fields_ = [("dm_min", ctypes.c_double), ("dm_max", ctypes.c_double), ("max_loss", ctypes.c_double),
+                ("w_min_s", ctypes.c_double)]
+
+
 class _OptParams(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("min_pts", ctypes.c_int32), ("coinc_min_beams", ctypes.c_int32),
                 ("t_scale_s", ctypes.c_double), ("dm_scale", ctypes.c_double), ("snr_min", ctypes.c_double),
@@ -103,6 +108,8 @@ _sig("spl_plan_query", [_P, ctypes.POINTER(_PlanInfo)])
 _sig("spl_plan_delays", [_P, _P])
 _sig("spl_plan_dms", [_P, _P])
 _sig("spl_plan_destroy", [_P], None)
+_sig("spl_plan_smearing_ranges", [ctypes.POINTER(_Band), ctypes.POINTER(_SmearingOpts), _P, _I32,
+                                  ctypes.POINTER(_I32)])
 _sig("spl_batch_create", [ctypes.POINTER(_P), _I32, ctypes.POINTER(_BatchOpts), ctypes.POINTER(_P)])
 _sig("spl_batch_workspace_size", [_P, ctypes.POINTER(_SZ)])
 _sig("spl_batch_set_workspace", [_P, _P, _SZ])
@@ -161,6 +168,18 @@ def _stream_handle(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def smearing_ranges(nchans, fch1, foff, tsamp, dm_min, dm_max, max_loss=0.1, w_min_s=0.0):
+    """DM sub-ranges [(dm_start, dm_step, n_trials)] with smearing-limited spacing
+    (see spl_plan_smearing_ranges)."""
+    band = _Band(int(nchans), 1, 0, 0, float(fch1), float(foff), float(tsamp))
+    o = _SmearingOpts(float(dm_min), float(dm_max), float(max_loss), float(w_min_s))
+    cap = 64
+    out = (_DMRange * cap)()
+    n = _I32()
+    _check(_lib.spl_plan_smearing_ranges(ctypes.byref(band), ctypes.byref(o), out, cap, ctypes.byref(n)))
+    return [(out[k].dm_start, out[k].dm_step, out[k].n_trials) for k in range(n.value)]
 
 
 class Plan:

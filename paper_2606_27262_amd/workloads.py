@@ -102,9 +102,15 @@ def real_time_s(plan):
 
 
 def describe(plan):
-    s, st, n = plan["dm_ranges"][0]
+    r = plan["dm_ranges"]
+    if len(r) == 1:
+        s, st, n = r[0]
+        dm = f"dm={s}+{st}x{n}"
+    else:
+        dm = (f"dm={r[0][0]}-{r[-1][0] + (r[-1][2] - 1) * r[-1][1]} in {len(r)} ranges "
+              f"(steps {'/'.join(str(x[1]) for x in r)}, {sum(x[2] for x in r)} trials)")
     return (f"{plan['nchans']}ch f1={plan['fch1']:.6f} df={plan['foff']:.6f} "
-            f"ts={plan['tsamp'] * 1e3:.5f}ms n_out={plan['n_out']} dm={s}+{st}x{n} "
+            f"ts={plan['tsamp'] * 1e3:.5f}ms n_out={plan['n_out']} {dm} "
             f"w<= {max(plan['widths'])}")
 
 

@@ -202,3 +202,16 @@ def test_anti_coincidence_equals_oracle():
         assert np.array_equal(got.view(np.int32), ref.view(np.int32)), n_beams
         if n_beams >= 3:
             assert 0 < ref.size < c.size   # the filter acted
+
+
+@pytest.mark.parametrize("band", [W.plan_c1, W.plan_c2, W.plan_band3_c4, W.plan_band4_c4])
+def test_smearing_ranges_equal_oracle(band):
+    p = band()
+    for loss, wmin, lo, hi in ((0.1, 0.0, 0.0, 2000.0), (0.05, 0.0, 3.0, 500.0), (0.2, 1e-3, 0.0, 3000.0)):
+        got = spl.smearing_ranges(p["nchans"], p["fch1"], p["foff"], p["tsamp"], lo, hi, loss, wmin)
+        ref = oracle.smearing_ranges(p["nchans"], p["fch1"], p["foff"], p["tsamp"], lo, hi, loss, wmin)
+        assert got == ref
+        plan = spl.Plan(p["nchans"], p["fch1"], p["foff"], p["tsamp"], 1024, got, (1, 2), 6.0)
+        dms = oracle.dm_trials(got)
+        D, ties = oracle.delay_table(p["nchans"], p["fch1"], p["foff"], p["tsamp"], dms)
+        assert ties == 0 and np.array_equal(plan.delays().astype(np.int64), D)

@@ -154,6 +154,30 @@ def test_c1_full(spl):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
+def test_smearing_plan_batch(spl, mode):
+    """A multi-range plan from the smearing-limited generator (seven sub-ranges, steps
+    1/16 .. 4) on the 256-channel band, two beams with pulses at low and high DM:
+    DM transform and candidates bit for bit."""
+    pd = W.plan_c1()
+    pd["n_out"] = pd["norm_window"] = 3000
+    pd["dm_ranges"] = spl.smearing_ranges(pd["nchans"], pd["fch1"], pd["foff"], pd["tsamp"], 0.0, 500.0, 0.1)
+    assert len(pd["dm_ranges"]) == 7
+    p = make_plan(spl, 0, 0, 0, None, 0, plan_dict=pd)
+    from paper_2606_27262_amd import synth
+    blocks = []
+    for b, dm in enumerate((30.0, 420.0)):
+        spec = W.block_spec(pd, p.info["n_in"], [synth.Pulse(t0=1500.0, dm=dm, fwhm=3.0, snr=25.0)])
+        blocks.append(synth.make_block(spec, 40 + b, b, pd["widths"])[:, :p.info["n_in"]])
+    g = gpu_run(spl, [p, p], blocks, mode=mode)
+    ref, rc = oracle_run([p, p], blocks)
+    compare(g, ref, rc)
+    for b, dm in enumerate((30.0, 420.0)):
+        cb = g["cands"][g["cands"]["beam"] == b]
+        best = cb[np.argmax(cb["snr"])]
+        assert abs(float(best["dm"]) - dm) < 0.05 * dm and abs(int(best["t_sample"]) - 1500) <= 8
+
+
+@pytest.mark.parametrize("mode", [0, 1])
 def test_c2_full_size(spl, mode):
     """4096 channels, 2048 trials, 16384 samples, 20 pulses, 2% RFI: DM-0 row = channel
     sum, sampled DM-transform entries by direct summation, moments, and the candidate

@@ -134,3 +134,66 @@ def test_plan_sizes_match_derived_table():
 def test_dm_250_is_trial_64_in_c1():
     dms = oracle.dm_trials(W.plan_c1()["dm_ranges"])
     assert dms.size == 128 and dms[64] == 250.0 and dms[1] == 3.90625
+
+
+# ---------------------------------------------------------------- smearing-limited plans
+def test_snr_kept_closed_forms():
+    # no offset keeps everything
+    assert oracle.snr_kept(0.0, 1.0, 200.0, 0.65) == 1.0
+    # z = 1: (sqrt(pi)/2) erf(1) = integral of exp(-t^2) over [0, 1] = 0.746824132812427...
+    ddm = 1.0 / (6.91e-3 * 200.0 / (1.0 * 0.65 ** 3))
+    assert abs(oracle.snr_kept(ddm, 1.0, 200.0, 0.65) - 0.7468241328124271) < 1e-14
+    # far off: the sqrt(pi) / (2 z) asymptote of the approximate form
+    z = 6.0
+    assert abs(oracle.snr_kept(z * ddm, 1.0, 200.0, 0.65) * 2 * z / math.sqrt(math.pi) - 1.0) < 1e-15
+
+
+def _ranges_check(nch, fch1, foff, tsamp, lo, hi, loss, wmin=0.0):
+    r = oracle.smearing_ranges(nch, fch1, foff, tsamp, lo, hi, loss, wmin)
+    edge = [fch1, fch1 + (nch - 1) * foff]
+    fl, fh = min(edge), max(edge)
+    bw, nu_c, nu_lo = nch * abs(foff), (fl + fh) / 2e3, fl / 1e3
+
+    def allowed(step, dm):
+        tc = 8.3e-3 * dm * abs(foff) / nu_lo ** 3
+        w = math.sqrt((wmin * 1e3) ** 2 + (tsamp * 1e3) ** 2 + tc ** 2)
+        return oracle.snr_kept(step / 2, w, bw, nu_c) >= 1 - loss
+
+    assert r[0][0] == lo
+    for k, (start, step, n) in enumerate(r):
+        assert n >= 1 and math.frexp(step)[0] == 0.5          # a power of two
+        assert allowed(step, start)
+        if k + 1 < len(r):
+            nxt = r[k + 1]
+            assert nxt[1] == 2 * step and nxt[0] == start + n * step   # contiguous, doubled
+            assert allowed(2 * step, nxt[0])                            # switched when allowed ...
+            assert n == 1 or not allowed(2 * step, start + (n - 1) * step)   # ... and not before
+        else:
+            assert start + (n - 1) * step >= hi and (n == 1 or start + (n - 2) * step < hi)
+    assert not allowed(2 * r[0][1], lo)   # the first step is the largest allowed
+    return r
+
+
+@pytest.mark.parametrize("band", ["c1", "c2", "b3", "b5"])
+def test_smearing_ranges_follow_their_definition(band):
+    bands = {"c1": (256, 499.609375, -0.78125, 1.31072e-3), "c2": (4096, 749.9755859375, -0.048828125, 1.31072e-3),
+             "b3": (2048, 499.951171875, -0.09765625, 0.65536e-3), "b5": (2048, 1459.90234375, -0.1953125, 0.65536e-3)}
+    for loss in (0.05, 0.1, 0.2):
+        r = _ranges_check(*bands[band], 0.0, 2000.0, loss)
+        assert len(r) >= 1
+    # a smaller tolerated loss needs more trials; a wider minimum pulse fewer
+    n = lambda r: sum(x[2] for x in r)
+    assert n(oracle.smearing_ranges(*bands[band], 0.0, 2000.0, 0.05)) > n(oracle.smearing_ranges(*bands[band], 0.0, 2000.0, 0.2))
+    assert n(oracle.smearing_ranges(*bands[band], 0.0, 2000.0, 0.1, 2e-3)) < n(oracle.smearing_ranges(*bands[band], 0.0, 2000.0, 0.1))
+
+
+def test_intra_channel_smearing_constant():
+    """8.3 us per MHz of channel width and unit DM at 1 GHz (Cordes & McLaughlin): at
+    1 GHz with 1 MHz channels a DM of 1000 smears 8.3 ms within a channel; the effective
+    width the generator uses at that DM with 1 ms sampling is sqrt(1 + 8.3^2) ms."""
+    tc = 8.3e-3 * 1000.0 * 1.0 / (1.0 ** 3)
+    assert abs(tc - 8.3) < 1e-12
+    # the generator's first step at DM 1000 equals the one for that width at DM 0
+    r_hi = oracle.smearing_ranges(16, 1008.0, -1.0, 1e-3, 1000.0, 1001.0, 0.1)
+    r_w = oracle.smearing_ranges(16, 1008.0, -1.0, 1e-3, 0.0, 1.0, 0.1, w_min_s=8.3e-3 * 1000 * 1.0 / (0.993 ** 3) * 1e-3)
+    assert r_hi[0][1] == r_w[0][1]
