@@ -210,6 +210,47 @@ def corner_turn_leg(spl, plan, reps=12, nbuf=4):
             "frac": gbps / 8000.0}
 
 
+def injector_leg(spl, W, pds, plans, blocks, pulses, ms_step, reps=5):
+    """Quantised-domain injection of the workload's bursts (the same pulses its blocks
+    carry, each a window of the dispersed template over every channel) into copies of
+    the beams' blocks: HIP-event time per block of all beams (one call per beam), with
+    10 bytes per injected value (signal, random word, sample read and written) as the
+    algorithmic traffic."""
+    import numpy as np
+    import torch
+    from paper_2606_27262_amd import synth
+    work = []
+    for b, (pd, p) in enumerate(zip(pds, plans)):
+        n_in = p.info["n_in"]
+        if not pulses[b]:
+            continue
+        t_start, sig = synth.burst_windows(W.block_spec(pd, n_in, pulses[b]), pulses[b], pd["widths"])
+        words = synth.random_words(1000 + b, sig.shape).view(np.int32)
+        work.append((blocks[b].clone(), n_in, torch.from_numpy(t_start).cuda(), torch.from_numpy(sig).cuda(),
+                     torch.from_numpy(words).cuda()))
+    if not work:
+        return None
+    values = sum(int(s.numel()) for _, _, _, s, _ in work)
+    s = torch.cuda.current_stream()
+
+    def one_block():
+        for blk, n_in, ts, sg, rw in work:
+            spl.inject_quantised(blk, ts, sg, rw, n_t=n_in, stream=s)
+
+    one_block()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        one_block()
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del work
+    return {"bursts": sum(len(x) for x in pulses), "values": values, "ms_per_block": ms,
+            "values_per_s": values / (ms / 1e3), "algorithmic_GBps": 10.0 * values / (ms / 1e3) / 1e9,
+            "frac_of_step": ms / ms_step, "mode": "sample"}
+
+
 def per_beam_comparison(spl, plans, blocks, args, cands, stats):
     """The same blocks searched beam by beam (plain mode: one launch sequence per beam),
     for the comparison of the batched form with the per-beam pipeline."""
@@ -467,6 +508,9 @@ def main():
         out["plain_per_beam"]["real_time_beams_per_gpu"] = nb / (out["plain_per_beam"]["ms_per_step"] / 1e3 / block_s)
     if all(pd["nchans"] % 16 == 0 for pd in pds):
         out["corner_turn"] = corner_turn_leg(spl, plans[0])
+    if any(pulses):
+        log("injector leg")
+        out["injector"] = injector_leg(spl, W, pds, plans, blocks, pulses, ms_step)
     if not args.no_ranker and all(pd["nchans"] % 64 == 0 for pd in pds):
         log("ranker leg")
         out["ranker"] = ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, args, ms_step,

@@ -457,6 +457,49 @@ spl_status spl_anti_coincidence(const spl_candidate *cands, int64_t n, const dou
                                 int32_t n_beams, const spl_opt_params *params, spl_candidate *out,
                                 int64_t capacity, int64_t *n_out);
 
+/* ---------------------------------------------------- quantised-domain injection */
+/*
+ * Injection of a simulated signal into data that is already quantised (the real-time
+ * injector of the injection section; the rules are the appendix on M-bit quantised
+ * streams).  The quantiser maps Gaussian noise N ~ Normal(mu, sigma) to 2^bits states:
+ * state n < 2^bits - 1 ends at edge e_n = mu + (n + 1 - 2^(bits-1) + offset) * level *
+ * sigma, state 0 starts at -inf and the top state ends at +inf.  offset = 0 is the
+ * appendix's quantiser; -0.5 is clip(round(mu + x)) when level * sigma = 1.
+ */
+typedef struct spl_quantiser {
+    int32_t bits;     /* 1..8; one state per byte, 0 .. 2^bits - 1 */
+    int32_t reserved; /* 0 */
+    double mu;        /* noise mean, in the units of the signal */
+    double sigma;     /* noise standard deviation, > 0 */
+    double level;     /* state width in units of sigma, > 0 */
+    double offset;    /* shift of every edge, in states; finite */
+} spl_quantiser;
+
+enum {
+    SPL_INJECT_SAMPLE = 0, /* draw the new state from the transition row (inverse CDF at u) */
+    SPL_INJECT_ARGMAX = 1  /* the most probable state of the row, the smaller one on ties */
+};
+
+/*
+ * Adds n_win windows of signal to a quantised block in place.  Window w adds
+ * d_signal[w][c][j] (FP32, the units of mu and sigma) to sample d_t_start[w][c] + j of
+ * channel c (int32 starts; samples outside [0, n_t) are skipped, so a burst may cross
+ * the block's ends).  A sample in state n with signal S > 0 moves to state k with the
+ * probability P(n -> k) of the appendix's transition matrix: the Gaussian mass of the
+ * part of state n that the shift by S carries into state k, over the mass of state n.
+ * SAMPLE mode takes the smallest k whose cumulative row sum exceeds
+ * u = (d_random[w][c][j] + 1/2) * 2^-32 (caller-supplied uniform 32-bit words, same
+ * layout as d_signal; NULL is allowed in ARGMAX mode).  A sample is left unchanged when
+ * S <= 0 or NaN, when its byte exceeds 2^bits - 1, or when its state has no binary64
+ * Gaussian mass.  Probabilities are evaluated in binary64.
+ * d_block device [nch][pitch] bytes; pitch >= n_t.  Windows of one call must not cover
+ * the same sample twice (such calls race); successive calls on one stream apply in
+ * order.  Asynchronous on `stream`.
+ */
+spl_status spl_inject_quantised(uint8_t *d_block, int64_t pitch, int64_t n_t, int32_t nch, const int32_t *d_t_start,
+                                const float *d_signal, const uint32_t *d_random, int32_t n_win, int32_t n_sig,
+                                const spl_quantiser *q, int32_t mode, hipStream_t stream);
+
 /* ------------------------------------------------------------- test hooks */
 /* The normaliser of the search on device, for parity tests: for i < count,
  * mu[i] = S1/n and sigma[i] = sqrt(n*S2 - S1^2)/n (exact 128-bit difference,

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "corner_turn.h"
+#include "inject.h"
 #include "kernels.h"
 #include "ranker.h"
 #include "spl_internal.h"
@@ -1172,6 +1173,30 @@ extern "C" spl_status spl_corner_turn(const uint8_t *d_in, int64_t n_t, int32_t 
     if (((uintptr_t)d_in & 15) || ((uintptr_t)d_out & 15))
         return fail(SPL_E_INVALID_ARG, "spl_corner_turn: buffers must be 16-byte aligned");
     HIP_TRY(launch_corner_turn(d_in, in_stride, n_t, nch, d_out, pitch, stream));
+    return SPL_OK;
+}
+
+static_assert(SPL_INJECT_ARGMAX == SPL_INJECT_ARGMAX_MODE, "injection mode numbers");
+
+extern "C" spl_status spl_inject_quantised(uint8_t *d_block, int64_t pitch, int64_t n_t, int32_t nch,
+                                           const int32_t *d_t_start, const float *d_signal, const uint32_t *d_random,
+                                           int32_t n_win, int32_t n_sig, const spl_quantiser *q, int32_t mode,
+                                           hipStream_t stream) {
+    if (!q) return fail(SPL_E_INVALID_ARG, "spl_inject_quantised: quantiser is NULL");
+    if (q->bits < 1 || q->bits > 8) return fail(SPL_E_INVALID_ARG, "spl_inject_quantised: bits must be 1..8");
+    if (!(q->sigma > 0) || !std::isfinite(q->sigma) || !(q->level > 0) || !std::isfinite(q->level) ||
+        !std::isfinite(q->mu) || !std::isfinite(q->offset) || !std::isfinite(q->level * q->sigma))
+        return fail(SPL_E_INVALID_ARG, "spl_inject_quantised: need finite mu and offset, sigma > 0, level > 0");
+    if (mode != SPL_INJECT_SAMPLE && mode != SPL_INJECT_ARGMAX)
+        return fail(SPL_E_INVALID_ARG, "spl_inject_quantised: unknown mode %d", mode);
+    if (nch < 1 || n_t < 0 || pitch < n_t || n_win < 0 || n_sig < 0)
+        return fail(SPL_E_INVALID_ARG, "spl_inject_quantised: need nch >= 1, 0 <= n_t <= pitch, n_win, n_sig >= 0");
+    if (n_t == 0 || n_win == 0 || n_sig == 0) return SPL_OK;
+    if (!d_block || !d_t_start || !d_signal) return fail(SPL_E_INVALID_ARG, "spl_inject_quantised: NULL buffer");
+    if (mode == SPL_INJECT_SAMPLE && !d_random)
+        return fail(SPL_E_INVALID_ARG, "spl_inject_quantised: SAMPLE mode needs random words");
+    HIP_TRY(launch_inject(d_block, pitch, n_t, nch, d_t_start, d_signal, mode == SPL_INJECT_SAMPLE ? d_random : nullptr,
+                          n_win, n_sig, q->bits, q->mu, q->sigma, q->level, q->offset, mode, stream));
     return SPL_OK;
 }
 

@@ -133,8 +133,16 @@ class _RankerOpts(ctypes.Structure):
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("reserved1", ctypes.c_float)]
 
 
+class _Quantiser(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mu", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("level", ctypes.c_double), ("offset", ctypes.c_double)]
+
+
+INJECT_SAMPLE, INJECT_ARGMAX = 0, 1
+
 _F32 = ctypes.c_float
 _sig("spl_corner_turn", [_P, _I64, _I32, _I64, _P, _I64, _P])
+_sig("spl_inject_quantised", [_P, _I64, _I64, _I32, _P, _P, _P, _I32, _I32, ctypes.POINTER(_Quantiser), _I32, _P])
 _sig("spl_ranker_snippets", [_P, _P, _I64, _P, _P])
 _sig("spl_ranker_create", [ctypes.POINTER(_RankerOpts), ctypes.POINTER(_P)])
 _sig("spl_ranker_workspace_size", [_P, ctypes.POINTER(_SZ)])
@@ -449,6 +457,35 @@ def corner_turn(x_tc, out=None, pitch=None, stream=None):
     _check(_lib.spl_corner_turn(ctypes.c_void_p(x_tc.data_ptr()), n_t, nch, x_tc.stride(0),
                                 ctypes.c_void_p(out.data_ptr()), out.stride(0), _stream_handle(stream)))
     return out
+
+
+def inject_quantised(block, t_start, signal, random_words=None, *, bits=8, mu=128.0, sigma=16.0,
+                     level=1.0 / 16.0, offset=-0.5, mode=INJECT_SAMPLE, n_t=None, stream=None):
+    """Add signal windows to a quantised uint8 CUDA block [nch][pitch] in place.
+
+    t_start int32 [n_win][nch], signal float32 [n_win][nch][n_sig] and random_words
+    uint32 (int32 storage) of the signal's shape, all on the block's device; samples
+    outside [0, n_t) (n_t defaults to the pitch) are skipped.  The default quantiser is
+    the synthetic blocks' clip(round(128 + 16 n)).  Windows of one call must not
+    overlap."""
+    import torch
+    nch, pitch = block.shape
+    assert block.dtype == torch.uint8 and block.stride(1) == 1
+    n_win, nch_s, n_sig = signal.shape
+    assert nch_s == nch and tuple(t_start.shape) == (n_win, nch)
+    assert signal.dtype == torch.float32 and signal.is_contiguous()
+    assert t_start.dtype == torch.int32 and t_start.is_contiguous()
+    rw = None
+    if random_words is not None:
+        assert random_words.shape == signal.shape and random_words.is_contiguous()
+        assert random_words.dtype in (torch.int32, torch.uint32)
+        rw = ctypes.c_void_p(random_words.data_ptr())
+    q = _Quantiser(bits=bits, reserved=0, mu=mu, sigma=sigma, level=level, offset=offset)
+    _check(_lib.spl_inject_quantised(ctypes.c_void_p(block.data_ptr()), block.stride(0),
+                                     pitch if n_t is None else int(n_t), nch, ctypes.c_void_p(t_start.data_ptr()),
+                                     ctypes.c_void_p(signal.data_ptr()), rw, n_win, n_sig, ctypes.byref(q), mode,
+                                     _stream_handle(stream)))
+    return block
 
 
 def snippets(batch: Batch, cands, n=None, out=None, stream=None):

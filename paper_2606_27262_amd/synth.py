@@ -202,3 +202,26 @@ def zero_dm_bursts(rng: np.random.Generator, n_in: int, tsamp: float, rate_hz: f
     k = rng.poisson(rate_hz * n_in * tsamp)
     return [(float(rng.integers(0, n_in)), int(rng.integers(1, 33)), float(rng.uniform(1.0, 4.0)))
             for _ in range(k)]
+
+
+# --------------------------------------------------------------------------
+# Inputs of the quantised-domain injector
+# --------------------------------------------------------------------------
+def burst_windows(spec: BlockSpec, pulses, widths=(1, 2, 4, 8, 16, 32, 64)):
+    """Noise-free dispersed pulses as injector windows: (t_start int32 [n_win][nch],
+    signal float32 [n_win][nch][n_sig]), one window per pulse, zero-padded to the widest
+    window; the amplitudes are those make_block adds before quantisation."""
+    temps = [pulse_template(spec, p, pulse_amplitude(p, spec.nch, widths)) for p in pulses]
+    n_sig = max((v.shape[1] for _, v in temps), default=0)
+    t_start = np.zeros((len(temps), spec.nch), np.int32)
+    signal = np.zeros((len(temps), spec.nch, n_sig), np.float32)
+    for w, (starts, vals) in enumerate(temps):
+        t_start[w] = starts.astype(np.int32)
+        signal[w, :, :vals.shape[1]] = vals
+    return t_start, signal
+
+
+def random_words(seed: int, shape, salt: int = 7) -> np.ndarray:
+    """Uniform 32-bit words (the injector's random draws), seeded."""
+    rng = _rng(seed, 0, 0, salt=salt)
+    return rng.integers(0, 1 << 32, size=shape, dtype=np.uint32)
