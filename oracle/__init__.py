@@ -410,3 +410,54 @@ def snippets(x: np.ndarray, delays: np.ndarray, X: np.ndarray, n_out: int, L: in
         if sg > 0.0:
             out[1, k, tvalid] = ((v.astype(np.float64) - mu) / sg).astype(np.float32)
     return f32_to_bf16_bits(out)
+
+
+FINE_KEEP = 0.1   # S/N kept at the edges of the fine-DM plane (a 90 % loss)
+
+
+def fine_dm_half_range(width: int, tsamp: float, fch1: float, foff: float, nch: int,
+                       keep: float = FINE_KEEP) -> float:
+    """Half-width dDM (pc cm^-3) of the fine-DM plane of a candidate of `width` samples:
+    the DM offset at which a Gaussian pulse that wide keeps `keep` of its S/N, from the
+    large-zeta form of Eq. snrloss, (S(dDM)/S) = sqrt(pi)/(2 zeta), with zeta of
+    Eq. zetadef.  This is Eq. deltadm with its unit conversion redone: with W in seconds
+    and nu in MHz the constant is sqrt(pi)/13820, not the printed sqrt(pi)/1382.  nu is
+    the band centre (midway between the outer channel centres), the bandwidth
+    nch*|foff|."""
+    f = fch1 + np.arange(nch, dtype=np.float64) * foff
+    fref, flo = float(f.max()), float(f.min())
+    w_ms = (float(width) * tsamp) * 1000.0
+    nu = ((fref + flo) * 0.5) / 1000.0
+    bw = float(nch) * abs(foff)
+    zeta = 0.88622692545275801365 / keep          # sqrt(pi)/2 over the S/N kept
+    return ((zeta * w_ms) * ((nu * nu) * nu)) / (6.91e-3 * bw)
+
+
+def fine_dm_snippet(x: np.ndarray, n_in: int, fch1: float, foff: float, tsamp: float, dm_star: float,
+                    width: int, t_star: int, keep: float = FINE_KEEP) -> np.ndarray:
+    """Fine-DM DM-time plane (64x256 BF16 bits) of a candidate (trial DM dm_star, boxcar
+    width, sample t_star): row r is the brute-force dedispersion at DM
+    dm_star + (r - 32) * dDM/32 (dDM from fine_dm_half_range; delays by Eq. (1) as for a
+    plan), over samples t_star-128 .. t_star+127.  An entry is valid when every
+    channel's sample lies in [0, n_in).  All valid entries are standardised by one
+    mu, sigma from their exact integer moments; values float32((v - mu)/sigma) in
+    float64, then BF16 (RNE); invalid entries 0."""
+    nch = x.shape[0]
+    R, C = SNIP_ROWS, SNIP_COLS
+    step = fine_dm_half_range(width, tsamp, fch1, foff, nch, keep) / 32.0
+    dms = np.array([dm_star + float(r - 32) * step for r in range(R)], dtype=np.float64)
+    D, _ = delay_table(nch, fch1, foff, tsamp, dms)
+    ts = np.arange(t_star - C // 2, t_star + C // 2, dtype=np.int64)
+    X = np.zeros((R, C), np.int64)
+    valid = np.zeros((R, C), bool)
+    for r in range(R):
+        ok = (ts + D[r].min() >= 0) & (ts + D[r].max() < n_in)
+        valid[r] = ok
+        tv = ts[ok]
+        for c in range(nch):
+            X[r, ok] += x[c, tv + D[r, c]]
+    mu, sg = _mu_sigma_exact(X[valid])
+    out = np.zeros((R, C), np.float32)
+    if sg > 0.0:
+        out[valid] = ((X[valid].astype(np.float64) - mu) / sg).astype(np.float32)
+    return f32_to_bf16_bits(out)
