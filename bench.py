@@ -325,6 +325,17 @@ def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, arg
         per_cand = [64 * 256 * 4 + nch[int(b)] * 256 + 2 * 64 * 256 * 2 for b in surv["beam"]]
         snip_leg = {"candidates": int(surv.size), "launch_ms": ms, "bytes": int(sum(per_cand)),
                     "achieved_GBps": sum(per_cand) / (ms / 1e3) / 1e9, "peak_GBps": 8000.0}
+        # fine-DM plane 0 (64 DMs around each candidate's DM, dedispersed from the block)
+        spl.snippets(batch, dev, out=buf, fine_keep=0.1)
+        e0.record()
+        for _ in range(3):
+            spl.snippets(batch, dev, out=buf, fine_keep=0.1)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_f = e0.elapsed_time(e1) / 3
+        adds = sum(64 * 256 * nch[int(b)] for b in surv["beam"])
+        snip_leg["fine_dm"] = {"launch_ms_both_planes": ms_f, "plane0_ms": ms_f - ms, "adds": adds,
+                               "Tadds_per_s": adds / ((ms_f - ms) / 1e3) / 1e12 if ms_f > ms else None}
     pr = ranking.recall_and_false_alarms(fp, pulses, pds)
     rr = ranking.recall_and_false_alarms(kept, pulses, pds)
 

@@ -387,6 +387,25 @@ spl_status spl_corner_turn(const uint8_t *d_in, int64_t n_t, int32_t nch, int64_
 spl_status spl_ranker_snippets(const spl_batch *batch, const spl_candidate *d_cands, int64_t n, uint16_t *d_out,
                                hipStream_t stream);
 
+/*
+ * As spl_ranker_snippets, with plane 0 replaced by the fine-DM DM-time plane (the
+ * classification section: the DM transform over a narrow DM range centred on the
+ * candidate's DM, its half-width the DM offset that costs a pulse of the candidate's
+ * width all but `keep` of its S/N).  Half-width dDM = (sqrt(pi)/2 / keep) * W_ms *
+ * nu_GHz^3 / (6.91e-3 * B_MHz) from Eq. snrloss at large zeta and Eq. zetadef (the
+ * paper's Eq. deltadm with its unit conversion redone), W = width * tsamp, nu the band
+ * centre, B = nchans * |foff|; all binary64 in this order.  Row r (0..63) is the
+ * brute-force dedispersion of the batch's block at DM = DM_d* + (r - 32) * dDM/32 with
+ * delays of Eq. (1) computed as a plan computes them, over samples t*-128 .. t*+127; an
+ * entry is valid when every channel's sample lies in [0, n_in).  The valid entries are
+ * standardised together by mu, sigma from their exact integer moments (value as in
+ * plane 1); invalid entries are 0.  keep in (0, 1) (the paper's default 0.1); nchans
+ * <= 16384 (else SPL_E_UNSUPPORTED); a record with width < 1 or outside the batch
+ * yields zero planes.  Asynchronous on `stream`.
+ */
+spl_status spl_ranker_snippets_fine(const spl_batch *batch, const spl_candidate *d_cands, int64_t n, double keep,
+                                    uint16_t *d_out, hipStream_t stream);
+
 /* The network: 4 x [3x3 convolution (zero padding 1) + bias -> ReLU -> 2x2 max pool]
  * with channels 2 -> 32 -> 32 -> 32 -> 32 (64x256 -> 4x16), flatten in (channel, row,
  * column) order -> fully connected 2048 -> 64 -> ReLU -> 64 -> 1 = logit; probability

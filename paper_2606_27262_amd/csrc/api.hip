@@ -625,6 +625,16 @@ static void fill_host_beams(spl_batch *B) {
         d.T = (int32_t *)(B->ws + B->off_T[b]);
         d.dms = (const double *)(B->ws + L.off_dms);
         d.theta = p.theta;
+        d.fch1 = p.band.fch1_mhz;
+        d.foff = p.band.foff_mhz;
+        d.fref = d.flo = p.band.fch1_mhz;
+        for (int c = 0; c < p.nch; ++c) {
+            const double f = p.band.fch1_mhz + (double)c * p.band.foff_mhz;
+            d.fref = std::max(d.fref, f);
+            d.flo = std::min(d.flo, f);
+        }
+        d.tsamp = p.band.tsamp_s;
+        d.n_in = p.n_in;
         d.nch = p.nch;
         d.ndm = p.ndm;
         d.ndm_pad = L.ndm_pad;
@@ -1212,6 +1222,19 @@ extern "C" spl_status spl_ranker_snippets(const spl_batch *B, const spl_candidat
         if (!B->cur_x[b]) return fail(SPL_E_INVALID_ARG, "the batch has not run: no block for beam %d", b);
     }
     HIP_TRY(launch_snippets((const DevBeam *)(B->ws + B->off_beams), B->nb, d_cands, n, d_out, stream));
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_ranker_snippets_fine(const spl_batch *B, const spl_candidate *d_cands, int64_t n,
+                                               double keep, uint16_t *d_out, hipStream_t stream) {
+    if (!(keep > 0.0 && keep < 1.0)) return fail(SPL_E_INVALID_ARG, "spl_ranker_snippets_fine: keep must be in (0, 1)");
+    const spl_status st = spl_ranker_snippets(B, d_cands, n, d_out, stream);
+    if (st != SPL_OK || n == 0) return st;
+    for (int b = 0; b < B->nb; ++b)
+        if (B->plans[b]->nch > 16384)
+            return fail(SPL_E_UNSUPPORTED, "fine-DM snippets need nchans <= 16384 (beam %d has %d)", b,
+                        B->plans[b]->nch);
+    HIP_TRY(launch_fine_dm((const DevBeam *)(B->ws + B->off_beams), B->nb, d_cands, n, keep, d_out, stream));
     return SPL_OK;
 }
 

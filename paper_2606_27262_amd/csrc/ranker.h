@@ -6,6 +6,9 @@
 
 namespace spl {
 
+// Plane 0 of each snippet replaced by the fine-DM transform around the candidate's DM.
+hipError_t launch_fine_dm(const DevBeam *beams, int nbeams, const spl_candidate *cands, int64_t n, double keep,
+                          uint16_t *out, hipStream_t s);
 hipError_t launch_snippets(const DevBeam *beams, int nbeams, const spl_candidate *cands, int64_t n, uint16_t *out,
                            hipStream_t s);
 hipError_t launch_gemm(const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb, float *C, int64_t ldc, int M,

@@ -152,6 +152,167 @@ __global__ __launch_bounds__(256) void k_snippets(const DevBeam *__restrict__ be
     }
 }
 
+// ------------------------------------------------------- fine-DM DM-time plane
+// Plane 0 replaced by the DM transform at 64 DMs DM* + (r - 32) * dDM/32 around the
+// candidate's trial DM, dDM the half-range at which a Gaussian pulse of the candidate's
+// width keeps `keep` of its S/N (Eq. snrlossapprox with zeta of Eq. zetadef; the paper's
+// Eq. deltadm with its unit conversion corrected): dDM = (sqrt(pi)/2 / keep) * W_ms *
+// nu_GHz^3 / (6.91e-3 * B_MHz), nu the band centre, B = nch * |foff|.  Delays follow
+// Eq. (1) exactly as the plan computes them (binary64, same order, round half away).
+// Entry (r, t) sums the block over all channels at t*-128+t plus the row's delays; it is
+// valid when every channel's sample lies in [0, n_in) (the extremes are the channels of
+// the highest and lowest frequency).  The plane is standardised by the exact moments
+// of its valid entries (one mu, sigma for all rows, so the S/N falling off away from
+// DM* stays visible), float((v - mu)/sigma) in binary64 -> BF16, invalid entries 0.
+// One workgroup of 1024 threads per candidate: thread (r = tid/16, q = tid%16) owns
+// samples 16q .. 16q+15 of row r; 128-channel chunks of delays are computed into the
+// LDS, and each channel's 16 bytes are read as five aligned dwords and added as 16-bit
+// pairs (at most 128 channels per pair sum: < 2^15).
+constexpr int kFineChunk = 128;
+
+__device__ inline int64_t fine_delay(double dd, double k, double tsamp) {
+    const double v = (dd * k) / tsamp;
+    if (!(fabs(v) < 1.0e9)) return v > 0 ? (int64_t)1 << 40 : -((int64_t)1 << 40);
+    return llround(v);
+}
+
+__global__ __launch_bounds__(1024) void k_fine_dm(const DevBeam *__restrict__ beams, int nbeams,
+                                                  const spl_candidate *__restrict__ cands, int64_t n, double keep,
+                                                  uint16_t *__restrict__ out) {
+    constexpr uint32_t kSelEven = 0x0C020C00u;
+    constexpr uint32_t kSelOdd = 0x0C030C01u;
+    constexpr double kD = 4148.8064239;   // Eq. (1), MHz^2 pc^-1 cm^3 s
+    __shared__ int32_t sdel[64][kFineChunk];
+    __shared__ double skc[kFineChunk];
+    __shared__ int64_t sh[3][16];
+    const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+    const int r = tid >> 4, q = tid & 15;
+    for (int64_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
+        const spl_candidate cd = cands[ci];
+        uint16_t *o0 = out + (size_t)ci * 2 * 64 * 256;
+        const int bsafe = cd.beam < 0 || cd.beam >= nbeams ? 0 : cd.beam;
+        const bool ok = cd.beam >= 0 && cd.beam < nbeams && cd.dm_index >= 0 && cd.dm_index < beams[bsafe].ndm &&
+                        cd.t_sample >= 0 && cd.t_sample < beams[bsafe].n_out && cd.width >= 1;
+        if (!ok) {   // both planes zero (plane 1 was written by the snippet kernel before)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                o0[r * 256 + 16 * q + j] = 0;
+                o0[64 * 256 + r * 256 + 16 * q + j] = 0;
+            }
+            continue;   // uniform across the workgroup
+        }
+        const DevBeam &B = beams[cd.beam];
+        const double w_ms = ((double)cd.width * B.tsamp) * 1000.0;
+        const double nu = ((B.fref + B.flo) * 0.5) / 1000.0;
+        const double bw = (double)B.nch * fabs(B.foff);
+        const double half = (((0.88622692545275801365 / keep) * w_ms) * ((nu * nu) * nu)) / (6.91e-3 * bw);
+        const double step = half / 32.0;
+        const double dm_star = B.dms[cd.dm_index];
+        const double dd_r = kD * (dm_star + (double)(r - 32) * step);
+        const double k_lo = (1.0 / (B.flo * B.flo)) - (1.0 / (B.fref * B.fref));
+        const int64_t s_lo = fine_delay(dd_r, k_lo, B.tsamp);
+        const int64_t smin = s_lo < 0 ? s_lo : 0, smax = s_lo > 0 ? s_lo : 0;
+        const int64_t ta = (int64_t)cd.t_sample - 128 + 16 * q;
+        // entry j of this thread is valid when ta + j + smin >= 0 and ta + j + smax < n_in
+        const int64_t j_lo = -smin - ta, j_hi = (int64_t)B.n_in - 1 - smax - ta;   // valid j in [j_lo, j_hi]
+        const bool full = j_lo <= 0 && j_hi >= 15;
+        const bool any = j_lo <= 15 && j_hi >= 0 && j_lo <= j_hi;
+        int32_t acc[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = 0;
+        for (int c0 = 0; c0 < B.nch; c0 += kFineChunk) {
+            const int nc = min(kFineChunk, B.nch - c0);
+            __syncthreads();   // the previous chunk's delays are no longer read
+            if (tid < kFineChunk) {
+                const double f = B.fch1 + (double)(c0 + tid) * B.foff;
+                skc[tid] = tid < nc ? (1.0 / (f * f)) - (1.0 / (B.fref * B.fref)) : 0.0;
+            }
+            __syncthreads();
+            for (int e = tid; e < 64 * kFineChunk; e += 1024) {
+                const int rr = e / kFineChunk, cc = e % kFineChunk;
+                const double dd = kD * (dm_star + (double)(rr - 32) * step);
+                const int64_t sv = fine_delay(dd, skc[cc], B.tsamp);
+                sdel[rr][cc] = (int32_t)(sv > (1 << 30) ? (1 << 30) : (sv < -(1 << 30) ? -(1 << 30) : sv));
+            }
+            __syncthreads();
+            if (!any) continue;
+            uint32_t ae[4] = {0u, 0u, 0u, 0u}, ao[4] = {0u, 0u, 0u, 0u};
+            for (int cc = 0; cc < nc; ++cc) {
+                const uint8_t *row = B.x + (size_t)(c0 + cc) * B.pitch;
+                const int64_t off = ta + sdel[r][cc];
+                uint32_t d4[4];
+                if (full && off >= 0 && (off & ~(int64_t)3) + 20 <= B.pitch) {
+                    const uint32_t *w = (const uint32_t *)(row + (off & ~(int64_t)3));
+                    const uint32_t w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3], w4 = w[4];
+                    const uint32_t sa = (uint32_t)(off & 3);
+                    d4[0] = __builtin_amdgcn_alignbyte(w1, w0, sa);
+                    d4[1] = __builtin_amdgcn_alignbyte(w2, w1, sa);
+                    d4[2] = __builtin_amdgcn_alignbyte(w3, w2, sa);
+                    d4[3] = __builtin_amdgcn_alignbyte(w4, w3, sa);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        uint32_t v = 0u;
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const int j = 4 * i + b;
+                            const int64_t t = off + j;
+                            if (j >= j_lo && j <= j_hi && t >= 0 && t < B.n_in) v |= (uint32_t)row[t] << (8 * b);
+                        }
+                        d4[i] = v;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    ae[i] += __builtin_amdgcn_perm(d4[i], d4[i], kSelEven);
+                    ao[i] += __builtin_amdgcn_perm(d4[i], d4[i], kSelOdd);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                acc[4 * i + 0] += (int32_t)(ae[i] & 0xFFFFu);
+                acc[4 * i + 2] += (int32_t)(ae[i] >> 16);
+                acc[4 * i + 1] += (int32_t)(ao[i] & 0xFFFFu);
+                acc[4 * i + 3] += (int32_t)(ao[i] >> 16);
+            }
+        }
+        // exact moments of the plane's valid entries
+        int64_t s1 = 0, s2 = 0, nv = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (j >= j_lo && j <= j_hi) {
+                s1 += acc[j];
+                s2 += (int64_t)acc[j] * acc[j];
+                nv += 1;
+            }
+        }
+        s1 = wave_sum(s1);
+        s2 = wave_sum(s2);
+        nv = wave_sum(nv);
+        if (lane == 0) {
+            sh[0][wave] = s1;
+            sh[1][wave] = s2;
+            sh[2][wave] = nv;
+        }
+        __syncthreads();
+        int64_t S1 = 0, S2 = 0, NV = 0;
+        for (int k = 0; k < 16; ++k) {
+            S1 += sh[0][k];
+            S2 += sh[1][k];
+            NV += sh[2][k];
+        }
+        double mu = 0.0, sg = 0.0;
+        if (NV > 0) mu_sigma(NV, S1, S2, mu, sg);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            float v = 0.f;
+            if (j >= j_lo && j <= j_hi && sg > 0.0) v = (float)(((double)acc[j] - mu) / sg);
+            o0[r * 256 + 16 * q + j] = f2bf(v);
+        }
+        __syncthreads();   // sh is reused by the next candidate
+    }
+}
+
 // --------------------------------------------------------------------- GEMM
 // C[M][N] (FP32, row stride ldc) = (mode 1: C +) A[M][K] * B[N][K]^T with A and B BF16,
 // K contiguous, row strides lda/ldb multiples of 8, K a multiple of 32.  Workgroup =
@@ -578,6 +739,15 @@ hipError_t launch_snippets(const DevBeam *beams, int nbeams, const spl_candidate
     if (n <= 0) return hipSuccess;
     const unsigned g = (unsigned)(n < 65536 ? n : 65536);
     hipLaunchKernelGGL(k_snippets, dim3(g), dim3(256), 0, s, beams, nbeams, cands, n, out);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_fine_dm(const DevBeam *beams, int nbeams, const spl_candidate *cands, int64_t n, double keep,
+                          uint16_t *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned g = (unsigned)(n < 65536 ? n : 65536);
+    hipLaunchKernelGGL(k_fine_dm, dim3(g), dim3(1024), 0, s, beams, nbeams, cands, n, keep, out);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -29,6 +29,10 @@ struct DevBeam {
     int32_t *T;              // integer thresholds [ndm][nseg][nw]
     const double *dms;       // [ndm]
     double theta;
+    double fch1, foff;       // channel c has centre fch1 + c*foff (MHz)
+    double fref, flo;        // highest and lowest channel centres (MHz)
+    double tsamp;            // s
+    int32_t n_in;            // samples per channel the block carries
     int32_t nch, ndm, ndm_pad, n_dd, n_out, L, nseg, nw;
     int32_t xpitch;          // int32 elements per DM row
     int32_t row_base;        // global row index of (beam, d = 0)

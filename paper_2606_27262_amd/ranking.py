@@ -136,9 +136,10 @@ def burst_batch(pds, seed: int, n_pulses: int = 8, dm_lo: float = 20.0, dm_hi: f
 class Stage:
     """Search + optimisation + optional ranker for a fixed batch of plans."""
 
-    def __init__(self, spl, pds, cand_capacity=1 << 20, mode=0):
+    def __init__(self, spl, pds, cand_capacity=1 << 20, mode=0, fine_keep=None):
         import torch
         self.spl, self.pds = spl, pds
+        self.fine_keep = fine_keep   # None: DM-time plane on the search grid; else fine-DM plane
         self.plans = [spl.Plan.from_dict(pd) for pd in pds]
         self.n_in = [p.info["n_in"] for p in self.plans]
         self.batch = spl.Batch(self.plans, mode=mode)
@@ -157,7 +158,7 @@ class Stage:
     def snippets(self, recs: np.ndarray):
         import torch
         dev = torch.from_numpy(np.ascontiguousarray(recs).view(np.int32).reshape(-1, 8).copy()).cuda()
-        return self.spl.snippets(self.batch, dev)
+        return self.spl.snippets(self.batch, dev, fine_keep=self.fine_keep)
 
     def plain(self, cands, **kw):
         return self.spl.optimise_plain(cands, self.tsamp, len(self.pds), **kw)
@@ -170,12 +171,12 @@ class Stage:
                            lambda recs: ranker.score(self.snippets(recs)).cpu().numpy())
 
 
-def mine(spl, pds, n_batches, seed0, neg_ratio=1.0, log=print, **burst_kw):
+def mine(spl, pds, n_batches, seed0, neg_ratio=1.0, log=print, fine_keep=None, **burst_kw):
     """Labelled snippets (device int16 [n][2][64][256], float32 labels) from the NMS
     candidates of searched blocks: matched candidates are positives, a random subset
     of the unmatched ones (neg_ratio per positive) negatives."""
     import torch
-    st = Stage(spl, pds)
+    st = Stage(spl, pds, fine_keep=fine_keep)
     xs, ys = [], []
     for i in range(n_batches):
         t0 = time.time()
@@ -234,10 +235,10 @@ def train(ranker, x, y, epochs=20, batch=256, lr=1e-3, val_frac=0.1, seed=0, log
     return hist
 
 
-def evaluate(spl, pds, ranker, n_batches, seed0, log=print, **burst_kw):
+def evaluate(spl, pds, ranker, n_batches, seed0, log=print, fine_keep=None, **burst_kw):
     """Recall and false alarms of the plain path and of the ranker path on fresh blocks."""
     import torch
-    st = Stage(spl, pds)
+    st = Stage(spl, pds, fine_keep=fine_keep)
     plain_all, rank_all, pulses_all, cand_all, scored_all, logit_all = [], [], [], 0, [], []
     t_rank = 0.0
     for i in range(n_batches):

@@ -144,6 +144,7 @@ _F32 = ctypes.c_float
 _sig("spl_corner_turn", [_P, _I64, _I32, _I64, _P, _I64, _P])
 _sig("spl_inject_quantised", [_P, _I64, _I64, _I32, _P, _P, _P, _I32, _I32, ctypes.POINTER(_Quantiser), _I32, _P])
 _sig("spl_ranker_snippets", [_P, _P, _I64, _P, _P])
+_sig("spl_ranker_snippets_fine", [_P, _P, _I64, _F64, _P, _P])
 _sig("spl_ranker_create", [ctypes.POINTER(_RankerOpts), ctypes.POINTER(_P)])
 _sig("spl_ranker_workspace_size", [_P, ctypes.POINTER(_SZ)])
 _sig("spl_ranker_set_workspace", [_P, _P, _SZ])
@@ -488,15 +489,20 @@ def inject_quantised(block, t_start, signal, random_words=None, *, bits=8, mu=12
     return block
 
 
-def snippets(batch: Batch, cands, n=None, out=None, stream=None):
+def snippets(batch: Batch, cands, n=None, out=None, stream=None, fine_keep=None):
     """Feature snippets of device candidate records (int32 [>= n, 8]) of the batch's
-    last run -> int16 tensor [n][2][64][256] holding BF16 bit patterns."""
+    last run -> int16 tensor [n][2][64][256] holding BF16 bit patterns.  With fine_keep
+    (e.g. 0.1) plane 0 is the fine-DM plane around each candidate's DM."""
     import torch
     n = cands.shape[0] if n is None else int(n)
     if out is None:
         out = torch.empty((n, 2, SNIPPET_ROWS, SNIPPET_COLS), dtype=torch.int16, device=cands.device)
-    _check(_lib.spl_ranker_snippets(batch._h, ctypes.c_void_p(cands.data_ptr()), n, ctypes.c_void_p(out.data_ptr()),
-                                    _stream_handle(stream)))
+    if fine_keep is None:
+        _check(_lib.spl_ranker_snippets(batch._h, ctypes.c_void_p(cands.data_ptr()), n,
+                                        ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    else:
+        _check(_lib.spl_ranker_snippets_fine(batch._h, ctypes.c_void_p(cands.data_ptr()), n, float(fine_keep),
+                                             ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
 
 

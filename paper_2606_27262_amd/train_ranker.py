@@ -34,6 +34,8 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--eval-seed", type=int, default=7000)
     ap.add_argument("--out", default="ranker_weights.npy")
+    ap.add_argument("--fine-keep", type=float, default=None,
+                    help="train and evaluate on fine-DM planes (DM* +- the offset keeping this S/N fraction)")
     ap.add_argument("--json", default=None)
     ap.add_argument("--eval-only", default=None, metavar="WEIGHTS",
                     help="skip training: evaluate these weights (.npy) against the plain path")
@@ -52,8 +54,10 @@ def main(argv=None):
     if a.eval_only:
         ranker.set_weights(np.load(a.eval_only))
         pde = [W.plan_c2() for _ in range(a.eval_beams)]
-        res = ranking.evaluate(spl, pde, ranker, a.eval_batches, a.eval_seed, log=log, n_pulses=a.pulses)
-        line = json.dumps({"eval": res, "weights": os.path.abspath(a.eval_only), "wall_s": time.time() - t_start})
+        res = ranking.evaluate(spl, pde, ranker, a.eval_batches, a.eval_seed, log=log, n_pulses=a.pulses,
+                               fine_keep=a.fine_keep)
+        line = json.dumps({"eval": res, "fine_keep": a.fine_keep, "weights": os.path.abspath(a.eval_only),
+                           "wall_s": time.time() - t_start})
         print(line, flush=True)
         if a.json:
             with open(a.json, "w") as f:
@@ -61,7 +65,8 @@ def main(argv=None):
         return
     ranker.set_weights(ranking.initial_weights(a.seed))
     pds = [W.plan_c2() for _ in range(a.beams)]
-    x, y = ranking.mine(spl, pds, a.train_batches, a.seed * 100000, log=log, n_pulses=a.pulses)
+    x, y = ranking.mine(spl, pds, a.train_batches, a.seed * 100000, log=log, n_pulses=a.pulses,
+                        fine_keep=a.fine_keep)
     log(f"training set: {x.shape[0]} snippets, {int(y.sum())} positive")
     t_train = time.time()
     hist = ranking.train(ranker, x, y, epochs=a.epochs, batch=a.max_batch, lr=a.lr, seed=a.seed, log=log)
@@ -71,8 +76,9 @@ def main(argv=None):
     np.save(a.out, w)
     del x
     pde = [W.plan_c2() for _ in range(a.eval_beams)]
-    res = ranking.evaluate(spl, pde, ranker, a.eval_batches, a.eval_seed, log=log, n_pulses=a.pulses)
-    out = {"train": {"snippets": int(y.size), "positives": int(y.sum()), "epochs": a.epochs, "lr": a.lr,
+    res = ranking.evaluate(spl, pde, ranker, a.eval_batches, a.eval_seed, log=log, n_pulses=a.pulses,
+                           fine_keep=a.fine_keep)
+    out = {"fine_keep": a.fine_keep, "train": {"snippets": int(y.size), "positives": int(y.sum()), "epochs": a.epochs, "lr": a.lr,
                      "batch": a.max_batch, "seconds": t_train,
                      "history": [[e, round(l, 5), round(v, 4)] for e, l, v in hist]},
            "eval": res, "weights": os.path.abspath(a.out), "wall_s": time.time() - t_start}
