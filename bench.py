@@ -334,8 +334,24 @@ def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, arg
         torch.cuda.synchronize()
         ms_f = e0.elapsed_time(e1) / 3
         adds = sum(64 * 256 * nch[int(b)] for b in surv["beam"])
+        # block bytes the plane must read: per channel the 256 samples plus the spread of
+        # its 64 delays (2 dDM x the channel's delay per unit DM), at most 64 x 256
+        touched = 0
+        for b in np.unique(surv["beam"]):
+            pd = pds[int(b)]
+            f = pd["fch1"] + np.arange(pd["nchans"]) * pd["foff"]
+            per_dm = 4148.8064239 * (1.0 / f ** 2 - 1.0 / f.max() ** 2) / pd["tsamp"]
+            nu, bw = (f.max() + f.min()) / 2e3, pd["nchans"] * abs(pd["foff"])
+            w = surv["width"][surv["beam"] == b].astype(np.float64)
+            half = (np.sqrt(np.pi) / 2 / 0.1) * (w * pd["tsamp"] * 1e3) * nu ** 3 / (6.91e-3 * bw)
+            touched += int(np.minimum(64 * 256, 256 + 2 * half[:, None] * per_dm[None, :]).sum())
+        sel_w = surv["width"].astype(np.int64)
         snip_leg["fine_dm"] = {"launch_ms_both_planes": ms_f, "plane0_ms": ms_f - ms, "adds": adds,
-                               "Tadds_per_s": adds / ((ms_f - ms) / 1e3) / 1e12 if ms_f > ms else None}
+                               "Tadds_per_s": adds / ((ms_f - ms) / 1e3) / 1e12 if ms_f > ms else None,
+                               "block_bytes_touched": touched,
+                               "touched_GBps": touched / ((ms_f - ms) / 1e3) / 1e9 if ms_f > ms else None,
+                               "widths_p50_p90_max": [int(np.percentile(sel_w, 50)), int(np.percentile(sel_w, 90)),
+                                                      int(sel_w.max())]}
     pr = ranking.recall_and_false_alarms(fp, pulses, pds)
     rr = ranking.recall_and_false_alarms(kept, pulses, pds)
 

@@ -164,16 +164,31 @@ __global__ __launch_bounds__(256) void k_snippets(const DevBeam *__restrict__ be
 // the highest and lowest frequency).  The plane is standardised by the exact moments
 // of its valid entries (one mu, sigma for all rows, so the S/N falling off away from
 // DM* stays visible), float((v - mu)/sigma) in binary64 -> BF16, invalid entries 0.
-// One workgroup of 1024 threads per candidate: thread (r = tid/16, q = tid%16) owns
-// samples 16q .. 16q+15 of row r; 128-channel chunks of delays are computed into the
-// LDS, and each channel's 16 bytes are read as five aligned dwords and added as 16-bit
-// pairs (at most 128 channels per pair sum: < 2^15).
-constexpr int kFineChunk = 128;
+// One workgroup of 1024 threads per candidate: thread (g = tid/64, q = tid%64) owns
+// samples 4q .. 4q+3 of rows g, g+16, g+32, g+48.  Channels go in chunks of 16: the
+// delays of the 64 rows are computed into the LDS, then each channel's window of the
+// block (the 256 samples plus the spread of its 64 delays) is staged as four copies
+// shifted by 0..3 bytes, so every 4-sample read of any row is one aligned LDS dword
+// (a wave's 64 lanes read 64 consecutive dwords: no bank conflicts).  Windows wider
+// than the staging buffer (wide pulses: dDM grows with the width) are read from the
+// block directly, two aligned dwords per 4 samples.  Sums go through 16-bit pairs,
+// flushed before they exceed 256 channels (< 2^16).
+constexpr int kFineChunk = 16;
+constexpr int kFineWords = 512;   // staged dwords per channel and copy (window <= 2 KiB; 128 KiB of LDS)
 
 __device__ inline int64_t fine_delay(double dd, double k, double tsamp) {
     const double v = (dd * k) / tsamp;
     if (!(fabs(v) < 1.0e9)) return v > 0 ? (int64_t)1 << 40 : -((int64_t)1 << 40);
     return llround(v);
+}
+
+__device__ inline uint32_t block_dword(const uint8_t *row, int64_t t, int64_t n_in) {
+    if (t >= 0 && t + 4 <= n_in) return *(const uint32_t *)(row + t);   // t is a multiple of 4 here
+    uint32_t v = 0u;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        if (t + b >= 0 && t + b < n_in) v |= (uint32_t)row[t + b] << (8 * b);
+    return v;
 }
 
 __global__ __launch_bounds__(1024) void k_fine_dm(const DevBeam *__restrict__ beams, int nbeams,
@@ -182,11 +197,13 @@ __global__ __launch_bounds__(1024) void k_fine_dm(const DevBeam *__restrict__ be
     constexpr uint32_t kSelEven = 0x0C020C00u;
     constexpr uint32_t kSelOdd = 0x0C030C01u;
     constexpr double kD = 4148.8064239;   // Eq. (1), MHz^2 pc^-1 cm^3 s
+    __shared__ uint32_t stage[kFineChunk][4][kFineWords];
     __shared__ int32_t sdel[64][kFineChunk];
-    __shared__ double skc[kFineChunk];
+    __shared__ int64_t sgs[kFineChunk];
+    __shared__ int32_t snw[kFineChunk];
     __shared__ int64_t sh[3][16];
     const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-    const int r = tid >> 4, q = tid & 15;
+    const int g = tid >> 6, q = tid & 63;
     for (int64_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
         const spl_candidate cd = cands[ci];
         uint16_t *o0 = out + (size_t)ci * 2 * 64 * 256;
@@ -194,11 +211,7 @@ __global__ __launch_bounds__(1024) void k_fine_dm(const DevBeam *__restrict__ be
         const bool ok = cd.beam >= 0 && cd.beam < nbeams && cd.dm_index >= 0 && cd.dm_index < beams[bsafe].ndm &&
                         cd.t_sample >= 0 && cd.t_sample < beams[bsafe].n_out && cd.width >= 1;
         if (!ok) {   // both planes zero (plane 1 was written by the snippet kernel before)
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                o0[r * 256 + 16 * q + j] = 0;
-                o0[64 * 256 + r * 256 + 16 * q + j] = 0;
-            }
+            for (int e = tid; e < 2 * 64 * 256; e += 1024) o0[e] = 0;
             continue;   // uniform across the workgroup
         }
         const DevBeam &B = beams[cd.beam];
@@ -208,82 +221,125 @@ __global__ __launch_bounds__(1024) void k_fine_dm(const DevBeam *__restrict__ be
         const double half = (((0.88622692545275801365 / keep) * w_ms) * ((nu * nu) * nu)) / (6.91e-3 * bw);
         const double step = half / 32.0;
         const double dm_star = B.dms[cd.dm_index];
-        const double dd_r = kD * (dm_star + (double)(r - 32) * step);
         const double k_lo = (1.0 / (B.flo * B.flo)) - (1.0 / (B.fref * B.fref));
-        const int64_t s_lo = fine_delay(dd_r, k_lo, B.tsamp);
-        const int64_t smin = s_lo < 0 ? s_lo : 0, smax = s_lo > 0 ? s_lo : 0;
-        const int64_t ta = (int64_t)cd.t_sample - 128 + 16 * q;
-        // entry j of this thread is valid when ta + j + smin >= 0 and ta + j + smax < n_in
-        const int64_t j_lo = -smin - ta, j_hi = (int64_t)B.n_in - 1 - smax - ta;   // valid j in [j_lo, j_hi]
-        const bool full = j_lo <= 0 && j_hi >= 15;
-        const bool any = j_lo <= 15 && j_hi >= 0 && j_lo <= j_hi;
-        int32_t acc[16];
+        const int64_t t_first = (int64_t)cd.t_sample - 128;   // sample of column 0
+        const int64_t ta = t_first + 4 * q;                    // the thread's first sample
+        // bit 4i + j: sample j (0..3) of row g + 16i is valid (ta + j + smin >= 0 and
+        // ta + j + smax < n_in, the extremes of the row's delays)
+        uint32_t vmask = 0u;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j] = 0;
+        for (int i = 0; i < 4; ++i) {
+            const int r = g + 16 * i;
+            const int64_t s_lo = fine_delay(kD * (dm_star + (double)(r - 32) * step), k_lo, B.tsamp);
+            const int64_t smin = s_lo < 0 ? s_lo : 0, smax = s_lo > 0 ? s_lo : 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (ta + j + smin >= 0 && ta + j + smax < (int64_t)B.n_in) vmask |= 1u << (4 * i + j);
+        }
+        int32_t acc[4][4];
+        uint32_t ae[4], ao[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ae[i] = ao[i] = 0u;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+        }
+        int pending = 0;   // channels in the 16-bit pair sums
         for (int c0 = 0; c0 < B.nch; c0 += kFineChunk) {
             const int nc = min(kFineChunk, B.nch - c0);
-            __syncthreads();   // the previous chunk's delays are no longer read
-            if (tid < kFineChunk) {
-                const double f = B.fch1 + (double)(c0 + tid) * B.foff;
-                skc[tid] = tid < nc ? (1.0 / (f * f)) - (1.0 / (B.fref * B.fref)) : 0.0;
-            }
-            __syncthreads();
-            for (int e = tid; e < 64 * kFineChunk; e += 1024) {
-                const int rr = e / kFineChunk, cc = e % kFineChunk;
-                const double dd = kD * (dm_star + (double)(rr - 32) * step);
-                const int64_t sv = fine_delay(dd, skc[cc], B.tsamp);
+            __syncthreads();   // the previous chunk's staging is no longer read
+            {
+                // one delay per thread: row rr, channel cc of the chunk (Eq. (1) as a plan
+                // computes it); the row-0 thread of a channel also bounds its window (the
+                // delays are monotone in the row, so rows 0 and 63 are the extremes)
+                const int rr = tid / kFineChunk, cc = tid % kFineChunk;
+                const double f = B.fch1 + (double)(c0 + cc) * B.foff;
+                const double kc = cc < nc ? (1.0 / (f * f)) - (1.0 / (B.fref * B.fref)) : 0.0;
+                const int64_t sv = fine_delay(kD * (dm_star + (double)(rr - 32) * step), kc, B.tsamp);
                 sdel[rr][cc] = (int32_t)(sv > (1 << 30) ? (1 << 30) : (sv < -(1 << 30) ? -(1 << 30) : sv));
+                if (rr == 0) {
+                    const int64_t s63 = fine_delay(kD * (dm_star + 31.0 * step), kc, B.tsamp);
+                    const int64_t a0 = sv, a1 = s63;
+                    const int64_t lo = a0 < a1 ? a0 : a1, hi = a0 < a1 ? a1 : a0;
+                    const int64_t gs = (t_first + lo) & ~(int64_t)3;
+                    const int64_t nw = ((t_first + 252 + hi - gs) >> 2) + 1;   // dwords holding every read
+                    sgs[cc] = gs;
+                    snw[cc] = (cc < nc && nw + 1 <= kFineWords) ? (int32_t)nw : 0;   // 0: read the block
+                }
             }
             __syncthreads();
-            if (!any) continue;
-            uint32_t ae[4] = {0u, 0u, 0u, 0u}, ao[4] = {0u, 0u, 0u, 0u};
-            for (int cc = 0; cc < nc; ++cc) {
-                const uint8_t *row = B.x + (size_t)(c0 + cc) * B.pitch;
-                const int64_t off = ta + sdel[r][cc];
-                uint32_t d4[4];
-                if (full && off >= 0 && (off & ~(int64_t)3) + 20 <= B.pitch) {
-                    const uint32_t *w = (const uint32_t *)(row + (off & ~(int64_t)3));
-                    const uint32_t w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3], w4 = w[4];
-                    const uint32_t sa = (uint32_t)(off & 3);
-                    d4[0] = __builtin_amdgcn_alignbyte(w1, w0, sa);
-                    d4[1] = __builtin_amdgcn_alignbyte(w2, w1, sa);
-                    d4[2] = __builtin_amdgcn_alignbyte(w3, w2, sa);
-                    d4[3] = __builtin_amdgcn_alignbyte(w4, w3, sa);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        uint32_t v = 0u;
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) {
-                            const int j = 4 * i + b;
-                            const int64_t t = off + j;
-                            if (j >= j_lo && j <= j_hi && t >= 0 && t < B.n_in) v |= (uint32_t)row[t] << (8 * b);
-                        }
-                        d4[i] = v;
-                    }
+            for (int e = tid; e < kFineChunk * kFineWords; e += 1024) {
+                const int cc = e / kFineWords, i = e % kFineWords;
+                const int nw = snw[cc];
+                if (i < nw) {
+                    const uint8_t *row = B.x + (size_t)(c0 + cc) * B.pitch;
+                    const int64_t t = sgs[cc] + 4 * (int64_t)i;
+                    const uint32_t w0 = block_dword(row, t, B.n_in), w1 = block_dword(row, t + 4, B.n_in);
+                    stage[cc][0][i] = w0;
+                    stage[cc][1][i] = __builtin_amdgcn_alignbyte(w1, w0, 1);
+                    stage[cc][2][i] = __builtin_amdgcn_alignbyte(w1, w0, 2);
+                    stage[cc][3][i] = __builtin_amdgcn_alignbyte(w1, w0, 3);
                 }
+            }
+            __syncthreads();
+            if (pending + nc > 256) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    ae[i] += __builtin_amdgcn_perm(d4[i], d4[i], kSelEven);
-                    ao[i] += __builtin_amdgcn_perm(d4[i], d4[i], kSelOdd);
+                    acc[i][0] += (int32_t)(ae[i] & 0xFFFFu);
+                    acc[i][2] += (int32_t)(ae[i] >> 16);
+                    acc[i][1] += (int32_t)(ao[i] & 0xFFFFu);
+                    acc[i][3] += (int32_t)(ao[i] >> 16);
+                    ae[i] = ao[i] = 0u;
+                }
+                pending = 0;
+            }
+            pending += nc;
+            for (int cc = 0; cc < nc; ++cc) {
+                const int nw = snw[cc];   // the same for the whole workgroup
+                if (nw > 0) {
+                    const int64_t base = ta - sgs[cc];
+                    const uint32_t lim = 4u * (uint32_t)nw;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int64_t off = base + sdel[g + 16 * i][cc];
+                        // in range by the monotone delays; checked all the same
+                        const uint32_t o = (off >= 0 && off < (int64_t)lim) ? (uint32_t)off : 0u;
+                        const uint32_t word = stage[cc][o & 3u][o >> 2];
+                        ae[i] += __builtin_amdgcn_perm(word, word, kSelEven);
+                        ao[i] += __builtin_amdgcn_perm(word, word, kSelOdd);
+                    }
+                } else {
+                    const uint8_t *row = B.x + (size_t)(c0 + cc) * B.pitch;
+                    for (int i = 0; i < 4; ++i) {
+                        const int64_t t = ta + sdel[g + 16 * i][cc];
+                        const int64_t t4 = t & ~(int64_t)3;
+                        const uint32_t word = __builtin_amdgcn_alignbyte(block_dword(row, t4 + 4, B.n_in),
+                                                                         block_dword(row, t4, B.n_in),
+                                                                         (uint32_t)(t & 3));
+                        ae[i] += __builtin_amdgcn_perm(word, word, kSelEven);
+                        ao[i] += __builtin_amdgcn_perm(word, word, kSelOdd);
+                    }
                 }
             }
+        }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                acc[4 * i + 0] += (int32_t)(ae[i] & 0xFFFFu);
-                acc[4 * i + 2] += (int32_t)(ae[i] >> 16);
-                acc[4 * i + 1] += (int32_t)(ao[i] & 0xFFFFu);
-                acc[4 * i + 3] += (int32_t)(ao[i] >> 16);
-            }
+        for (int i = 0; i < 4; ++i) {
+            acc[i][0] += (int32_t)(ae[i] & 0xFFFFu);
+            acc[i][2] += (int32_t)(ae[i] >> 16);
+            acc[i][1] += (int32_t)(ao[i] & 0xFFFFu);
+            acc[i][3] += (int32_t)(ao[i] >> 16);
         }
         // exact moments of the plane's valid entries
         int64_t s1 = 0, s2 = 0, nv = 0;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            if (j >= j_lo && j <= j_hi) {
-                s1 += acc[j];
-                s2 += (int64_t)acc[j] * acc[j];
-                nv += 1;
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (vmask >> (4 * i + j) & 1u) {
+                    s1 += acc[i][j];
+                    s2 += (int64_t)acc[i][j] * acc[i][j];
+                    nv += 1;
+                }
             }
         }
         s1 = wave_sum(s1);
@@ -304,10 +360,13 @@ __global__ __launch_bounds__(1024) void k_fine_dm(const DevBeam *__restrict__ be
         double mu = 0.0, sg = 0.0;
         if (NV > 0) mu_sigma(NV, S1, S2, mu, sg);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            float v = 0.f;
-            if (j >= j_lo && j <= j_hi && sg > 0.0) v = (float)(((double)acc[j] - mu) / sg);
-            o0[r * 256 + 16 * q + j] = f2bf(v);
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float v = 0.f;
+                if ((vmask >> (4 * i + j) & 1u) && sg > 0.0) v = (float)(((double)acc[i][j] - mu) / sg);
+                o0[(g + 16 * i) * 256 + 4 * q + j] = f2bf(v);
+            }
         }
         __syncthreads();   // sh is reused by the next candidate
     }
