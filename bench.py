@@ -140,11 +140,24 @@ def cpu_baseline(pd, plan, W, target_s=12.0):
     t = run(k)
     k2 = int(min(i["ndm"], max(k, k * target_s / max(t, 1e-3))))
     t2 = run(k2)
-    out = {"value": k2 * i["n_out"] / t2, "unit": "DM-trial·samples/s", "cores": oracle.num_threads(),
-           "kind": "oracle", "seconds": round(t2, 3),
-           "sample": f"first {k2} of {i['ndm']} DM trials x {i['n_out']} samples of one "
-                     f"{i['nchans']}-channel block: dedispersion + boxcar search + peak filters"}
     r = last["r"]
+    x0 = x
+    blocks = 1
+    if k2 == i["ndm"] and i["nchans"] > 256:
+        # the whole block took less than target_s: search further blocks of the workload
+        # (other beams, same plan) until about target_s of CPU work is timed
+        while t2 < target_s and blocks < 8:
+            _, x = W.c2_like_block(pd, i["n_in"], 99, blocks, 4)
+            x = np.ascontiguousarray(x[:, :i["n_in"]])
+            t2 += run(k2)
+            blocks += 1
+        x = x0
+    out = {"value": blocks * k2 * i["n_out"] / t2, "unit": "DM-trial·samples/s", "cores": oracle.num_threads(),
+           "kind": "oracle", "seconds": round(t2, 3),
+           "sample": (f"first {k2} of {i['ndm']} DM trials x {i['n_out']} samples of one "
+                      f"{i['nchans']}-channel block" if blocks == 1 else
+                      f"all {k2} DM trials x {i['n_out']} samples of {blocks} {i['nchans']}-channel blocks "
+                      f"(beams of the workload)") + ": dedispersion + boxcar search + peak filters"}
     if i["nchans"] % 64 == 0 and r["cands"].size and k2 == i["ndm"]:
         from oracle import cnn
         cs = r["cands"][:8]
