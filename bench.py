@@ -176,20 +176,28 @@ def cpu_baseline(pd, plan, W, target_s=12.0):
     return out
 
 
+def dedisp_source_hash():
+    """SHA-256 over the sources the dedispersion kernel is compiled from (the kernel
+    file and the headers that define its descriptors), in a fixed order."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h", "spl_internal.h", "spl_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_2606_27262_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def counter_traffic(workload, tiles):
     """HBM bytes per dedispersion launch from the committed rocprofv3 counter summary of
     this workload (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy), or None when
     there is none, or the kernel source or the tile shape differ from those the counters
     were taken with."""
-    import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"dedisp_{workload}_hbm_counters.md")
     if not os.path.exists(path):
         return None
     m = re.search(r"^counters: workload=(\S+) kernel=k_dedisp tiles=(\d+),(\d+),(\d+),(\d+) grid=\d+ "
-                  r"fetch_bytes=(\d+) write_bytes=(\d+) kernels_hip_sha256=([0-9a-f]{64})$", open(path).read(), re.M)
-    src = os.path.join(ROOT, "paper_2606_27262_amd", "csrc", "kernels.hip")
-    if not m or m.group(1) != workload or hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(8):
+                  r"fetch_bytes=(\d+) write_bytes=(\d+) dedisp_src_sha256=([0-9a-f]{64})$", open(path).read(), re.M)
+    if not m or m.group(1) != workload or dedisp_source_hash() != m.group(8):
         return None
     shape = tuple(int(m.group(i)) for i in range(2, 6))
     if any((t["dm_per_wave"], t["time_groups"], t["waves"], t["chan_chunk"]) != shape for t in tiles):
