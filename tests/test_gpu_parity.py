@@ -210,6 +210,47 @@ def test_c2_full_size(spl, mode):
     assert np.array_equal(g["cands"], rc)
 
 
+def test_c4_mixed_beams_full_size(spl):
+    """The 32-beam workload's two plans at full size in one persistent, graph-captured
+    batch: a 2048-channel 300-500 MHz beam (0.65536 ms, 32768 samples, 1024 trials to
+    DM 1000, delays up to 44,946 samples) and a 4096-channel beam with 3072 trials to DM
+    3000, each with ten pulses, RFI channels and zero-DM bursts.  Per beam: DM-0 row =
+    channel sum, sampled DM-transform entries by direct summation, moments, and the
+    candidate list of the oracle's search on the GPU's DM transform."""
+    pds = [W.plan_band3_c4(), W.plan_band4_c4()]
+    plans = [make_plan(spl, 0, 0, 0, None, 0, plan_dict=pd) for pd in pds]
+    blocks = []
+    for b, (pd, p) in enumerate(zip(pds, plans)):
+        _, x = W.c2_like_block(pd, p.info["n_in"], seed=4, beam=b, n_pulses=10,
+                               dm_max_pulse=0.9 * W.dm_max(pd), zero_dm_rate=0.2)
+        blocks.append(x[:, :p.info["n_in"]])
+        say(f"c4 beam {b} block generated", blocks[-1].shape)
+    g = gpu_run(spl, plans, blocks, mode=1, cand_cap=1 << 20)
+    assert g["stats"]["hit_overflow"] == 0
+    rng = np.random.default_rng(9)
+    refs = []
+    for b, (pd, p, x) in enumerate(zip(pds, plans, blocks)):
+        i = p.info
+        X = g["X"][b]
+        assert np.array_equal(X[0], x[:, :i["n_dd"]].astype(np.int64).sum(0))
+        D = p.delays().astype(np.int64)
+        ds = rng.integers(0, i["ndm"], 1500)
+        ts = rng.integers(0, i["n_dd"], 1500)
+        ds[:8] = i["ndm"] - 1
+        ts[:8] = i["n_dd"] - 1 - np.arange(8)
+        ch = np.arange(i["nchans"])
+        for d, t in zip(ds, ts):
+            assert X[d, t] == int(x[ch, t + D[d]].astype(np.int64).sum()), (b, d, t)
+        n, s1, s2 = oracle.moments(X, i["n_out"], i["norm_window"])
+        assert np.array_equal(g["S1"][b], s1) and np.array_equal(g["S2"][b], s2)
+        hits = oracle.search(X, i["n_out"], i["norm_window"], pd["widths"], pd["threshold"])
+        alive = oracle.nms(hits, i["ndm"], i["n_out"])
+        refs.append(oracle.candidates(b, hits, alive, p.dms()))
+        say(f"c4 beam {b}: hits {hits['d'].size}, candidates {refs[-1].size}")
+    rc = np.concatenate(refs)
+    assert np.array_equal(g["cands"], rc)
+
+
 @pytest.mark.parametrize("nch", [512, 37])
 def test_tile_shapes_give_identical_results(spl, nch):
     """Every compiled tile shape and staging depth gives the oracle's results (37
