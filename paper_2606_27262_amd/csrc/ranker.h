@@ -13,6 +13,11 @@ hipError_t launch_snippets(const DevBeam *beams, int nbeams, const spl_candidate
                            hipStream_t s);
 hipError_t launch_gemm(const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb, float *C, int64_t ldc, int M,
                        int N, int K, int splits, bool accumulate, hipStream_t s);
+// Forward convolution (mode 0: first layer, NCHW 2 channels; 1: NHWC 32 channels) with
+// bias, ReLU and 2x2 max pool fused: pooled BF16 NHWC [N][H/2][W/2][32] and the pool
+// decisions; H even, W a multiple of 8, N*H*W a multiple of 64.
+hipError_t launch_conv_pool(int mode, const uint16_t *X, int N, int nvalid, int H, int W, const uint16_t *Wt, int ldw,
+                            const float *bias, uint16_t *pooled, uint8_t *arg, hipStream_t s);
 // Implicit-GEMM convolution (mode 0: first layer, NCHW 2 channels; 1: forward, NHWC 32
 // channels; 2: input gradient, NHWC 32 channels, flipped taps) into C [N*H*W][32] FP32.
 hipError_t launch_conv(int mode, const uint16_t *X, int N, int nvalid, int H, int W, const uint16_t *Wt, int ldw,
@@ -23,8 +28,6 @@ hipError_t launch_wgrad(int mode, const uint16_t *X, int N, int nvalid, int H, i
 hipError_t launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s);
 hipError_t launch_transpose16(const uint16_t *in, int64_t rows, int64_t cols, int64_t ldi, uint16_t *out, int64_t ldo,
                               hipStream_t s);
-hipError_t launch_conv_epilogue(const float *Z, const float *bias, int N, int H, int W, uint16_t *out, uint8_t *arg,
-                                hipStream_t s);
 hipError_t launch_unpool(const float *dOut, const uint8_t *arg, int N, int H, int W, uint16_t *dZ, uint16_t *dZT,
                          int64_t ldT, float *dbias, hipStream_t s);
 hipError_t launch_head(const float *Hm, const float *b1, const float *f2w, const float *f2b, int N, int Nb,

@@ -426,17 +426,39 @@ __global__ __launch_bounds__(256) void k_gemm(const uint16_t *__restrict__ A, in
 // MODE 2: 32 input channels, NHWC, src = (h - ky + 1, w - kx + 1)   (input gradient: the
 //         input is dZ and Wt the weights repacked as [ci][t*32 + co]).
 // Workgroup = 4 wavefronts x 16 pixels; each wavefront computes all 32 columns.
-template <int MODE>
+// POOL (forward only): a wavefront's 16 rows are a 2 x 8 pixel patch (rows 2ph, 2ph+1,
+// columns 8c .. 8c+7) instead of 16 consecutive pixels, so the result holds four whole
+// 2 x 2 windows: lane l keeps rows 4(l/16) .. +3, i.e. two horizontal pairs of one image
+// row, and lane l ^ 32 the pairs below them.  Bias, ReLU and the max pool (with the
+// window position of the first maximum, 255 when no element is positive) then run in
+// registers and only the pooled BF16 activation and the decision bytes are written.
+template <int MODE, bool POOL>
 __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, int N, int nvalid, int H, int W,
-                                              const uint16_t *__restrict__ Wt, int ldw, float *__restrict__ C) {
+                                              const uint16_t *__restrict__ Wt, int ldw, float *__restrict__ C,
+                                              const float *__restrict__ bias, uint16_t *__restrict__ pooled,
+                                              uint8_t *__restrict__ arg) {
     const int lane = lane_id(), wave = wave_id();
     const int64_t P = (int64_t)N * H * W;
     const int64_t m_base = (int64_t)blockIdx.x * 64 + wave * 16;
-    const int64_t p = m_base + (lane & 15);
     const int kq = 8 * (lane >> 4);
-    const int n = (int)(p / ((int64_t)H * W));
-    const int hw = (int)(p - (int64_t)n * H * W);
-    const int h = hw / W, w = hw - (hw / W) * W;
+    int64_t p;
+    int n, h, w;
+    if constexpr (POOL) {
+        const int64_t tile = m_base >> 4;                 // 2 x 8 patches, row-major per image
+        const int per_row = W >> 3, per_img = (H >> 1) * per_row;
+        n = (int)(tile / per_img);
+        const int rem = (int)(tile - (int64_t)n * per_img);
+        const int r = lane & 15;
+        h = 2 * (rem / per_row) + (r >> 3);
+        w = 8 * (rem % per_row) + (r & 7);
+        p = ((int64_t)n * H + h) * W + w;
+    } else {
+        p = m_base + (lane & 15);
+        n = (int)(p / ((int64_t)H * W));
+        const int hw = (int)(p - (int64_t)n * H * W);
+        h = hw / W;
+        w = hw - h * W;
+    }
     const bool row_ok = p < P && n < nvalid;
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
     const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -474,12 +496,50 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, in
                                                            __builtin_bit_cast(bf16x8, x1), acc1, 0, 0, 0);
         }
     }
+    if constexpr (POOL) {
+        // window k (0, 1) of this lane: own pair i = 2k, 2k+1 (window positions 0, 1),
+        // the partner lane's pair below it (positions 2, 3); positions tried in order
+        const int g = lane >> 4, co = lane & 15;
+        const int64_t tile = m_base >> 4;
+        const int per_row = W >> 3, per_img = (H >> 1) * per_row;
+        const int nn = (int)(tile / per_img);
+        const int rem = (int)(tile - (int64_t)nn * per_img);
+        const int ph = rem / per_row, pw0 = 4 * (rem % per_row) + 2 * (g & 1);
+        const int H2 = H >> 1, W2 = W >> 1;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t m = m_base + 4 * (lane >> 4) + i;
-        if (m >= P) continue;
-        C[m * 32 + (lane & 15)] = acc0[i];
-        C[m * 32 + 16 + (lane & 15)] = acc1[i];
+        for (int half = 0; half < 2; ++half) {
+            const f32x4 a = half ? acc1 : acc0;
+            const float b = bias[co + 16 * half];
+            float below[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) below[i] = __shfl_xor(a[i], 32);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const float z[4] = {a[2 * k] + b, a[2 * k + 1] + b, below[2 * k] + b, below[2 * k + 1] + b};
+                float best = 0.f;
+                int ba = 255;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (z[j] > best) {
+                        best = z[j];
+                        ba = j;
+                    }
+                }
+                if (g < 2 && tile * 16 < P) {
+                    const size_t o = (((size_t)nn * H2 + ph) * W2 + pw0 + k) * 32 + co + 16 * half;
+                    pooled[o] = f2bf(best);
+                    arg[o] = (uint8_t)ba;
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t m = m_base + 4 * (lane >> 4) + i;
+            if (m >= P) continue;
+            C[m * 32 + (lane & 15)] = acc0[i];
+            C[m * 32 + 16 + (lane & 15)] = acc1[i];
+        }
     }
 }
 
@@ -601,36 +661,6 @@ __global__ void k_transpose16(const uint16_t *__restrict__ in, int64_t rows, int
     for (int j = ty; j < 32; j += 8) {
         const int64_t c = c0 + j, r = r0 + tx;
         if (c < cols && r < rows) out[c * ldo + r] = tile[tx][j];
-    }
-}
-
-// ------------------------------------------------ conv epilogue (bias, ReLU, pool)
-// Z [N*H*W][32] FP32 -> out [N][H/2][W/2][32] BF16 = max over the 2x2 window of
-// ReLU(Z + bias); arg = window position (row-major, first maximum) of a positive maximum,
-// 255 when the pooled value is 0 (no gradient flows back).
-__global__ void k_conv_epilogue(const float *__restrict__ Z, const float *__restrict__ bias, int N, int H, int W,
-                                uint16_t *__restrict__ out, uint8_t *__restrict__ arg) {
-    const int H2 = H / 2, W2 = W / 2;
-    const int64_t total = (int64_t)N * H2 * W2 * 32;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const int co = (int)(i & 31);
-        const int64_t q = i >> 5;
-        const int n = (int)(q / ((int64_t)H2 * W2));
-        const int hw = (int)(q - (int64_t)n * H2 * W2);
-        const int h2 = hw / W2, w2 = hw - h2 * W2;
-        float best = 0.f;
-        int ba = 255;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int h = 2 * h2 + (j >> 1), w = 2 * w2 + (j & 1);
-            const float z = Z[(((size_t)n * H + h) * W + w) * 32 + co] + bias[co];
-            if (z > best) {
-                best = z;
-                ba = j;
-            }
-        }
-        out[i] = f2bf(best);
-        arg[i] = (uint8_t)ba;
     }
 }
 
@@ -829,9 +859,32 @@ hipError_t launch_conv(int mode, const uint16_t *X, int N, int nvalid, int H, in
     const int64_t P = (int64_t)N * H * W;
     if (P <= 0 || (ldw & 7)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((P + 63) / 64));
-    if (mode == 0) hipLaunchKernelGGL(k_conv<0>, grid, dim3(256), 0, s, X, N, nvalid, H, W, Wt, ldw, C);
-    else if (mode == 1) hipLaunchKernelGGL(k_conv<1>, grid, dim3(256), 0, s, X, N, nvalid, H, W, Wt, ldw, C);
-    else hipLaunchKernelGGL(k_conv<2>, grid, dim3(256), 0, s, X, N, nvalid, H, W, Wt, ldw, C);
+    float *nb = nullptr;
+    uint16_t *np = nullptr;
+    uint8_t *na = nullptr;
+    if (mode == 0)
+        hipLaunchKernelGGL((k_conv<0, false>), grid, dim3(256), 0, s, X, N, nvalid, H, W, Wt, ldw, C, nb, np, na);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_conv<1, false>), grid, dim3(256), 0, s, X, N, nvalid, H, W, Wt, ldw, C, nb, np, na);
+    else
+        hipLaunchKernelGGL((k_conv<2, false>), grid, dim3(256), 0, s, X, N, nvalid, H, W, Wt, ldw, C, nb, np, na);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_conv_pool(int mode, const uint16_t *X, int N, int nvalid, int H, int W, const uint16_t *Wt, int ldw,
+                            const float *bias, uint16_t *pooled, uint8_t *arg, hipStream_t s) {
+    const int64_t P = (int64_t)N * H * W;
+    // whole 2 x 8 patches, four per workgroup
+    if (P <= 0 || (ldw & 7) || (H & 1) || (W & 7) || (P & 63) || (mode != 0 && mode != 1)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(P / 64));
+    float *nc = nullptr;
+    if (mode == 0)
+        hipLaunchKernelGGL((k_conv<0, true>), grid, dim3(256), 0, s, X, N, nvalid, H, W, Wt, ldw, nc, bias, pooled,
+                           arg);
+    else
+        hipLaunchKernelGGL((k_conv<1, true>), grid, dim3(256), 0, s, X, N, nvalid, H, W, Wt, ldw, nc, bias, pooled,
+                           arg);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -857,14 +910,6 @@ hipError_t launch_transpose16(const uint16_t *in, int64_t rows, int64_t cols, in
     if ((cols + 31) / 32 > 65535) return hipErrorInvalidValue;
     dim3 grid((unsigned)((rows + 31) / 32), (unsigned)((cols + 31) / 32));
     hipLaunchKernelGGL(k_transpose16, grid, dim3(256), 0, s, in, rows, cols, ldi, out, ldo);
-    SPL_HIP_LAUNCH_CHECK();
-    return hipSuccess;
-}
-
-hipError_t launch_conv_epilogue(const float *Z, const float *bias, int N, int H, int W, uint16_t *out, uint8_t *arg,
-                                hipStream_t s) {
-    hipLaunchKernelGGL(k_conv_epilogue, dim3(grid_1d((int64_t)N * (H / 2) * (W / 2) * 32)), dim3(256), 0, s, Z, bias,
-                       N, H, W, out, arg);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -6,8 +6,8 @@
 // candidates pads with zero images whose gradients are zero):
 //   layer k = 1..4, input H_k x W_k (64x256, 32x128, 16x64, 8x32), Cin_k (2, 32, 32, 32),
 //   P_k = Nb*H_k*W_k output pixels, K_k = 9*Cin_k padded to a multiple of 32 (32, 288):
-//     Z     = conv(X_{k-1}, Wp_k)                   [P_k][32]   FP32 (implicit GEMM)
-//     X_k   = maxpool(ReLU(Z + b_k)), arg_k          NHWC BF16
+//     X_k, arg_k = maxpool(ReLU(conv(X_{k-1}, Wp_k) + b_k))   NHWC BF16, one kernel: the
+//                   implicit-GEMM convolution keeps its FP32 result in registers
 //   Hm = X_4 [Nb][2048 (h,w,c)] * Wf1p^T            [Nb][64]    FP32, then the VALU head.
 // Backward, layer k = 4..1, from dX = dLoss/dX_k (FP32):
 //     dZ = unpool(dX, arg_k); db_k += sums
@@ -102,7 +102,7 @@ struct spl_ranker {
     int64_t gc_w[kLayers] = {}, gc_f1 = 0;                                   // element offsets in gc
     // per-pass buffers
     size_t off_X[kLayers] = {}, off_arg[kLayers] = {};
-    size_t off_Z = 0, off_Hm = 0, off_logits = 0, off_dH = 0, off_dHT = 0, off_X4T = 0, off_dX = 0;
+    size_t off_Hm = 0, off_logits = 0, off_dH = 0, off_dHT = 0, off_X4T = 0, off_dX = 0;
     size_t off_dZ = 0, off_part = 0;
     std::vector<int32_t> pack_idx, gc_idx;
 
@@ -196,7 +196,6 @@ void layout(spl_ranker *R) {
         max_dz = std::max(max_dz, R->P(k) * kCout);
         if (k > 0) max_dx = std::max(max_dx, R->P(k) * kCout);
     }
-    R->off_Z = take((size_t)R->P(0) * kCout * 4);
     R->off_Hm = take((size_t)nb * kFcHidden * 4);
     R->off_logits = take((size_t)nb * 4 + 4);  // + loss slot
     R->off_dH = take((size_t)nb * kFcHidden * 2);
@@ -229,12 +228,10 @@ spl_status forward(spl_ranker *R, const uint16_t *snip, int n, hipStream_t s) {
     const int nb = R->nb;
     const uint16_t *packed = R->at<uint16_t>(R->off_packed);
     const float *master = R->at<float>(R->off_master);
-    float *Z = R->at<float>(R->off_Z);
     for (int k = 0; k < kLayers; ++k) {
         const uint16_t *in = k == 0 ? snip : R->at<uint16_t>(R->off_X[k - 1]);
-        RK_TRY(launch_conv(k == 0 ? 0 : 1, in, nb, k == 0 ? n : nb, kH[k], kW[k], packed + R->pk_wp[k], kKp[k], Z, s));
-        RK_TRY(launch_conv_epilogue(Z, master + R->po.cb[k], nb, kH[k], kW[k], R->at<uint16_t>(R->off_X[k]),
-                                    R->at<uint8_t>(R->off_arg[k]), s));
+        RK_TRY(launch_conv_pool(k == 0 ? 0 : 1, in, nb, k == 0 ? n : nb, kH[k], kW[k], packed + R->pk_wp[k], kKp[k],
+                                master + R->po.cb[k], R->at<uint16_t>(R->off_X[k]), R->at<uint8_t>(R->off_arg[k]), s));
     }
     RK_TRY(gemm(R->at<uint16_t>(R->off_X[3]), kFcIn, packed + R->pk_f1, kFcIn, R->at<float>(R->off_Hm), kFcHidden, nb,
                 kFcHidden, kFcIn, s));
