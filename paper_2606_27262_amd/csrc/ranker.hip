@@ -165,16 +165,18 @@ __global__ __launch_bounds__(256) void k_snippets(const DevBeam *__restrict__ be
 // of its valid entries (one mu, sigma for all rows, so the S/N falling off away from
 // DM* stays visible), float((v - mu)/sigma) in binary64 -> BF16, invalid entries 0.
 // One workgroup of 1024 threads per candidate: thread (g = tid/64, q = tid%64) owns
-// samples 4q .. 4q+3 of rows g, g+16, g+32, g+48.  Channels go in chunks of 16: the
+// samples 4q .. 4q+3 of rows g, g+16, g+32, g+48.  Channels go in chunks of 8: the
 // delays of the 64 rows are computed into the LDS, then each channel's window of the
 // block (the 256 samples plus the spread of its 64 delays) is staged as four copies
 // shifted by 0..3 bytes, so every 4-sample read of any row is one aligned LDS dword
-// (a wave's 64 lanes read 64 consecutive dwords: no bank conflicts).  Windows wider
+// (a wave's 64 lanes read 64 consecutive dwords: no bank conflicts).  The three steps
+// are pipelined over chunks (sums of chunk k, staging of k+1, delays of k+2) with one
+// barrier per chunk, so the waves of the one workgroup a CU holds overlap them.  Windows wider
 // than the staging buffer (wide pulses: dDM grows with the width) are read from the
 // block directly, two aligned dwords per 4 samples.  Sums go through 16-bit pairs,
 // flushed before they exceed 256 channels (< 2^16).
-constexpr int kFineChunk = 16;
-constexpr int kFineWords = 512;   // staged dwords per channel and copy (window <= 2 KiB; 128 KiB of LDS)
+constexpr int kFineChunk = 8;
+constexpr int kFineWords = 512;   // staged dwords per channel and copy (window <= 2 KiB)
 
 __device__ inline int64_t fine_delay(double dd, double k, double tsamp) {
     const double v = (dd * k) / tsamp;
@@ -197,10 +199,13 @@ __global__ __launch_bounds__(1024) void k_fine_dm(const DevBeam *__restrict__ be
     constexpr uint32_t kSelEven = 0x0C020C00u;
     constexpr uint32_t kSelOdd = 0x0C030C01u;
     constexpr double kD = 4148.8064239;   // Eq. (1), MHz^2 pc^-1 cm^3 s
-    __shared__ uint32_t stage[kFineChunk][4][kFineWords];
-    __shared__ int32_t sdel[64][kFineChunk];
-    __shared__ int64_t sgs[kFineChunk];
-    __shared__ int32_t snw[kFineChunk];
+    // three-stage pipeline over channel chunks: while chunk k is summed from stage buffer
+    // k&1, chunk k+1 is staged into the other buffer and the delays of chunk k+2 are
+    // computed into delay set (k+2)%3; one barrier per chunk
+    __shared__ uint32_t stage[2][kFineChunk][4][kFineWords];
+    __shared__ int32_t sdel[3][64][kFineChunk];
+    __shared__ int64_t sgs[3][kFineChunk];
+    __shared__ int32_t snw[3][kFineChunk];
     __shared__ int64_t sh[3][16];
     const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
     const int g = tid >> 6, q = tid & 63;
@@ -236,6 +241,52 @@ __global__ __launch_bounds__(1024) void k_fine_dm(const DevBeam *__restrict__ be
             for (int j = 0; j < 4; ++j)
                 if (ta + j + smin >= 0 && ta + j + smax < (int64_t)B.n_in) vmask |= 1u << (4 * i + j);
         }
+        const int nchunks = (B.nch + kFineChunk - 1) / kFineChunk;
+
+        // delays of chunk `chunk` into set `set`: wavefront w (< kFineChunk) takes channel
+        // w, lane = row (Eq. (1) as a plan computes it).  The delays are monotone in the
+        // row, so rows 0 and 63 bound the channel's window; each lane then stores its
+        // row's LDS byte offset into the staged copies ((rel & 3) selects the copy,
+        // rel >> 2 the dword, rel = t_first + delay - window start), or the raw delay when
+        // the channel is read from the block (window too wide, or any offset out of range)
+        auto delays = [&](int chunk, int set) {
+            const int cc = wave, rr = lane;
+            const int c0 = chunk * kFineChunk, nc = min(kFineChunk, B.nch - c0);
+            const double f = B.fch1 + (double)(c0 + cc) * B.foff;
+            const double kc = cc < nc ? (1.0 / (f * f)) - (1.0 / (B.fref * B.fref)) : 0.0;
+            const int64_t sv = fine_delay(kD * (dm_star + (double)(rr - 32) * step), kc, B.tsamp);
+            const int64_t s0 = __shfl(sv, 0), s63 = __shfl(sv, 63);
+            const int64_t lo = s0 < s63 ? s0 : s63, hi = s0 < s63 ? s63 : s0;
+            const int64_t gs = (t_first + lo) & ~(int64_t)3;
+            const int64_t nw = ((t_first + 252 + hi - gs) >> 2) + 1;   // dwords holding every read
+            const int64_t rel = t_first + sv - gs;
+            const bool bad = rel < 0 || (rel >> 2) + 63 > nw - 1;
+            const bool staged = cc < nc && nw + 1 <= kFineWords && !__any(bad);
+            sdel[set][rr][cc] =
+                staged ? (int32_t)(cc * (4 * kFineWords * 4) + (int)(rel & 3) * (kFineWords * 4) + (int)(rel >> 2) * 4)
+                       : (int32_t)(sv > (1 << 30) ? (1 << 30) : (sv < -(1 << 30) ? -(1 << 30) : sv));
+            if (lane == 0) {
+                sgs[set][cc] = gs;
+                snw[set][cc] = staged ? (int32_t)nw : 0;   // 0: read the block
+            }
+        };
+        // the window of every channel of chunk `chunk` as four byte-shifted copies
+        auto stage_chunk = [&](int chunk, int set, int buf) {
+            const int c0 = chunk * kFineChunk;
+            for (int e = tid; e < kFineChunk * kFineWords; e += 1024) {
+                const int cc = e / kFineWords, i = e % kFineWords;
+                if (i < snw[set][cc]) {
+                    const uint8_t *row = B.x + (size_t)(c0 + cc) * B.pitch;
+                    const int64_t t = sgs[set][cc] + 4 * (int64_t)i;
+                    const uint32_t w0 = block_dword(row, t, B.n_in), w1 = block_dword(row, t + 4, B.n_in);
+                    stage[buf][cc][0][i] = w0;
+                    stage[buf][cc][1][i] = __builtin_amdgcn_alignbyte(w1, w0, 1);
+                    stage[buf][cc][2][i] = __builtin_amdgcn_alignbyte(w1, w0, 2);
+                    stage[buf][cc][3][i] = __builtin_amdgcn_alignbyte(w1, w0, 3);
+                }
+            }
+        };
+
         int32_t acc[4][4];
         uint32_t ae[4], ao[4];
 #pragma unroll
@@ -245,43 +296,17 @@ __global__ __launch_bounds__(1024) void k_fine_dm(const DevBeam *__restrict__ be
             for (int j = 0; j < 4; ++j) acc[i][j] = 0;
         }
         int pending = 0;   // channels in the 16-bit pair sums
-        for (int c0 = 0; c0 < B.nch; c0 += kFineChunk) {
-            const int nc = min(kFineChunk, B.nch - c0);
-            __syncthreads();   // the previous chunk's staging is no longer read
-            {
-                // one delay per thread: row rr, channel cc of the chunk (Eq. (1) as a plan
-                // computes it); the row-0 thread of a channel also bounds its window (the
-                // delays are monotone in the row, so rows 0 and 63 are the extremes)
-                const int rr = tid / kFineChunk, cc = tid % kFineChunk;
-                const double f = B.fch1 + (double)(c0 + cc) * B.foff;
-                const double kc = cc < nc ? (1.0 / (f * f)) - (1.0 / (B.fref * B.fref)) : 0.0;
-                const int64_t sv = fine_delay(kD * (dm_star + (double)(rr - 32) * step), kc, B.tsamp);
-                sdel[rr][cc] = (int32_t)(sv > (1 << 30) ? (1 << 30) : (sv < -(1 << 30) ? -(1 << 30) : sv));
-                if (rr == 0) {
-                    const int64_t s63 = fine_delay(kD * (dm_star + 31.0 * step), kc, B.tsamp);
-                    const int64_t a0 = sv, a1 = s63;
-                    const int64_t lo = a0 < a1 ? a0 : a1, hi = a0 < a1 ? a1 : a0;
-                    const int64_t gs = (t_first + lo) & ~(int64_t)3;
-                    const int64_t nw = ((t_first + 252 + hi - gs) >> 2) + 1;   // dwords holding every read
-                    sgs[cc] = gs;
-                    snw[cc] = (cc < nc && nw + 1 <= kFineWords) ? (int32_t)nw : 0;   // 0: read the block
-                }
-            }
-            __syncthreads();
-            for (int e = tid; e < kFineChunk * kFineWords; e += 1024) {
-                const int cc = e / kFineWords, i = e % kFineWords;
-                const int nw = snw[cc];
-                if (i < nw) {
-                    const uint8_t *row = B.x + (size_t)(c0 + cc) * B.pitch;
-                    const int64_t t = sgs[cc] + 4 * (int64_t)i;
-                    const uint32_t w0 = block_dword(row, t, B.n_in), w1 = block_dword(row, t + 4, B.n_in);
-                    stage[cc][0][i] = w0;
-                    stage[cc][1][i] = __builtin_amdgcn_alignbyte(w1, w0, 1);
-                    stage[cc][2][i] = __builtin_amdgcn_alignbyte(w1, w0, 2);
-                    stage[cc][3][i] = __builtin_amdgcn_alignbyte(w1, w0, 3);
-                }
-            }
-            __syncthreads();
+
+        if (wave < kFineChunk) {
+            delays(0, 0);
+            if (nchunks > 1) delays(1, 1);
+        }
+        __syncthreads();
+        stage_chunk(0, 0, 0);
+        __syncthreads();
+        for (int k = 0; k < nchunks; ++k) {
+            const int set = k % 3, buf = k & 1;
+            const int c0 = k * kFineChunk, nc = min(kFineChunk, B.nch - c0);
             if (pending + nc > 256) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -295,23 +320,19 @@ __global__ __launch_bounds__(1024) void k_fine_dm(const DevBeam *__restrict__ be
             }
             pending += nc;
             for (int cc = 0; cc < nc; ++cc) {
-                const int nw = snw[cc];   // the same for the whole workgroup
+                const int nw = snw[set][cc];   // the same for the whole workgroup
                 if (nw > 0) {
-                    const int64_t base = ta - sgs[cc];
-                    const uint32_t lim = 4u * (uint32_t)nw;
+                    const uint8_t *lbase = (const uint8_t *)&stage[buf][0][0][0] + 4 * q;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int64_t off = base + sdel[g + 16 * i][cc];
-                        // in range by the monotone delays; checked all the same
-                        const uint32_t o = (off >= 0 && off < (int64_t)lim) ? (uint32_t)off : 0u;
-                        const uint32_t word = stage[cc][o & 3u][o >> 2];
+                        const uint32_t word = *(const uint32_t *)(lbase + sdel[set][g + 16 * i][cc]);
                         ae[i] += __builtin_amdgcn_perm(word, word, kSelEven);
                         ao[i] += __builtin_amdgcn_perm(word, word, kSelOdd);
                     }
                 } else {
                     const uint8_t *row = B.x + (size_t)(c0 + cc) * B.pitch;
                     for (int i = 0; i < 4; ++i) {
-                        const int64_t t = ta + sdel[g + 16 * i][cc];
+                        const int64_t t = ta + sdel[set][g + 16 * i][cc];
                         const int64_t t4 = t & ~(int64_t)3;
                         const uint32_t word = __builtin_amdgcn_alignbyte(block_dword(row, t4 + 4, B.n_in),
                                                                          block_dword(row, t4, B.n_in),
@@ -321,6 +342,9 @@ __global__ __launch_bounds__(1024) void k_fine_dm(const DevBeam *__restrict__ be
                     }
                 }
             }
+            if (k + 1 < nchunks) stage_chunk(k + 1, (k + 1) % 3, (k + 1) & 1);
+            if (k + 2 < nchunks && wave < kFineChunk) delays(k + 2, (k + 2) % 3);
+            __syncthreads();
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
