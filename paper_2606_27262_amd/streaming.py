@@ -13,10 +13,14 @@ behind the big copy).  For block k, slot k % 3:
                  path (grouping, snippets and CNN on a third stream, anti-coincidence)
 So the copy of the next block and the candidate stage of the previous one both overlap
 the search of the current one.  Every copy between host and device goes through pinned
-buffers on a stream (candidate records and statistics are copied on the compute stream
-right after the search): a copy into pageable host memory would wait for the whole
-device, i.e. for the search of the next block.  All device memory and streams come from torch; every
-step of the search runs in libspotlight.
+buffers on a stream: a copy into pageable host memory would wait for the whole device,
+i.e. for the search of the next block.  The run statistics and a prefix of the
+candidate records (a power of two above the largest count seen) follow the search on
+the compute stream; records beyond the prefix, if a block has more, are fetched after
+the statistics arrive.  Copying the whole 1M-record buffer there instead queued it
+behind the next block's 2.6 GB upload and held back the next search by ~7 ms.  All
+device memory and streams come from torch; every step of the search runs in
+libspotlight.
 """
 from __future__ import annotations
 
@@ -57,6 +61,11 @@ class StreamingSearch:
         self.copy_stream = torch.cuda.Stream()
         self.compute_stream = torch.cuda.Stream()
         self.rank_stream = torch.cuda.Stream()
+        # records copied back right behind each search: a power of two above the largest
+        # count seen (the whole 1M-record buffer queued behind the next block's upload on
+        # the copy engine and held back the next search by ~7 ms)
+        self.copy_hint = min(cand_capacity, 1 << 17)
+        self.copied = [0, 0, 0]
         self.tsamp = np.array([pd["tsamp"] for pd in pds], np.float64)
 
     def attach(self, tile_cache=None):
@@ -79,13 +88,30 @@ class StreamingSearch:
         torch.cuda.synchronize()
         return reps * sum(h.numel() for h in host_set) / (e0.elapsed_time(e1) / 1e3)
 
-    def _stage(self, slot):
-        """Candidate stage of the block searched in batch `slot`: its records are already in
-        pinned host memory (the search's copy has completed)."""
+    def _fetch(self, slot, searched):
+        """Complete the block's candidate records on the host: the prefix copied behind
+        the search already holds the first `copied` of them; any beyond it are copied now
+        (and the prefix grows for later blocks).  Returns their number and the search's
+        total."""
+        import torch
+        n = int(self.h_stats[slot][1])
+        cap = self.h_cands[slot].shape[0]
+        m = min(n, cap)
+        c = self.copied[slot]
+        if m > c:   # rare: more records than the prefix; the common path touches no stream
+            self.rank_stream.wait_event(searched)
+            with torch.cuda.stream(self.rank_stream):
+                self.h_cands[slot][c:m].copy_(self.cands[slot][c:m], non_blocking=True)
+            self.rank_stream.synchronize()
+        while self.copy_hint < cap and self.copy_hint < m + (m >> 2):
+            self.copy_hint = min(cap, 2 * self.copy_hint)
+        return m, n
+
+    def _stage(self, slot, m, n):
+        """Candidate stage of the block searched in batch `slot`: its m records are in
+        pinned host memory."""
         import torch
         spl = self.spl
-        n = int(self.h_stats[slot][1])
-        m = min(n, self.h_cands[slot].shape[0])
         recs = self.h_cands[slot][:m].numpy().view(spl.CAND_DTYPE).reshape(-1).copy()
         if self.ranker is None:
             return spl.optimise_plain(recs, self.tsamp, self.nb), n
@@ -109,14 +135,19 @@ class StreamingSearch:
         final, _, _ = ranking.ranker_path(spl, recs, self.tsamp, self.nb, score)
         return final, n
 
-    def run(self, host_sets, n_blocks, warmup=2, on_block=None):
+    def run(self, host_sets, n_blocks, warmup=2, on_block=None, timing=None):
         """Stream n_blocks blocks, block k taken from host_sets[k % len(host_sets)] (lists of
         pinned uint8 tensors [nch][pitch], one per beam).  Returns the wall time per block
-        over the blocks after `warmup` and the per-block results of on_block(k, final,
-        n_candidates)."""
+        over the blocks after `warmup` (the last block's candidate stage, which nothing
+        overlaps, included) and the per-block results of on_block(k, final,
+        n_candidates).  With a dict `timing`, also fills in the steady-state period: the
+        device time from the first measured block's start to the end of the last block's
+        search and its copies back, per block ("steady_s"), and the candidate stage of the
+        last block alone ("drain_s")."""
         import torch
         copied = [torch.cuda.Event() for _ in range(3)]
-        searched = [torch.cuda.Event() for _ in range(3)]
+        searched = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        t_ev0 = torch.cuda.Event(enable_timing=True)
         results = []
 
         def enqueue_copy(k):
@@ -131,9 +162,11 @@ class StreamingSearch:
             s = k % 3
             self.compute_stream.wait_event(copied[s])
             self.batches[s].run(self.dev[s], self.cands[s], self.stats[s], stream=self.compute_stream)
+            c = self.copy_hint
             with torch.cuda.stream(self.compute_stream):
                 self.h_stats[s].copy_(self.stats[s], non_blocking=True)
-                self.h_cands[s].copy_(self.cands[s], non_blocking=True)
+                self.h_cands[s][:c].copy_(self.cands[s][:c], non_blocking=True)
+            self.copied[s] = c
             searched[s].record(self.compute_stream)
 
         torch.cuda.synchronize()
@@ -143,15 +176,23 @@ class StreamingSearch:
             if k == warmup:
                 torch.cuda.synchronize()
                 t_start = time.perf_counter()
+                t_ev0.record(self.compute_stream)
             if k < n_blocks:
                 enqueue_search(k)
             if k + 1 < n_blocks:
                 enqueue_copy(k + 1)   # set (k+1) % 3 last held block k-2, done in the previous iteration
             if k >= 1:
                 searched[(k - 1) % 3].synchronize()
-                final, ncand = self._stage((k - 1) % 3)
+                t_stage = time.perf_counter()
+                m, ncand = self._fetch((k - 1) % 3, searched[(k - 1) % 3])
+                final, ncand = self._stage((k - 1) % 3, m, ncand)
                 if on_block is not None:
                     results.append(on_block(k - 1, final, ncand))
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t_start
-        return wall / max(1, n_blocks - warmup), results
+        t_end = time.perf_counter()
+        wall = t_end - t_start
+        m = max(1, n_blocks - warmup)
+        if timing is not None:
+            timing["steady_s"] = t_ev0.elapsed_time(searched[(n_blocks - 1) % 3]) / 1e3 / m
+            timing["drain_s"] = t_end - t_stage
+        return wall / m, results

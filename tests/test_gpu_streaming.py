@@ -58,6 +58,14 @@ def test_stream_equals_direct_runs(spl):
         print(f"block {k}: {n} candidates, {final.size} kept", flush=True)
         assert n == rn
         assert np.array_equal(final.view(np.int32), rf.view(np.int32)), k
+    # a record prefix far smaller than the blocks' candidate counts: the records beyond
+    # it are fetched after the statistics, with the same results, and the prefix grows
+    ss.copy_hint = 16
+    _, res = ss.run(sets, 4, warmup=1, on_block=lambda k, f, n: (k, f.copy(), n))
+    for k, final, n in res:
+        rf, rn = ref[k % 2]
+        assert n == rn and np.array_equal(final.view(np.int32), rf.view(np.int32)), k
+    assert ss.copy_hint >= min(1 << 16, max(r[1] for r in ref))
     # the ranker path runs through the same pipeline and keeps a subset of its inputs
     w = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2606_27262_amd", "data",
                      "ranker_weights.npy")
