@@ -217,3 +217,41 @@ def test_smearing_ranges_equal_oracle(band):
         dms = oracle.dm_trials(got)
         D, ties = oracle.delay_table(p["nchans"], p["fch1"], p["foff"], p["tsamp"], dms)
         assert ties == 0 and np.array_equal(plan.delays().astype(np.int64), D)
+
+
+def test_injector_argument_checks_before_any_device_work():
+    """spl_inject_quantised refuses bad quantisers, modes, shapes and missing buffers on
+    the host; empty work returns SPL_OK without touching a device."""
+    lib = spl._lib
+    Q = spl._Quantiser
+    P = ctypes.c_void_p
+    fake = P(16)   # never dereferenced: every call below fails or returns before a launch
+
+    def call(q, mode=spl.INJECT_ARGMAX, nch=4, n_t=64, pitch=64, n_win=1, n_sig=8, block=fake, ts=fake,
+             sig=fake, words=None):
+        return lib.spl_inject_quantised(block, pitch, n_t, nch, ts, sig, words, n_win, n_sig,
+                                        None if q is None else ctypes.byref(q), mode, None)
+
+    good = Q(bits=8, reserved=0, mu=128.0, sigma=16.0, level=1.0 / 16, offset=-0.5)
+    assert call(None) == spl.SPL_E_INVALID_ARG
+    for bad in (Q(0, 0, 0.0, 1.0, 1.0, 0.0), Q(9, 0, 0.0, 1.0, 1.0, 0.0), Q(8, 0, 0.0, 0.0, 1.0, 0.0),
+                Q(8, 0, 0.0, 1.0, -1.0, 0.0), Q(8, 0, float("nan"), 1.0, 1.0, 0.0),
+                Q(8, 0, 0.0, 1.0, 1.0, float("inf"))):
+        assert call(bad) == spl.SPL_E_INVALID_ARG
+    assert call(good, mode=2) == spl.SPL_E_INVALID_ARG
+    assert call(good, nch=0) == spl.SPL_E_INVALID_ARG
+    assert call(good, pitch=32) == spl.SPL_E_INVALID_ARG        # pitch < n_t
+    assert call(good, n_sig=-1) == spl.SPL_E_INVALID_ARG
+    assert call(good, block=None) == spl.SPL_E_INVALID_ARG
+    assert call(good, mode=spl.INJECT_SAMPLE) == spl.SPL_E_INVALID_ARG   # SAMPLE needs random words
+    # nothing to do: no launch, no error
+    assert call(good, n_t=0, block=None) == spl.SPL_OK
+    assert call(good, n_win=0, block=None) == spl.SPL_OK
+    assert call(good, n_sig=0, block=None) == spl.SPL_OK
+
+
+def test_fine_snippets_argument_checks():
+    lib = spl._lib
+    assert lib.spl_ranker_snippets_fine(None, None, 0, 1.5, None, None) == spl.SPL_E_INVALID_ARG
+    assert lib.spl_ranker_snippets_fine(None, None, 0, 0.0, None, None) == spl.SPL_E_INVALID_ARG
+    assert lib.spl_ranker_snippets_fine(None, None, 0, 0.1, None, None) == spl.SPL_E_INVALID_ARG   # no batch
