@@ -323,11 +323,28 @@ __global__ __launch_bounds__(kThreads) void k_thresholds(const DevBeam *__restri
     const int32_t *Xr = B.X + (size_t)d * B.xpitch;
     for (int sg = 0; sg < B.nseg; ++sg) {
         const int lo = sg * B.L, hi = min((sg + 1) * B.L, B.n_out);
+        // exact integer moments: 16-byte loads over the aligned middle of the segment
+        // (rows start 256-byte aligned), single values at its ends
         int64_t s1 = 0, s2 = 0;
-        for (int t = lo + (int)threadIdx.x; t < hi; t += kThreads) {
+        const int a0 = min(hi, (lo + 3) & ~3), a1 = max(a0, hi & ~3);
+        for (int t = lo + (int)threadIdx.x; t < a0; t += kThreads) {
             const int64_t v = Xr[t];
             s1 += v;
             s2 += v * v;
+        }
+        for (int t = a1 + (int)threadIdx.x; t < hi; t += kThreads) {
+            const int64_t v = Xr[t];
+            s1 += v;
+            s2 += v * v;
+        }
+        const int4 *V = (const int4 *)(Xr + a0);
+        const int nv = (a1 - a0) >> 2;
+#pragma unroll 4
+        for (int i = (int)threadIdx.x; i < nv; i += kThreads) {
+            const int4 q = V[i];
+            const int64_t x = q.x, y = q.y, z = q.z, w = q.w;
+            s1 += (x + y) + (z + w);
+            s2 += (x * x + y * y) + (z * z + w * w);
         }
         int64_t t1, t2;
         (void)block_exclusive_scan<int64_t>(s1, &t1, sh);
