@@ -1024,7 +1024,10 @@ extern "C" spl_status spl_autotune(spl_batch *B, const uint8_t *const *d_blocks,
         B->cur_pitch[b] = pitches[b];
     }
     auto cache = read_cache(cache_path);
-    static const int shapes[][3] = {{2, 2, 8}, {4, 1, 4}, {4, 2, 4}, {4, 1, 8}, {4, 2, 8}, {8, 1, 4}, {8, 1, 8}};
+    constexpr int kTuneBeams = 4;
+    // 16-wavefront tiles (64 trials) share each staged channel row among twice the trials
+    static const int shapes[][3] = {{2, 2, 8}, {4, 1, 4}, {4, 2, 4}, {4, 1, 8}, {4, 2, 8}, {8, 1, 4}, {8, 1, 8},
+                                    {4, 1, 16}, {4, 2, 16}};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1065,12 +1068,23 @@ extern "C" spl_status spl_autotune(spl_batch *B, const uint8_t *const *d_blocks,
                 if (st != SPL_OK) { result = st; break; }
                 const DevBeam *beams = (const DevBeam *)(B->ws + B->off_beams);
                 const DedispItem *items = (const DedispItem *)(B->ws + B->off_items);
-                const int lo = B->item_base[rep], hi = lo + L.ntile_d * L.ntile_t;
+                // time the shape as a batched run launches it: one persistent launch (grid from
+                // the occupancy, work items from a queue) over up to kTuneBeams consecutive
+                // beams of this plan; one beam with one workgroup per item favours small
+                // tiles through its tail
+                int b_end = rep + 1;
+                while (b_end < B->nb && b_end < rep + kTuneBeams && B->layout_of_beam[b_end] == (int)li) ++b_end;
+                const int lo = B->item_base[rep], hi = B->item_base[b_end - 1] + L.ntile_d * L.ntile_t;
                 const Tiles t = L.tiles;
+                int occ = 0;
+                HIP_TRY(prepare_dedisp(t.dw, t.j, t.nw, t.sv, B->beam_lds[rep], &occ));
+                const int grid = std::min(hi - lo, std::max(1, occ) * 256);
+                int *queue = &((DevRun *)(B->ws + B->off_run))->queue[0];
                 float best_run = 1e30f;
                 for (int r = 0; r < 4; ++r) {
+                    HIP_TRY(hipMemsetAsync(queue, 0, sizeof(int), stream));
                     HIP_TRY(hipEventRecord(e0, stream));
-                    HIP_TRY(launch_dedisp(t.dw, t.j, t.nw, t.sv, beams, items, lo, hi, nullptr, hi - lo,
+                    HIP_TRY(launch_dedisp(t.dw, t.j, t.nw, t.sv, beams, items, lo, hi, queue, grid,
                                           B->beam_lds[rep], stream));
                     HIP_TRY(hipEventRecord(e1, stream));
                     HIP_TRY(hipEventSynchronize(e1));
