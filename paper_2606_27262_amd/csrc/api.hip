@@ -1069,12 +1069,20 @@ extern "C" spl_status spl_autotune(spl_batch *B, const uint8_t *const *d_blocks,
                 const DevBeam *beams = (const DevBeam *)(B->ws + B->off_beams);
                 const DedispItem *items = (const DedispItem *)(B->ws + B->off_items);
                 // time the shape as a batched run launches it: one persistent launch (grid from
-                // the occupancy, work items from a queue) over up to kTuneBeams consecutive
-                // beams of this plan; one beam with one workgroup per item favours small
-                // tiles through its tail
-                int b_end = rep + 1;
-                while (b_end < B->nb && b_end < rep + kTuneBeams && B->layout_of_beam[b_end] == (int)li) ++b_end;
-                const int lo = B->item_base[rep], hi = B->item_base[b_end - 1] + L.ntile_d * L.ntile_t;
+                // the occupancy, work items from a queue) over up to kTuneBeams beams of this
+                // plan whose work items follow each other in the item list (beams of one
+                // shape are listed in beam order, so other plans' beams of a different shape
+                // leave gaps only in beam numbers); one beam with one workgroup per item
+                // favours small tiles through its tail
+                const int per_beam = L.ntile_d * L.ntile_t;
+                const int lo = B->item_base[rep];
+                int hi = lo + per_beam, used = 1;
+                for (int b = rep + 1; b < B->nb && used < kTuneBeams; ++b) {
+                    if (B->layout_of_beam[b] != (int)li) continue;
+                    if (B->item_base[b] != hi) break;
+                    hi += per_beam;
+                    ++used;
+                }
                 const Tiles t = L.tiles;
                 int occ = 0;
                 HIP_TRY(prepare_dedisp(t.dw, t.j, t.nw, t.sv, B->beam_lds[rep], &occ));
