@@ -275,6 +275,8 @@ struct spl_batch {
     size_t off_S_all = 0, bytes_S_all = 0;
     size_t off_counts = 0, off_chunk_off = 0, off_block_sums = 0, off_row_start = 0;
     size_t off_hits = 0, off_alive0 = 0, off_alive1 = 0, off_pos = 0, off_run = 0;
+    size_t off_nms_blk = 0;   // block index of the hit rows [n_rows][nms_nblk] int32
+    int nms_nblk = 0;
     int n_block_sums = 0;
     std::vector<int> xpitch;
     std::vector<DevBeam> host_beams;
@@ -530,6 +532,12 @@ static spl_status build_layout(spl_batch *B) {
     B->n_block_sums = std::max(scan_blocks(B->n_chunks), scan_blocks(B->hit_cap)) + 1;
     B->off_block_sums = take((size_t)B->n_block_sums * sizeof(int64_t));
     B->off_row_start = take((size_t)(B->n_rows + 1) * sizeof(int64_t));
+    {
+        int n_out_max = 1;
+        for (int b = 0; b < nb; ++b) n_out_max = std::max(n_out_max, B->plans[b]->n_out);
+        B->nms_nblk = ((n_out_max >> kNmsBlockShift) + 3) & ~1;   // >= 2 past the largest block, even
+        B->off_nms_blk = take((size_t)B->n_rows * B->nms_nblk * sizeof(int32_t));
+    }
     B->off_hits = take((size_t)B->hit_cap * sizeof(Hit));
     B->off_alive0 = take((size_t)B->hit_cap);
     B->off_alive1 = take((size_t)B->hit_cap);
@@ -806,10 +814,13 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
     HIP_TRY(t_bc.stop());
     // 4. peak filters, then ordered compaction into candidate records
     StageTimer t_pk(B, s, SPL_STAGE_PEAKS);
+    int32_t *blk = (int32_t *)(B->ws + B->off_nms_blk);
+    if (max_nst)
+        HIP_TRY(launch_nms_index(row_lo, row_hi - row_lo, hits, &run->n_hits, cap, row_start, blk, B->nms_nblk, s));
     const uint8_t *in = nullptr;
     for (int k = 0; k < max_nst; ++k) {
         uint8_t *o = alive[k & 1];
-        HIP_TRY(launch_nms(beams, b_lo, b_hi, row_lo, hits, &run->n_hits, cap, row_start, k, in, o,
+        HIP_TRY(launch_nms(beams, b_lo, b_hi, row_lo, hits, &run->n_hits, cap, row_start, blk, B->nms_nblk, k, in, o,
                            &run->n_alive[k], s));
         in = o;
     }

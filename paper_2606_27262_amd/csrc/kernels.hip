@@ -629,15 +629,57 @@ __global__ void k_row_start(const DevBeam *__restrict__ beams, int beam_lo, int 
     if (r == row_hi) row_start[r - row_lo] = stored;
 }
 
+// ------------------------------------------------------- block index of hit rows
+// blk[r][b] = index (within row r) of the first hit with t >= 64 b, or the row's hit count.
+// k_nms_mark writes the first hit of every occupied block (the table holds INT32_MAX
+// elsewhere); k_nms_suffix then takes the suffix minimum along each row.
+__global__ __launch_bounds__(kThreads) void k_nms_mark(int row_lo, const Hit *__restrict__ hits,
+                                                       const int64_t *n_hits, int64_t cap,
+                                                       const int64_t *__restrict__ row_start, int32_t *blk,
+                                                       int nblk) {
+    const int64_t n = min(*n_hits, cap);
+    for (int64_t q = blockIdx.x * (int64_t)kThreads + threadIdx.x; q < n; q += (int64_t)gridDim.x * kThreads) {
+        const Hit h = hits[q];
+        const int r = h.row - row_lo;
+        const int b = h.t >> kNmsBlockShift;
+        const bool first = q == 0 || hits[q - 1].row != h.row || (hits[q - 1].t >> kNmsBlockShift) != b;
+        if (first) blk[(int64_t)r * nblk + b] = (int32_t)(q - row_start[r]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_nms_suffix(const int64_t *__restrict__ row_start, int n_rows,
+                                                         int32_t *blk, int nblk) {
+    const int lane = lane_id();
+    const int r = blockIdx.x * (kThreads / 64) + wave_id();
+    if (r >= n_rows) return;   // uniform per wavefront
+    int32_t carry = (int32_t)(row_start[r + 1] - row_start[r]);
+    int32_t *row = blk + (int64_t)r * nblk;
+    for (int c = (nblk - 1) & ~63; c >= 0; c -= 64) {
+        const int b = c + lane;
+        int32_t v = b < nblk ? row[b] : INT_MAX;
+        v = min(v, carry);
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t o = __shfl_down(v, off);
+            if (lane + off < 64) v = min(v, o);
+        }
+        if (b < nblk) row[b] = v;
+        carry = __shfl(v, 0);
+    }
+}
+
 // ---------------------------------------------------------------- peak filter
 // q beats p when (snr_q, -d_q, -t_q) > (snr_p, -d_p, -t_p).  p survives when no other
 // alive hit of its beam within |dd| <= rd, |dt| <= rt beats it.  Rows of a beam are
-// contiguous in the hit list and sorted by t, so each neighbour row is searched by
-// bisection.
+// contiguous in the hit list and sorted by t; a neighbour row's window starts at the
+// first hit with t >= t_p - rt, found by bisection between the row's first hits of that
+// 64-sample block and of the next (the block index, built once per run by k_nms_mark and
+// k_nms_suffix): at most 6 dependent loads instead of one per halving of the row.
 __global__ __launch_bounds__(kThreads) void k_nms(const DevBeam *__restrict__ beams, int beam_lo, int beam_hi,
                                                   int row_lo, const Hit *__restrict__ hits,
                                                   const int64_t *n_hits, int64_t cap,
-                                                  const int64_t *__restrict__ row_start, int stencil,
+                                                  const int64_t *__restrict__ row_start,
+                                                  const int32_t *__restrict__ blk, int nblk, int stencil,
                                                   const uint8_t *alive_in, uint8_t *alive_out,
                                                   int64_t *n_alive) {
     __shared__ int64_t sh[kThreads / 64];
@@ -662,13 +704,21 @@ __global__ __launch_bounds__(kThreads) void k_nms(const DevBeam *__restrict__ be
             const int d2 = d + dd;
             if (d2 < 0 || d2 >= B.ndm) continue;
             const int r2 = B.row_base + d2 - row_lo;
-            int64_t lo = row_start[r2], hi = row_start[r2 + 1];
             const int tmin = h.t - rt;
-            while (lo < hi) {   // first index with t >= tmin
+            const int64_t end = row_start[r2 + 1];
+            // first index with t >= tmin: it lies between the first hits of tmin's 64-sample
+            // block and of the next block (block index), found by bisection in between
+            int64_t lo = row_start[r2], hi = end;
+            if (tmin > 0) {
+                const int b = tmin >> kNmsBlockShift;
+                const int32_t *br = blk + (int64_t)r2 * nblk;
+                hi = lo + br[b + 1];   // b + 1 < nblk: the index has a block past every t
+                lo += br[b];
+            }
+            while (lo < hi) {
                 const int64_t m = (lo + hi) >> 1;
                 if (hits[m].t < tmin) lo = m + 1; else hi = m;
             }
-            const int64_t end = row_start[r2 + 1];
             for (int64_t q = lo; q < end; ++q) {
                 const Hit g = hits[q];
                 if (g.t > h.t + rt) break;
@@ -888,11 +938,27 @@ static int grid_for(int64_t cap) {
     return (int)g;
 }
 
+hipError_t launch_nms_index(int row_lo, int n_rows, const Hit *hits, const int64_t *n_hits, int64_t cap,
+                            const int64_t *row_start, int32_t *blk, int nblk, hipStream_t s) {
+    if (n_rows <= 0) return hipSuccess;
+    if (nblk & 1) return hipErrorInvalidValue;   // filled in 8-byte words
+    hipError_t e = launch_fill_u64((uint64_t *)blk, (int64_t)n_rows * nblk / 2, 0x7FFFFFFF7FFFFFFFull, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_nms_mark, dim3(grid_for(cap)), dim3(kThreads), 0, s, row_lo, hits, n_hits, cap, row_start,
+                       blk, nblk);
+    SPL_HIP_LAUNCH_CHECK();
+    const int waves = kThreads / 64;
+    hipLaunchKernelGGL(k_nms_suffix, dim3((unsigned)((n_rows + waves - 1) / waves)), dim3(kThreads), 0, s, row_start,
+                       n_rows, blk, nblk);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
 hipError_t launch_nms(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, const Hit *hits,
-                      const int64_t *n_hits, int64_t cap, const int64_t *row_start, int stencil,
-                      const uint8_t *alive_in, uint8_t *alive_out, int64_t *n_alive, hipStream_t s) {
+                      const int64_t *n_hits, int64_t cap, const int64_t *row_start, const int32_t *blk, int nblk,
+                      int stencil, const uint8_t *alive_in, uint8_t *alive_out, int64_t *n_alive, hipStream_t s) {
     hipLaunchKernelGGL(k_nms, dim3(grid_for(cap)), dim3(kThreads), 0, s, beams, beam_lo, beam_hi, row_lo, hits,
-                       n_hits, cap, row_start, stencil, alive_in, alive_out, n_alive);
+                       n_hits, cap, row_start, blk, nblk, stencil, alive_in, alive_out, n_alive);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -10,6 +10,7 @@ constexpr int kMaxWidths = 16;
 constexpr int kMaxStencils = 4;
 constexpr int kBoxTile = 4096;        // owned samples per boxcar workgroup (multiple of 1024)
 constexpr int kThreads = 256;         // threads per workgroup of every kernel
+constexpr int kNmsBlockShift = 6;     // the peak filter indexes hit rows in blocks of 64 samples
 constexpr int kScanPerBlock = 4096;   // elements per block of the device-wide scan
 constexpr int kMaxWmax = 8192;
 constexpr int kMaxShapeGroups = 4;  // distinct dedispersion tile shapes per batch
