@@ -385,9 +385,9 @@ static Tiles default_tiles(const spl_plan &p) {
     return t;
 }
 
-// Channels per staging step: the largest power of two <= 256 whose two copies fit the
-// LDS budget (a caller-set value is rounded down to a power of two).  Then the table
-// of LDS byte offsets of every delay.
+// Channels per staging step: the largest power of two <= 256 whose four shifted copies
+// and offset table fit the LDS budget (a caller-set value is rounded down to a power of
+// two).  Then the table of LDS byte offsets of every delay.
 static void choose_chunk(PlanLayout &L, size_t lds_budget) {
     const int rmax = *std::max_element(L.row_bytes.begin(), L.row_bytes.end());
     int cc = L.tiles.cc;

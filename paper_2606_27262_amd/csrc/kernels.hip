@@ -152,8 +152,9 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
             for (int e = 0; e < kTabRegs; ++e) {
                 const int idx = tid + 64 * NW * e;
                 const int r = idx / TD;
-                // rows past cc (read by the branch-free prefetch) point at row cc
-                lds_tab[idx] = r < cc ? pt[e] + r * R : cc * R;
+                // rows past cc (read by the branch-free prefetch) point at row cc; the
+                // last register's entries beyond kTabRows rows lie outside the table
+                if (r < kTabRows) lds_tab[idx] = r < cc ? pt[e] + r * R : cc * R;
             }
             if (cc & 1) {   // an odd chunk ends with a zero row (the pair's second row)
                 for (int v = tid; v < 4 * nvec; v += 64 * NW)
