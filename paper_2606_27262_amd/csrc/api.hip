@@ -1036,9 +1036,11 @@ extern "C" spl_status spl_autotune(spl_batch *B, const uint8_t *const *d_blocks,
     }
     auto cache = read_cache(cache_path);
     constexpr int kTuneBeams = 4;
-    // 16-wavefront tiles (64 trials) share each staged channel row among twice the trials
+    // 16-wavefront tiles (64 trials) share each staged channel row among twice the trials;
+    // 16 wavefronts of 2 trials keep 4 wavefronts per SIMD where a band's wide delay
+    // spread leaves room in the LDS for one workgroup per CU only
     static const int shapes[][3] = {{2, 2, 8}, {4, 1, 4}, {4, 2, 4}, {4, 1, 8}, {4, 2, 8}, {8, 1, 4}, {8, 1, 8},
-                                    {4, 1, 16}, {4, 2, 16}};
+                                    {4, 1, 16}, {4, 2, 16}, {2, 2, 16}};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));

@@ -835,7 +835,8 @@ static hipError_t launch_dedisp_t(const DevBeam *beams, const DedispItem *items,
 // lane, wavefronts per workgroup, 16-byte vectors staged per lane and row).
 #define SPL_DEDISP_SHAPES(X) \
     X(2, 2, 8, 1) X(4, 1, 4, 1) X(4, 2, 4, 1) X(4, 1, 8, 1) X(4, 2, 8, 1) X(8, 1, 4, 1) \
-    X(8, 1, 8, 1) X(2, 2, 8, 2) X(4, 1, 4, 2) X(4, 1, 8, 2) X(4, 2, 8, 2) X(4, 1, 16, 1) X(4, 2, 16, 1)
+    X(8, 1, 8, 1) X(2, 2, 8, 2) X(4, 1, 4, 2) X(4, 1, 8, 2) X(4, 2, 8, 2) X(4, 1, 16, 1) X(4, 2, 16, 1) \
+    X(2, 2, 16, 1) X(2, 2, 16, 2)
 
 bool dedisp_shape_supported(int dw, int j, int nw, int sv) {
 #define SPL_X(a, b, c, d) if (dw == a && j == b && nw == c && sv == d) return true;

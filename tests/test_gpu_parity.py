@@ -251,17 +251,21 @@ def test_c4_mixed_beams_full_size(spl):
     assert np.array_equal(g["cands"], rc)
 
 
-@pytest.mark.parametrize("band", ["300-500", "550-750"])
+@pytest.mark.parametrize("band", ["300-500", "300-500-fine", "550-750"])
 @pytest.mark.parametrize("nch", [512, 37])
 def test_tile_shapes_give_identical_results(spl, nch, band):
     """Every compiled tile shape and staging depth the plan admits gives the oracle's
     results (37 channels: odd chunks, padded with the zero row).  The 300-500 MHz plan
     (3 pc cm^-3 steps, ~67 samples of extra delay per trial at the lowest channel)
-    admits only 16-trial tiles; the 550-750 MHz plan with the 4096-channel band's trial
-    step (~4.7 samples per trial) admits every shape, up to the 64-trial tiles the
-    autotuner picks for that band."""
+    admits only 16-trial tiles; with the 2048-channel band's sampling and trial step
+    (~44 samples per trial) 32-trial tiles stage rows of 1-2 KB (two 16-byte vectors
+    per lane); the 550-750 MHz plan with the 4096-channel band's trial step (~4.7
+    samples per trial) admits every shape, up to the 64-trial tiles the autotuner picks
+    for that band."""
     if band == "300-500":
         pd = W.make_plan(nch, 300.0, 500.0, 1.31072e-3, 3000, 0.0, 300.0, 100, W.W64)
+    elif band == "300-500-fine":
+        pd = W.make_plan(nch, 300.0, 500.0, 0.65536e-3, 3000, 0.0, 62.5, 64, W.W64)
     else:
         pd = W.make_plan(nch, 550.0, 750.0, 1.31072e-3, 3000, 0.0, 125.0, 128, W.W64)
     p = make_plan(spl, 0, 0, 0, None, 0, plan_dict=pd)
@@ -270,7 +274,7 @@ def test_tile_shapes_give_identical_results(spl, nch, band):
     ref, rc = oracle_run([p], [x])
     batch = spl.Batch([p])
     shapes = ((2, 2, 8), (2, 4, 8), (4, 1, 4), (4, 2, 4), (4, 4, 4), (4, 1, 8), (4, 2, 8), (8, 1, 4),
-              (8, 2, 4), (8, 1, 8), (16, 1, 4), (4, 1, 16), (4, 2, 16))
+              (8, 2, 4), (8, 1, 8), (16, 1, 4), (4, 1, 16), (4, 2, 16), (2, 2, 16))
     ran = set()
     for dw, j, nw in shapes:
         for cc in (0, 1, 4, 32):
@@ -284,7 +288,9 @@ def test_tile_shapes_give_identical_results(spl, nch, band):
             ran.add((dw, j, nw))
     say("shapes checked", sorted(ran))
     if band == "550-750":
-        assert {(4, 2, 8), (4, 2, 16), (4, 1, 16), (8, 1, 8)} <= ran, ran
+        assert {(4, 2, 8), (4, 2, 16), (4, 1, 16), (8, 1, 8), (2, 2, 16)} <= ran, ran
+    elif band == "300-500-fine":
+        assert {(4, 2, 8), (2, 2, 16)} <= ran, ran
     else:
         assert ran
 
