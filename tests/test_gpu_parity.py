@@ -210,22 +210,30 @@ def test_c2_full_size(spl, mode):
     assert np.array_equal(g["cands"], rc)
 
 
-def test_c4_mixed_beams_full_size(spl):
+@pytest.mark.parametrize("tiles", ["default", "tuned"])
+def test_c4_mixed_beams_full_size(spl, tiles):
     """The 32-beam workload's two plans at full size in one persistent, graph-captured
     batch: a 2048-channel 300-500 MHz beam (0.65536 ms, 32768 samples, 1024 trials to
     DM 1000, delays up to 44,946 samples) and a 4096-channel beam with 3072 trials to DM
     3000, each with ten pulses, RFI channels and zero-DM bursts.  Per beam: DM-0 row =
     channel sum, sampled DM-transform entries by direct summation, moments, and the
-    candidate list of the oracle's search on the GPU's DM transform."""
+    candidate list of the oracle's search on the GPU's DM transform.  Default tiles, and
+    the tiles the autotuner picks for these plans (16 wavefronts of 2 trials with
+    16-channel chunks; 16 wavefronts of 4 trials with 32-channel chunks)."""
     pds = [W.plan_band3_c4(), W.plan_band4_c4()]
     plans = [make_plan(spl, 0, 0, 0, None, 0, plan_dict=pd) for pd in pds]
+    batch = spl.Batch(plans, mode=1)
+    if tiles == "tuned":
+        batch.set_tiles(0, 2, 2, 16, waves=16)
+        batch.set_tiles(1, 4, 2, 32, waves=16)
+        say("tiles", batch.tiles(0), batch.tiles(1))
     blocks = []
     for b, (pd, p) in enumerate(zip(pds, plans)):
         _, x = W.c2_like_block(pd, p.info["n_in"], seed=4, beam=b, n_pulses=10,
                                dm_max_pulse=0.9 * W.dm_max(pd), zero_dm_rate=0.2)
         blocks.append(x[:, :p.info["n_in"]])
         say(f"c4 beam {b} block generated", blocks[-1].shape)
-    g = gpu_run(spl, plans, blocks, mode=1, cand_cap=1 << 20)
+    g = gpu_run(spl, plans, blocks, cand_cap=1 << 20, batch=batch)
     assert g["stats"]["hit_overflow"] == 0
     rng = np.random.default_rng(9)
     refs = []
