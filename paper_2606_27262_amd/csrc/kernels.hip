@@ -675,7 +675,9 @@ __global__ __launch_bounds__(kThreads) void k_nms_suffix(const int64_t *__restri
 // contiguous in the hit list and sorted by t; a neighbour row's window starts at the
 // first hit with t >= t_p - rt, found by bisection between the row's first hits of that
 // 64-sample block and of the next (the block index, built once per run by k_nms_mark and
-// k_nms_suffix): at most 6 dependent loads instead of one per halving of the row.
+// k_nms_suffix): at most 6 dependent loads instead of one per halving of the row.  A row
+// holds at most one hit per sample, so in p's own row the window starts no more than rt
+// entries before p and needs no search.
 __global__ __launch_bounds__(kThreads) void k_nms(const DevBeam *__restrict__ beams, int beam_lo, int beam_hi,
                                                   int row_lo, const Hit *__restrict__ hits,
                                                   const int64_t *n_hits, int64_t cap,
@@ -710,20 +712,24 @@ __global__ __launch_bounds__(kThreads) void k_nms(const DevBeam *__restrict__ be
             // first index with t >= tmin: it lies between the first hits of tmin's 64-sample
             // block and of the next block (block index), found by bisection in between
             int64_t lo = row_start[r2], hi = end;
-            if (tmin > 0) {
-                const int b = tmin >> kNmsBlockShift;
-                const int32_t *br = blk + (int64_t)r2 * nblk;
-                hi = lo + br[b + 1];   // b + 1 < nblk: the index has a block past every t
-                lo += br[b];
-            }
-            while (lo < hi) {
-                const int64_t m = (lo + hi) >> 1;
-                if (hits[m].t < tmin) lo = m + 1; else hi = m;
+            if (dd == 0) {
+                lo = max(lo, p - rt);
+            } else {
+                if (tmin > 0) {
+                    const int b = tmin >> kNmsBlockShift;
+                    const int32_t *br = blk + (int64_t)r2 * nblk;
+                    hi = lo + br[b + 1];   // b + 1 < nblk: the index has a block past every t
+                    lo += br[b];
+                }
+                while (lo < hi) {
+                    const int64_t m = (lo + hi) >> 1;
+                    if (hits[m].t < tmin) lo = m + 1; else hi = m;
+                }
             }
             for (int64_t q = lo; q < end; ++q) {
                 const Hit g = hits[q];
                 if (g.t > h.t + rt) break;
-                if (q == p || (alive_in && !alive_in[q])) continue;
+                if (g.t < tmin || q == p || (alive_in && !alive_in[q])) continue;
                 const bool beats = g.snr != h.snr ? g.snr > h.snr : (d2 != d ? d2 < d : g.t < h.t);
                 if (beats) {
                     keep = false;
