@@ -709,12 +709,13 @@ __global__ __launch_bounds__(kThreads) void k_nms(const DevBeam *__restrict__ be
             const int r2 = B.row_base + d2 - row_lo;
             const int tmin = h.t - rt;
             const int64_t end = row_start[r2 + 1];
-            // first index with t >= tmin: it lies between the first hits of tmin's 64-sample
-            // block and of the next block (block index), found by bisection in between
+            // where the window [tmin, t_p + rt] starts in row r2
             int64_t lo = row_start[r2], hi = end;
             if (dd == 0) {
-                lo = max(lo, p - rt);
+                lo = max(lo, p - rt);   // own row: no earlier entry can have t >= tmin
             } else {
+                // the first index with t >= tmin lies between the first hits of tmin's
+                // 64-sample block and of the next block (block index): bisect in between
                 if (tmin > 0) {
                     const int b = tmin >> kNmsBlockShift;
                     const int32_t *br = blk + (int64_t)r2 * nblk;
