@@ -57,3 +57,28 @@ def test_undefined_name_checker_catches_a_deleted_helper():
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, BENCH, "--gpus", "2"], capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_traffic_only_for_the_counted_source_and_tiles(monkeypatch):
+    """`roofline.traffic` comes from the committed counter summary only while the
+    dedispersion sources hash to the recorded value and every beam runs the recorded
+    tile shape; otherwise it is null."""
+    import re
+    sys.path.insert(0, ROOT)
+    import bench
+    text = open(os.path.join(ROOT, "profiles", "dedisp_c3_hbm_counters.md")).read()
+    m = re.search(r"^counters: workload=c3 kernel=k_dedisp tiles=(\d+),(\d+),(\d+),(\d+) grid=\d+ "
+                  r"fetch_bytes=(\d+) write_bytes=(\d+) dedisp_src_sha256=([0-9a-f]{64})$", text, re.M)
+    assert m, "the summary carries one machine-readable counters line"
+    dw, j, nw, cc = (int(m.group(i)) for i in range(1, 5))
+    tiles = [{"dm_per_wave": dw, "time_groups": j, "waves": nw, "chan_chunk": cc}] * 2
+    want = {"fetch_bytes": int(m.group(5)), "write_bytes": int(m.group(6))}
+    monkeypatch.setattr(bench, "dedisp_source_hash", lambda: m.group(7))
+    assert bench.counter_traffic("c3", tiles) == want
+    assert bench.counter_traffic("c3", tiles[:1] + [dict(tiles[0], chan_chunk=cc // 2)]) is None
+    assert bench.counter_traffic("c4", tiles) is None          # no summary for that workload
+    monkeypatch.setattr(bench, "dedisp_source_hash", lambda: "0" * 64)
+    assert bench.counter_traffic("c3", tiles) is None
+    # the counted bytes are at least the launch's algorithmic bytes (blocks read once,
+    # DM transforms written once)
+    assert want["fetch_bytes"] >= 24 * 4096 * 26305 and want["write_bytes"] >= 24 * 2048 * 16639 * 4
