@@ -394,7 +394,7 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const DevBeam *__restrict__
                                                      int beam_hi, int chunk_lo, int32_t *counts,
                                                      const int64_t *offsets, Hit *hits, int64_t cap) {
     extern __shared__ __align__(16) uint32_t S[];
-    __shared__ uint32_t sh32[kThreads / 64];
+    __shared__ uint32_t sh32[2][kThreads / 64];
     __shared__ int64_t sh64[kThreads / 64];
     constexpr int kQ = kBoxTile / 1024;   // quarters of 1024 samples
     const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
@@ -408,38 +408,56 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const DevBeam *__restrict__
     const int nvalid = min(M, B.n_dd - t0);
     const int32_t *Xr = B.X + (size_t)d * B.xpitch + t0;
 
-    // prefix sums in stripes of 1024 (4 consecutive per thread)
+    // prefix sums in stripes of 1024 (4 consecutive per thread).  The global loads of up
+    // to kPre stripes are issued together; the wave totals of consecutive stripes
+    // alternate between two slots, so one barrier per stripe suffices (a slot is written
+    // again two stripes later, after every thread has passed the barrier in between).
+    constexpr int kPre = 5;
+    constexpr int kStripe = 4 * kThreads;
     if (tid == 0) S[0] = 0u;
     uint32_t carry = 0;
-    for (int base = 0; base < M; base += 4 * kThreads) {
-        const int i0 = base + 4 * tid;
-        uint32_t v[4];
-        if (i0 + 3 < nvalid) {
-            const int4 q4 = *(const int4 *)(Xr + i0);
-            v[0] = (uint32_t)q4.x; v[1] = (uint32_t)q4.y; v[2] = (uint32_t)q4.z; v[3] = (uint32_t)q4.w;
-        } else {
+    int stripe = 0;
+    for (int s0 = 0; s0 < M; s0 += kPre * kStripe) {
+        uint32_t v[kPre][4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = i0 + k < nvalid ? (uint32_t)Xr[i0 + k] : 0u;
+        for (int k = 0; k < kPre; ++k) {
+            // one unconditional 16-byte load per thread and stripe (no branch, so the
+            // loads of all stripes are in flight together).  Rows are padded to a
+            // multiple of 64 entries and t0 is a multiple of 4, so a read starting at
+            // i0 < nvalid stays inside the row; past nvalid the row's first vector is
+            // read and the values are replaced by zeros.
+            const int i0 = s0 + k * kStripe + 4 * tid;
+            const u32x4 q4 = *(gu32x4 *)(Xr + (i0 < nvalid ? i0 : 0));
+            v[k][0] = i0 < nvalid ? q4.x : 0u;
+            v[k][1] = i0 + 1 < nvalid ? q4.y : 0u;
+            v[k][2] = i0 + 2 < nvalid ? q4.z : 0u;
+            v[k][3] = i0 + 3 < nvalid ? q4.w : 0u;
         }
-        v[1] += v[0];
-        v[2] += v[1];
-        v[3] += v[2];
-        const uint32_t x = wave_inclusive_scan(v[3]);
-        if (lane == 63) sh32[wave] = x;
-        __syncthreads();
-        uint32_t pre = carry, tot = 0;
 #pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) {
-            if (w < wave) pre += sh32[w];
-            tot += sh32[w];
+        for (int k = 0; k < kPre; ++k, ++stripe) {
+            const int i0 = s0 + k * kStripe + 4 * tid;
+            if (s0 + k * kStripe >= M) break;   // uniform
+            v[k][1] += v[k][0];
+            v[k][2] += v[k][1];
+            v[k][3] += v[k][2];
+            const uint32_t x = wave_inclusive_scan(v[k][3]);
+            uint32_t *tw = sh32[stripe & 1];
+            if (lane == 63) tw[wave] = x;
+            __syncthreads();
+            uint32_t pre = carry, tot = 0;
+#pragma unroll
+            for (int w = 0; w < kThreads / 64; ++w) {
+                if (w < wave) pre += tw[w];
+                tot += tw[w];
+            }
+            pre += x - v[k][3];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (i0 + e < M) S[i0 + e + 1] = pre + v[k][e];
+            carry += tot;
         }
-        pre += x - v[3];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (i0 + k < M) S[i0 + k + 1] = pre + v[k];
-        carry += tot;
-        __syncthreads();
     }
+    __syncthreads();   // every prefix entry is written
 
     const int nw = B.nw, L = B.L, nseg = B.nseg;
     const int tend = min(t0 + kBoxTile, B.n_out);   // owned samples of this chunk: [t0, tend)
