@@ -721,7 +721,11 @@ __global__ __launch_bounds__(kThreads) void k_nms(const DevBeam *__restrict__ be
         const int rd = B.rd[stencil], rt = B.rt[stencil];
         const int d = h.row - B.row_base;
         bool keep = true;
-        for (int dd = -rd; dd <= rd && keep; ++dd) {
+        // rows in the order 0, -1, +1, -2, +2, ...: the own row needs no search and the
+        // nearest rows most often hold a hit that beats p (the outcome does not depend
+        // on the order, only how early the loop stops)
+        for (int i = 0; i <= 2 * rd && keep; ++i) {
+            const int dd = (i & 1) ? -((i + 1) >> 1) : (i >> 1);
             const int d2 = d + dd;
             if (d2 < 0 || d2 >= B.ndm) continue;
             const int r2 = B.row_base + d2 - row_lo;
