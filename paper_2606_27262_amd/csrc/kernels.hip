@@ -704,6 +704,15 @@ __global__ __launch_bounds__(kThreads) void k_nms(const DevBeam *__restrict__ be
                                                   const uint8_t *alive_in, uint8_t *alive_out,
                                                   int64_t *n_alive) {
     __shared__ int64_t sh[kThreads / 64];
+    // first rows of the beams, for the bisection from a hit's row to its beam in the LDS
+    // (when the batch has more beams than fit, the bisection reads the descriptors)
+    constexpr int kBeamCache = 256;
+    __shared__ int32_t s_rb[kBeamCache];
+    const int nbm = beam_hi - beam_lo;
+    const bool cached = nbm <= kBeamCache;
+    if (cached)
+        for (int b = threadIdx.x; b < nbm; b += kThreads) s_rb[b] = beams[beam_lo + b].row_base;
+    __syncthreads();
     const int64_t n = min(*n_hits, cap);
     int64_t kept = 0;
     for (int64_t p = blockIdx.x * (int64_t)kThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kThreads) {
@@ -712,7 +721,18 @@ __global__ __launch_bounds__(kThreads) void k_nms(const DevBeam *__restrict__ be
             continue;
         }
         const Hit h = hits[p];
-        const DevBeam &B = beams[beam_of_row(beams, beam_lo, beam_hi, h.row)];
+        int bi;
+        if (cached) {   // largest b with row_base <= row
+            int a = 0, z = nbm - 1;
+            while (a < z) {
+                const int m = (a + z + 1) >> 1;
+                if (s_rb[m] <= h.row) a = m; else z = m - 1;
+            }
+            bi = beam_lo + a;
+        } else {
+            bi = beam_of_row(beams, beam_lo, beam_hi, h.row);
+        }
+        const DevBeam &B = beams[bi];
         if (stencil >= B.nst) {   // this beam's plan has fewer filters: pass through
             alive_out[p] = 1;
             ++kept;
