@@ -193,3 +193,67 @@ def flops_forward_per_sample() -> int:
         tot += 2 * 9 * CONV_CHANNELS[k] * CONV_CHANNELS[k + 1] * h * w
         h, w = h // 2, w // 2
     return tot + 2 * FC_IN * FC_HIDDEN + 2 * FC_HIDDEN
+
+
+# --------------------------------------------------------------------------
+# How far an evaluation with BF16 operands may lie from this float64 network
+# --------------------------------------------------------------------------
+BF16_SIGNIFICAND_BITS = 8      # bfloat16: 7 stored bits + the implicit one
+FP32_UNIT_ROUNDOFF = 2.0 ** -24
+
+
+def round_bf16(a):
+    """float64 values rounded to the nearest bfloat16 (ties to even), as float64."""
+    a = np.asarray(a, np.float64)
+    m, e = np.frexp(a)                              # a = m 2^e, 0.5 <= |m| < 1
+    scale = np.ldexp(1.0, BF16_SIGNIFICAND_BITS - e)
+    with np.errstate(invalid="ignore", over="ignore"):
+        r = np.rint(a * scale) / scale              # rint: ties to even
+    return np.where(a == 0.0, 0.0, r)
+
+
+def half_ulp_bf16(a):
+    """Half the spacing of bfloat16 numbers at |a|: the largest error of rounding a to
+    the nearest bfloat16 (0 at 0)."""
+    a = np.asarray(a, np.float64)
+    _, e = np.frexp(a)                              # 2^(e-1) <= |a| < 2^e
+    return np.where(a == 0.0, 0.0, np.ldexp(1.0, e - 1 - BF16_SIGNIFICAND_BITS))
+
+
+def deviation_model(p: dict, cache: dict, weight_rounding: bool = True) -> dict:
+    """Variance of the difference between this network's pre-activations and those of an
+    evaluation that rounds every convolution and FC1 weight to bfloat16, rounds every
+    pooled activation to bfloat16 and accumulates in float32 (the ranker ABI's stated
+    arithmetic), given this network's forward cache.
+
+    Model: each rounding error is independent, with variance (the rounding error of that
+    weight)^2 for the weights (known exactly) and h^2/3 (uniform within half an ulp h of
+    the oracle's value) for the pooled activations; errors propagate linearly through each
+    layer (Var dz = sum w^2 Var da + sum a^2 dw^2); max pooling passes on the largest
+    variance of its window; float32 accumulation adds at most K 2^-24 sum |a w| for K
+    products, counted as a variance term of that size squared.  Returns the variances
+    "z1".."z4" (conv pre-activations [N][32][H][W]), "h" (FC1 pre-activations [N][64])
+    and "logit" [N]."""
+    out = {}
+    Va = np.zeros_like(cache["x0"])
+    zero_b = np.zeros(CONV_CHANNELS[1])
+    for k in range(1, 5):
+        w = p[f"c{k}w"]
+        dw = (round_bf16(w) - w) if weight_rounding else np.zeros_like(w)
+        xin = cache[f"x{k - 1}"]
+        K = 9 * w.shape[1]
+        acc = K * FP32_UNIT_ROUNDOFF * conv3x3(np.abs(xin), np.abs(w), zero_b)
+        Vz = conv3x3(Va, w * w, zero_b) + conv3x3(xin * xin, dw * dw, zero_b) + acc * acc
+        out[f"z{k}"] = Vz
+        n, c, hgt, wid = Vz.shape
+        win = Vz.reshape(n, c, hgt // 2, 2, wid // 2, 2).max(axis=(3, 5))
+        Va = win + half_ulp_bf16(cache[f"x{k}"]) ** 2 / 3.0
+    f = cache["f"]
+    Vf = Va.reshape(Va.shape[0], -1)
+    w1 = p["f1w"]
+    dw1 = (round_bf16(w1) - w1) if weight_rounding else np.zeros_like(w1)
+    acc = FC_IN * FP32_UNIT_ROUNDOFF * (np.abs(f) @ np.abs(w1).T)
+    Vh = Vf @ (w1 * w1).T + (f * f) @ (dw1 * dw1).T + acc * acc
+    out["h"] = Vh
+    out["logit"] = Vh @ (p["f2w"][0] ** 2)
+    return out

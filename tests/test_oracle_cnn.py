@@ -121,3 +121,71 @@ def test_given_fc_gate_closes_a_unit():
     assert np.isclose(l0[0] - l1[0], c0["h"][0, j] * p["f2w"][0, j], rtol=1e-12, atol=1e-12)
     _, g1 = cnn.backward(p, c1, y)
     assert g1["f1b"][j] == 0.0 and np.all(g1["f1w"][j] == 0.0)
+
+
+def _bf16_emulation(p, x):
+    """The network as the ranker ABI states its arithmetic, emulated in numpy: weights of
+    the convolutions and FC1 rounded to bfloat16, products summed in float32, pooled
+    activations rounded to bfloat16.  An implementation independent of the deviation
+    model, to pin that model against."""
+    wb = {k: cnn.round_bf16(v).astype(np.float32) for k, v in p.items()}
+    a = x.astype(np.float32)
+    zs = []
+    for k in range(1, 5):
+        w, b = wb[f"c{k}w"], p[f"c{k}b"].astype(np.float32)
+        n, c, h, wd = a.shape
+        ap = np.pad(a, ((0, 0), (0, 0), (1, 1), (1, 1)))
+        z = np.zeros((n, w.shape[0], h, wd), np.float32)
+        for ky in range(3):
+            for kx in range(3):
+                z += np.einsum("nchw,oc->nohw", ap[:, :, ky:ky + h, kx:kx + wd], w[:, :, ky, kx]).astype(np.float32)
+        z += b[None, :, None, None]
+        zs.append(z.astype(np.float64))
+        r = np.maximum(z, np.float32(0))
+        pooled = r.reshape(n, w.shape[0], h // 2, 2, wd // 2, 2).max(axis=(3, 5))
+        a = cnn.round_bf16(pooled).astype(np.float32)
+    f = a.reshape(a.shape[0], -1)
+    h = (f @ wb["f1w"].T).astype(np.float64)
+    return zs, h
+
+
+def test_bf16_deviation_model_covers_an_emulation():
+    """Pin of the deviation model the GPU ranker's parity bounds come from: the
+    pre-activations of an independent float32/bfloat16 emulation of the stated arithmetic
+    lie within 6 model standard deviations of the float64 network's at every element of
+    every layer, the model is not loose (root-mean-square deviation between 0.2 and 1.5
+    standard deviations per layer), and dropping its weight-rounding term fails the first
+    layer (whose input is exact)."""
+    rng = np.random.default_rng(12)
+    p = cnn.init_params(5)
+    for k in p:
+        if k.endswith("b"):
+            p[k] = rng.normal(0, 0.05, p[k].shape)
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    x = cnn.round_bf16(rng.normal(0, 1, size=(3, 2, 64, 256)))
+    _, cache = cnn.forward(p, x)
+    V = cnn.deviation_model(p, cache)
+    zs, h = _bf16_emulation(p, x)
+    for k in range(1, 5):
+        d = (zs[k - 1] - cache[f"z{k}"]) / np.sqrt(V[f"z{k}"])
+        rms = float(np.sqrt(np.mean(d * d)))
+        assert np.max(np.abs(d)) <= 6.0, (k, np.max(np.abs(d)))
+        assert 0.2 <= rms <= 1.5, (k, rms)
+    dh = (h - (cache["h"] - p["f1b"])) / np.sqrt(V["h"])
+    assert np.max(np.abs(dh)) <= 6.0 and 0.2 <= float(np.sqrt(np.mean(dh * dh))) <= 1.5
+    V0 = cnn.deviation_model(p, cache, weight_rounding=False)
+    d1 = (zs[0] - cache["z1"]) / np.sqrt(V0["z1"] + 1e-300)
+    assert np.max(np.abs(d1)) > 6.0
+
+
+def test_round_bf16_matches_bit_rounding():
+    """round_bf16 equals the snippets' float32 -> bfloat16 bit rounding (ties to even)."""
+    import oracle
+    rng = np.random.default_rng(3)
+    v = np.concatenate([rng.normal(0, 1, 5000), rng.normal(0, 1e-3, 1000), [0.0, 1.0, -1.0]]).astype(np.float32)
+    ties = np.array([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -8)], np.float32)
+    v = np.concatenate([v, ties])
+    want = oracle.bf16_bits_to_f32(oracle.f32_to_bf16_bits(v)).astype(np.float64)
+    assert np.array_equal(cnn.round_bf16(v.astype(np.float64)), want)
+    h = cnn.half_ulp_bf16(v.astype(np.float64))
+    assert np.all(np.abs(want - v) <= h)
