@@ -129,9 +129,11 @@ def cpu_baseline(pd, plan, W, target_s=12.0):
     import numpy as np
 
     import oracle
-    D = plan.delays().astype(np.int64)
-    dms = plan.dms()
-    i = plan.info
+    # the oracle's own DM trials and delay table, from the plan's parameters
+    dms = oracle.dm_trials(pd["dm_ranges"])
+    D, _ = oracle.delay_table(pd["nchans"], pd["fch1"], pd["foff"], pd["tsamp"], dms)
+    i = dict(oracle.sizes(D, pd["n_out"], pd["widths"]), ndm=int(dms.size), nchans=int(pd["nchans"]),
+             n_out=int(pd["n_out"]), norm_window=int(pd.get("norm_window") or pd["n_out"]))
     _, x = W.c2_like_block(pd, i["n_in"], 99, 0, 4) if i["nchans"] > 256 else W.c1_block(i["n_in"], seed=99)
     x = np.ascontiguousarray(x[:, :i["n_in"]])
     last = {}

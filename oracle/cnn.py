@@ -257,3 +257,34 @@ def deviation_model(p: dict, cache: dict, weight_rounding: bool = True) -> dict:
     out["h"] = Vh
     out["logit"] = Vh @ (p["f2w"][0] ** 2)
     return out
+
+
+def forward_bf16(p: dict, x: np.ndarray):
+    """The network evaluated with the ranker ABI's stated arithmetic, in numpy float32:
+    convolution and FC1 weights rounded to bfloat16, products summed in float32, biases
+    added in float32, pooled activations rounded to bfloat16, FC2 in float32.  Returns
+    the logits [N] (float64), the conv pre-activations z1..z4 and the FC1
+    pre-activations h (float64 copies of the float32 values).  Written independently of
+    deviation_model, which is pinned against it."""
+    wb = {k: round_bf16(v).astype(np.float32) for k, v in p.items()}
+    a = np.asarray(x).astype(np.float32)
+    zs = []
+    for k in range(1, 5):
+        w, b = wb[f"c{k}w"], np.asarray(p[f"c{k}b"]).astype(np.float32)
+        n, c, h, wd = a.shape
+        ap = np.pad(a, ((0, 0), (0, 0), (1, 1), (1, 1)))
+        z = np.zeros((n, w.shape[0], h, wd), np.float32)
+        for ky in range(3):
+            for kx in range(3):
+                z += np.einsum("nchw,oc->nohw", ap[:, :, ky:ky + h, kx:kx + wd], w[:, :, ky, kx]).astype(np.float32)
+        z += b[None, :, None, None]
+        zs.append(z.astype(np.float64))
+        r = np.maximum(z, np.float32(0))
+        pooled = r.reshape(n, w.shape[0], h // 2, 2, wd // 2, 2).max(axis=(3, 5))
+        a = round_bf16(pooled).astype(np.float32)
+    f = a.reshape(a.shape[0], -1)
+    h = (f @ wb["f1w"].T).astype(np.float32) + np.asarray(p["f1b"]).astype(np.float32)
+    hr = np.maximum(h, np.float32(0))
+    logit = (hr @ np.asarray(p["f2w"]).astype(np.float32).T)[:, 0] + np.float32(np.asarray(p["f2b"])[0])
+    return logit.astype(np.float64), zs, h.astype(np.float64)
+

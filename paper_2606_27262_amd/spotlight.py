@@ -217,6 +217,14 @@ class Plan:
                                                     ctypes.byref(h)))
         self._h = h
         self.tsamp = float(tsamp)
+        # the caller's own arguments, kept so that a checker can rebuild the plan's tables
+        # independently of the library
+        self.args = {"nchans": int(nchans), "fch1": float(fch1), "foff": float(foff), "tsamp": float(tsamp),
+                     "n_out": int(n_out), "dm_ranges": None if dm_ranges is None else [tuple(r) for r in dm_ranges],
+                     "widths": tuple(int(v) for v in widths), "threshold": float(threshold),
+                     "norm_window": int(norm_window), "stencils": tuple(tuple(s) for s in stencils),
+                     "delays": None if delays is None else np.array(delays, np.int64),
+                     "dms": None if dms is None else np.array(dms, np.float64)}
         self.info = self.query()
 
     @classmethod
@@ -239,10 +247,13 @@ class Plan:
         _check(_lib.spl_plan_dms(self._h, out.ctypes.data))
         return out
 
-    def __del__(self):
-        if getattr(self, "_h", None):
-            _lib.spl_plan_destroy(self._h)
+    def __del__(self, _destroy=_lib.spl_plan_destroy):
+        # the destroy function is bound when the class is made: at interpreter exit the
+        # module's globals may already be gone when the last handle is collected
+        h = getattr(self, "_h", None)
+        if h:
             self._h = None
+            _destroy(h)
 
 
 class Batch:
@@ -365,10 +376,13 @@ class Batch:
         s2 = self._view(b.value, n * 8, torch.int64).view(info["ndm"], info["n_segments"])
         return s1, s2
 
-    def __del__(self):
-        if getattr(self, "_h", None):
-            _lib.spl_batch_destroy(self._h)
+    def __del__(self, _destroy=_lib.spl_batch_destroy):
+        # the destroy function is bound when the class is made: at interpreter exit the
+        # module's globals may already be gone when the last handle is collected
+        h = getattr(self, "_h", None)
+        if h:
             self._h = None
+            _destroy(h)
 
 
 def new_candidates(capacity, device="cuda"):
@@ -590,10 +604,13 @@ class Ranker:
         assert 0 <= off and off + nb * 64 * 4 <= self.ws.numel()
         return self.ws[off:off + nb * 64 * 4].view(torch.float32).view(nb, 64)
 
-    def __del__(self):
-        if getattr(self, "_h", None):
-            _lib.spl_ranker_destroy(self._h)
+    def __del__(self, _destroy=_lib.spl_ranker_destroy):
+        # the destroy function is bound when the class is made: at interpreter exit the
+        # module's globals may already be gone when the last handle is collected
+        h = getattr(self, "_h", None)
+        if h:
             self._h = None
+            _destroy(h)
 
 
 def debug_gemm_bf16(a, b, stream=None):

@@ -12,6 +12,7 @@ import pytest
 import oracle
 from paper_2606_27262_amd import synth
 from paper_2606_27262_amd import workloads as W
+from plan_tables import assert_library_tables, oracle_plan
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -31,6 +32,8 @@ def say(*a):
 
 
 def gpu_run(spl, plans, blocks, mode=0, hit_capacity=0, cand_cap=1 << 16, batch=None):
+    for p in {id(p): p for p in plans}.values():
+        assert_library_tables(p)
     if batch is None:
         batch = spl.Batch(plans, mode=mode, hit_capacity=hit_capacity)
     tb = [spl.upload_block(x) for x in blocks]
@@ -47,17 +50,19 @@ def gpu_run(spl, plans, blocks, mode=0, hit_capacity=0, cand_cap=1 << 16, batch=
     return out
 
 
-def oracle_run(plans, blocks, stencils=((1, 1), (5, 5))):
-    res = []
-    for b, (p, x) in enumerate(zip(plans, blocks)):
-        i = p.info
-        D = p.delays().astype(np.int64)
-        widths = p.widths_
-        r = oracle.search_beam(x[:, :i["n_in"]], D, p.dms(), i["n_out"], i["norm_window"], widths,
-                               i["threshold"], stencils=p.stencils_, beam=b)
-        n, s1, s2 = oracle.moments(r["X"], i["n_out"], i["norm_window"])
-        r["S1"], r["S2"] = s1, s2
-        res.append(r)
+def oracle_search(p, x, beam=0):
+    """The oracle's whole search of one beam on its own view of the plan (delay table,
+    DM values and sizes rebuilt from the plan's arguments), with its moments."""
+    o = oracle_plan(p)
+    r = oracle.search_beam(x[:, :o["n_in"]], o["D"], o["dms"], o["n_out"], o["L"], o["widths"], o["threshold"],
+                           stencils=o["stencils"], beam=beam)
+    n, s1, s2 = oracle.moments(r["X"], o["n_out"], o["L"])
+    r["S1"], r["S2"] = s1, s2
+    return r
+
+
+def oracle_run(plans, blocks):
+    res = [oracle_search(p, x, b) for b, (p, x) in enumerate(zip(plans, blocks))]
     cands = np.concatenate([r["cands"] for r in res]) if res else np.zeros(0, oracle.CAND_DTYPE)
     return res, cands
 
@@ -65,14 +70,9 @@ def oracle_run(plans, blocks, stencils=((1, 1), (5, 5))):
 def make_plan(spl, nch, ndm, n_out, widths, theta, L=0, delays=None, dms=None, stencils=((1, 1), (5, 5)),
               plan_dict=None):
     if plan_dict is not None:
-        p = spl.Plan.from_dict(plan_dict, stencils=stencils)
-        p.widths_ = tuple(plan_dict["widths"])
-    else:
-        p = spl.Plan(nch, 500.0, -0.5, 1e-3, n_out, widths=widths, threshold=theta, norm_window=L,
-                     delays=delays, dms=dms, stencils=stencils)
-        p.widths_ = tuple(widths)
-    p.stencils_ = tuple(stencils)
-    return p
+        return spl.Plan.from_dict(plan_dict, stencils=stencils)
+    return spl.Plan(nch, 500.0, -0.5, 1e-3, n_out, widths=widths, threshold=theta, norm_window=L,
+                    delays=delays, dms=dms, stencils=stencils)
 
 
 def compare(g, ref_beams, ref_cands, check_X=True):
@@ -179,35 +179,20 @@ def test_smearing_plan_batch(spl, mode):
 
 @pytest.mark.parametrize("mode", [0, 1])
 def test_c2_full_size(spl, mode):
-    """4096 channels, 2048 trials, 16384 samples, 20 pulses, 2% RFI: DM-0 row = channel
-    sum, sampled DM-transform entries by direct summation, moments, and the candidate
-    list of the oracle's search run on the GPU's DM transform."""
+    """4096 channels, 2048 trials, 16384 samples, 20 pulses, 2% RFI, plain and graph
+    modes: the whole DM transform, the moments and the candidate list equal the oracle's
+    own search of the block, bit for bit."""
     pd = W.plan_c2()
     p = make_plan(spl, 0, 0, 0, None, 0, plan_dict=pd)
     i = p.info
     _, x = W.c2_like_block(pd, i["n_in"], seed=2, beam=0, n_pulses=20)
     x = x[:, :i["n_in"]]
     say("c2 block generated", x.shape)
-    g = gpu_run(spl, [p], [x], mode=mode)
-    X = g["X"][0]
-    assert np.array_equal(X[0], x[:, :i["n_dd"]].astype(np.int64).sum(0))
-    D = p.delays().astype(np.int64)
-    rng = np.random.default_rng(5)
-    ds = rng.integers(0, i["ndm"], 3000)
-    ts = rng.integers(0, i["n_dd"], 3000)
-    ds[:8] = i["ndm"] - 1
-    ts[:8] = i["n_dd"] - 1 - np.arange(8)
-    ch = np.arange(i["nchans"])
-    for d, t in zip(ds, ts):
-        assert X[d, t] == int(x[ch, t + D[d]].astype(np.int64).sum())
-    n, s1, s2 = oracle.moments(X, i["n_out"], i["norm_window"])
-    assert np.array_equal(g["S1"][0], s1) and np.array_equal(g["S2"][0], s2)
-    hits = oracle.search(X, i["n_out"], i["norm_window"], pd["widths"], pd["threshold"])
-    alive = oracle.nms(hits, i["ndm"], i["n_out"])
-    rc = oracle.candidates(0, hits, alive, p.dms())
-    say("c2 hits", hits["d"].size, "candidates", rc.size)
-    assert g["stats"]["n_hits"] == hits["d"].size
-    assert np.array_equal(g["cands"], rc)
+    g = gpu_run(spl, [p], [x], mode=mode, cand_cap=1 << 18)
+    ref, rc = oracle_run([p], [x])
+    say("c2 hits", ref[0]["hits"]["d"].size, "candidates", rc.size)
+    assert np.array_equal(g["X"][0][0], x[:, :i["n_dd"]].astype(np.int64).sum(0))
+    compare(g, ref, rc)
 
 
 @pytest.mark.parametrize("tiles", ["default", "tuned"])
@@ -215,11 +200,11 @@ def test_c4_mixed_beams_full_size(spl, tiles):
     """The 32-beam workload's two plans at full size in one persistent, graph-captured
     batch: a 2048-channel 300-500 MHz beam (0.65536 ms, 32768 samples, 1024 trials to
     DM 1000, delays up to 44,946 samples) and a 4096-channel beam with 3072 trials to DM
-    3000, each with ten pulses, RFI channels and zero-DM bursts.  Per beam: DM-0 row =
-    channel sum, sampled DM-transform entries by direct summation, moments, and the
-    candidate list of the oracle's search on the GPU's DM transform.  Default tiles, and
-    the tiles the autotuner picks for these plans (16 wavefronts of 2 trials with
-    16-channel chunks; 16 wavefronts of 4 trials with 32-channel chunks)."""
+    3000, each with ten pulses, RFI channels and zero-DM bursts.  Per beam the whole DM
+    transform, the moments and the candidate list equal the oracle's own search, bit for
+    bit.  Default tiles, and the tiles the autotuner picks for these plans (16 wavefronts
+    of 2 trials with 16-channel chunks; 16 wavefronts of 4 trials with 32-channel
+    chunks)."""
     pds = [W.plan_band3_c4(), W.plan_band4_c4()]
     plans = [make_plan(spl, 0, 0, 0, None, 0, plan_dict=pd) for pd in pds]
     batch = spl.Batch(plans, mode=1)
@@ -234,29 +219,76 @@ def test_c4_mixed_beams_full_size(spl, tiles):
         blocks.append(x[:, :p.info["n_in"]])
         say(f"c4 beam {b} block generated", blocks[-1].shape)
     g = gpu_run(spl, plans, blocks, cand_cap=1 << 20, batch=batch)
-    assert g["stats"]["hit_overflow"] == 0
-    rng = np.random.default_rng(9)
-    refs = []
-    for b, (pd, p, x) in enumerate(zip(pds, plans, blocks)):
-        i = p.info
-        X = g["X"][b]
-        assert np.array_equal(X[0], x[:, :i["n_dd"]].astype(np.int64).sum(0))
-        D = p.delays().astype(np.int64)
-        ds = rng.integers(0, i["ndm"], 1500)
-        ts = rng.integers(0, i["n_dd"], 1500)
-        ds[:8] = i["ndm"] - 1
-        ts[:8] = i["n_dd"] - 1 - np.arange(8)
-        ch = np.arange(i["nchans"])
-        for d, t in zip(ds, ts):
-            assert X[d, t] == int(x[ch, t + D[d]].astype(np.int64).sum()), (b, d, t)
-        n, s1, s2 = oracle.moments(X, i["n_out"], i["norm_window"])
-        assert np.array_equal(g["S1"][b], s1) and np.array_equal(g["S2"][b], s2)
-        hits = oracle.search(X, i["n_out"], i["norm_window"], pd["widths"], pd["threshold"])
-        alive = oracle.nms(hits, i["ndm"], i["n_out"])
-        refs.append(oracle.candidates(b, hits, alive, p.dms()))
-        say(f"c4 beam {b}: hits {hits['d'].size}, candidates {refs[-1].size}")
-    rc = np.concatenate(refs)
-    assert np.array_equal(g["cands"], rc)
+    ref, rc = oracle_run(plans, blocks)
+    for b, r in enumerate(ref):
+        say(f"c4 beam {b}: hits {r['hits']['d'].size}, candidates {r['cands'].size}")
+    compare(g, ref, rc)
+
+
+C3_BEAMS = 24
+C3_GROUP = 4
+C3_TILES = (4, 2, 32, 16)    # trials per wavefront, time groups, channel chunk, wavefronts
+
+
+@pytest.fixture(scope="module")
+def c3_batch(spl):
+    """The 24-beam workload exactly as the benchmark searches it: 24 blocks of the
+    4096-channel plan (seed 3, ten pulses and 2% RFI channels per beam), one persistent
+    launch captured in a hipGraph, with the tiles the autotuner picks for this plan."""
+    pd = W.plan_c2()
+    p = make_plan(spl, 0, 0, 0, None, 0, plan_dict=pd)
+    assert_library_tables(p)
+    n_in = p.info["n_in"]
+    blocks, dev = [], []
+    for b in range(C3_BEAMS):
+        _, x = W.c2_like_block(pd, n_in, 3, b, 10)
+        blocks.append(np.ascontiguousarray(x[:, :n_in]))
+        dev.append(spl.upload_block(blocks[-1]))
+        if b % 8 == 7:
+            say(f"c3 blocks generated: {b + 1}")
+    batch = spl.Batch([p] * C3_BEAMS, mode=spl.MODE_PERSISTENT_GRAPH)
+    dw, j, cc, nw = C3_TILES
+    for b in range(C3_BEAMS):
+        batch.set_tiles(b, dw, j, cc, waves=nw)
+    cands = spl.new_candidates(1 << 20)
+    cands, stats = batch.run(dev, cands)
+    torch.cuda.synchronize()
+    st = spl.stats_dict(stats)
+    say("c3 batch searched:", st)
+    assert st["hit_overflow"] == 0 and st["cand_overflow"] == 0
+    return {"plan": p, "batch": batch, "blocks": blocks, "dev": dev, "cands_dev": cands,
+            "cands": spl.candidates_to_numpy(cands, stats), "stats": st}
+
+
+@pytest.mark.parametrize("group", range(C3_BEAMS // C3_GROUP))
+def test_c3_batch_full_size(spl, c3_batch, group):
+    """Beams 4g .. 4g+3 of the 24-beam persistent graph batch: the whole DM transform, the
+    moments and the candidate list of every beam equal the oracle's own search of its
+    block, bit for bit; then both snippet planes of a sample of each beam's candidates
+    (the first, the last, the strongest and every 64th) equal the oracle's."""
+    p, batch = c3_batch["plan"], c3_batch["batch"]
+    i = p.info
+    o = oracle_plan(p)
+    for b in range(group * C3_GROUP, (group + 1) * C3_GROUP):
+        x = c3_batch["blocks"][b]
+        r = oracle_search(p, x, beam=b)
+        X = batch.dm_transform(b)[:, :i["n_dd"]].cpu().numpy().astype(np.int64)
+        assert np.array_equal(X, r["X"]), f"X differs (beam {b})"
+        del X
+        s1, s2 = batch.moments(b)
+        assert np.array_equal(s1.cpu().numpy(), r["S1"]) and np.array_equal(s2.cpu().numpy(), r["S2"]), b
+        got = c3_batch["cands"][c3_batch["cands"]["beam"] == b]
+        say(f"c3 beam {b}: hits {r['hits']['d'].size}, candidates {got.size} / {r['cands'].size}")
+        assert np.array_equal(got, r["cands"]), f"candidates differ (beam {b})"
+        pick = sorted(set([0, got.size - 1, int(np.argmax(got["snr"]))] + list(range(0, got.size, 64))))
+        recs = np.ascontiguousarray(got[pick])
+        snip = spl.snippets(batch, torch.from_numpy(recs.view(np.int32).reshape(-1, 8).copy()).cuda())
+        torch.cuda.synchronize()
+        gs = snip.cpu().numpy().view(np.uint16)
+        for k, c in enumerate(recs):
+            want = oracle.snippets(x, o["D"], r["X"], o["n_out"], o["L"], int(c["dm_index"]), int(c["t_sample"]))
+            assert np.array_equal(gs[k], want), (b, k, c)
+        say(f"  snippets of {len(pick)} candidates bit-exact")
 
 
 @pytest.mark.parametrize("band", ["300-500", "300-500-fine", "550-750"])

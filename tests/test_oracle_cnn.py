@@ -124,29 +124,10 @@ def test_given_fc_gate_closes_a_unit():
 
 
 def _bf16_emulation(p, x):
-    """The network as the ranker ABI states its arithmetic, emulated in numpy: weights of
-    the convolutions and FC1 rounded to bfloat16, products summed in float32, pooled
-    activations rounded to bfloat16.  An implementation independent of the deviation
-    model, to pin that model against."""
-    wb = {k: cnn.round_bf16(v).astype(np.float32) for k, v in p.items()}
-    a = x.astype(np.float32)
-    zs = []
-    for k in range(1, 5):
-        w, b = wb[f"c{k}w"], p[f"c{k}b"].astype(np.float32)
-        n, c, h, wd = a.shape
-        ap = np.pad(a, ((0, 0), (0, 0), (1, 1), (1, 1)))
-        z = np.zeros((n, w.shape[0], h, wd), np.float32)
-        for ky in range(3):
-            for kx in range(3):
-                z += np.einsum("nchw,oc->nohw", ap[:, :, ky:ky + h, kx:kx + wd], w[:, :, ky, kx]).astype(np.float32)
-        z += b[None, :, None, None]
-        zs.append(z.astype(np.float64))
-        r = np.maximum(z, np.float32(0))
-        pooled = r.reshape(n, w.shape[0], h // 2, 2, wd // 2, 2).max(axis=(3, 5))
-        a = cnn.round_bf16(pooled).astype(np.float32)
-    f = a.reshape(a.shape[0], -1)
-    h = (f @ wb["f1w"].T).astype(np.float64)
-    return zs, h
+    """The float32/bfloat16 evaluation of the stated arithmetic (oracle.cnn.forward_bf16):
+    conv pre-activations z1..z4 and FC1 pre-activations without the bias."""
+    _, zs, h = cnn.forward_bf16(p, x)
+    return zs, h - np.asarray(p["f1b"]).astype(np.float32).astype(np.float64)
 
 
 def test_bf16_deviation_model_covers_an_emulation():
@@ -189,3 +170,40 @@ def test_round_bf16_matches_bit_rounding():
     assert np.array_equal(cnn.round_bf16(v.astype(np.float64)), want)
     h = cnn.half_ulp_bf16(v.astype(np.float64))
     assert np.all(np.abs(want - v) <= h)
+
+
+def test_decision_check_accepts_an_emulation_and_rejects_planted_choices():
+    """The GPU parity test's decision check (near-tie bound from the deviation model):
+    every pooling choice and hidden-layer gate of the float32/bfloat16 emulation passes it,
+    some differ from the float64 network's own (so the check is exercised), and choosing
+    the smallest element of every window, or flipping a clearly open gate, fails it."""
+    from cnn_decisions import NEAR_TIE_SIGMAS, check_pool_decisions, _windows
+    rng = np.random.default_rng(40)
+    p = cnn.init_params(40)
+    for k in p:
+        if k.endswith("b"):
+            p[k] = rng.normal(0, 0.05, p[k].shape)
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    x = cnn.round_bf16(rng.normal(0, 1, size=(2, 2, 64, 256)))
+    _, cache = cnn.forward(p, x)
+    V = cnn.deviation_model(p, cache)
+    zs, h = _bf16_emulation(p, x)
+    n_diff_total = 0
+    for k in range(1, 5):
+        zw = _windows(zs[k - 1])
+        emu = np.where(zw.max(-1) > 0, np.argmax(zw, -1), 255)
+        n_diff, n_bad = check_pool_decisions(cache[f"z{k}"], V[f"z{k}"], emu)
+        assert n_bad == 0, (k, n_bad)
+        n_diff_total += n_diff
+        _, n_bad = check_pool_decisions(cache[f"z{k}"], V[f"z{k}"], np.argmin(zw, -1))
+        assert n_bad > 0.5 * zw[..., 0].size, (k, n_bad)
+    assert n_diff_total > 0
+    hv = cache["h"]
+    gate = (h + p["f1b"]) > 0
+    ok = (gate == (hv > 0)) | (np.abs(hv) <= NEAR_TIE_SIGMAS * np.sqrt(V["h"]))
+    assert ok.all()
+    j = np.unravel_index(np.argmax(hv), hv.shape)
+    flipped = gate.copy()
+    flipped[j] = False
+    ok = (flipped == (hv > 0)) | (np.abs(hv) <= NEAR_TIE_SIGMAS * np.sqrt(V["h"]))
+    assert not ok[j]
