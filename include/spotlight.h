@@ -248,6 +248,31 @@ spl_status spl_batch_run(spl_batch *batch, const uint8_t *const *d_blocks, const
                          spl_candidate *d_cands, int64_t capacity, spl_run_stats *d_stats,
                          hipStream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): spl_batch_run with the batch's
+ * workspace replaced, for this call, by a static device array of the library
+ * (SPL_STATIC_SCRATCH_BYTES per GPU, reserved on each GPU the library runs on until
+ * the process ends).  Same arguments, results and candidate order as spl_batch_run;
+ * no spl_batch_set_workspace is needed, and the call allocates nothing on the device
+ * (no hipMalloc, no graph; the run is enqueued eagerly in every mode).
+ *   - SPL_E_UNSUPPORTED when spl_batch_workspace_size exceeds SPL_STATIC_SCRATCH_BYTES
+ *     (create the batch with a smaller hit_capacity, or fewer or smaller beams).
+ *   - The current device must be the stream's device.
+ *   - The call first waits for the work already enqueued on `stream`, then copies the
+ *     batch's plan tables into the array (synchronous host-to-device copies) and
+ *     enqueues the run.  Every call on one GPU shares that GPU's array, which keeps
+ *     the last call's contents: calls on one GPU whose runs overlap in time (other
+ *     streams, other threads) race and give undefined results.
+ *   - The batch's own workspace, descriptors and captured graph are left unchanged;
+ *     spl_batch_dm_transform and spl_batch_moments keep reading that workspace, and
+ *     spl_ranker_snippets must not be given a batch whose last run was this one.
+ */
+#define SPL_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+spl_status spl_batch_run_static(spl_batch *batch, const uint8_t *const *d_blocks, const int64_t *pitches,
+                                spl_candidate *d_cands, int64_t capacity, spl_run_stats *d_stats,
+                                hipStream_t stream);
+
 /* Read-only device views of the last run's intermediate results of one beam:
  * the DM transform int32 [ndm][pitch_elems] (valid columns 0..n_dd-1) and the
  * segment moments int64 S1[ndm][n_segments], S2[ndm][n_segments]. */

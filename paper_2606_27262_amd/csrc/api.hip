@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -669,12 +670,9 @@ static void fill_host_beams(spl_batch *B) {
     }
 }
 
-// Upload the plan tables and beam descriptors of the current layout (synchronous).
-static spl_status upload_tables(spl_batch *B) {
-    if (B->staging_pending) {
-        HIP_TRY(hipEventSynchronize(B->staging_done));
-        B->staging_pending = false;
-    }
+// Copy the plan tables, work items and beam descriptors of the current layout into the
+// workspace at B->ws (synchronous copies from host memory).
+static spl_status copy_tables(spl_batch *B) {
     for (auto &L : B->layouts) {
         HIP_TRY(hipMemcpy(B->ws + L.off_dcm, L.dtab.data(), L.dtab.size() * sizeof(int32_t),
                           hipMemcpyHostToDevice));
@@ -690,6 +688,12 @@ static spl_status upload_tables(spl_batch *B) {
                           hipMemcpyHostToDevice));
     fill_host_beams(B);
     HIP_TRY(hipMemcpy(B->ws + B->off_beams, B->host_beams.data(), sizeof(DevBeam) * B->nb, hipMemcpyHostToDevice));
+    return SPL_OK;
+}
+
+// LDS limits of the dedispersion instantiations the batch launches, and the occupancy of
+// each persistent shape group.
+static spl_status prepare_shapes(spl_batch *B) {
     for (auto &g : B->groups) {
         int occ = 0;
         HIP_TRY(prepare_dedisp(g.dw, g.j, g.nw, g.sv, g.lds, &occ));
@@ -700,6 +704,19 @@ static spl_status upload_tables(spl_batch *B) {
         int occ = 0;
         HIP_TRY(prepare_dedisp(t.dw, t.j, t.nw, t.sv, B->beam_lds[b], &occ));
     }
+    return SPL_OK;
+}
+
+// Upload the plan tables and beam descriptors of the current layout (synchronous).
+static spl_status upload_tables(spl_batch *B) {
+    if (B->staging_pending) {
+        HIP_TRY(hipEventSynchronize(B->staging_done));
+        B->staging_pending = false;
+    }
+    spl_status st = copy_tables(B);
+    if (st != SPL_OK) return st;
+    st = prepare_shapes(B);
+    if (st != SPL_OK) return st;
     if (B->graph_exec) {
         (void)hipGraphExecDestroy(B->graph_exec);
         B->graph_exec = nullptr;
@@ -855,6 +872,21 @@ static spl_status enqueue_all(spl_batch *B, spl_candidate *cands, int64_t cap, s
     return SPL_OK;
 }
 
+// Arguments of a search run: candidate buffer, statistics and every beam's block.
+static spl_status check_run_args(const spl_batch *B, const uint8_t *const *d_blocks, const int64_t *pitches,
+                                 const spl_candidate *d_cands, int64_t capacity, const spl_run_stats *d_stats) {
+    if (capacity < 0 || (capacity > 0 && !d_cands)) return fail(SPL_E_INVALID_ARG, "bad candidate buffer");
+    if (((uintptr_t)d_stats & 7) != 0) return fail(SPL_E_INVALID_ARG, "d_stats must be 8-byte aligned");
+    for (int b = 0; b < B->nb; ++b) {
+        const spl_plan &p = *B->plans[b];
+        if (!d_blocks[b]) return fail(SPL_E_INVALID_ARG, "block of beam %d is NULL", b);
+        if (((uintptr_t)d_blocks[b] & 15) != 0) return fail(SPL_E_INVALID_ARG, "block of beam %d is not 16-byte aligned", b);
+        if (pitches[b] < p.n_in || (pitches[b] & 15) != 0)
+            return fail(SPL_E_INVALID_ARG, "pitch of beam %d must be a multiple of 16 and >= n_in = %d", b, p.n_in);
+    }
+    return SPL_OK;
+}
+
 extern "C" spl_status spl_batch_run(spl_batch *B, const uint8_t *const *d_blocks, const int64_t *pitches,
                                     spl_candidate *d_cands, int64_t capacity, spl_run_stats *d_stats,
                                     hipStream_t stream) {
@@ -862,17 +894,11 @@ extern "C" spl_status spl_batch_run(spl_batch *B, const uint8_t *const *d_blocks
     static_assert(sizeof(DevRun) % 8 == 0, "run state is cleared in 8-byte words");
     if (!B || !d_blocks || !pitches || !d_stats) return fail(SPL_E_INVALID_ARG, "NULL argument");
     if (!B->tables_uploaded) return fail(SPL_E_INVALID_ARG, "spl_batch_set_workspace was not called");
-    if (capacity < 0 || (capacity > 0 && !d_cands)) return fail(SPL_E_INVALID_ARG, "bad candidate buffer");
-    if (((uintptr_t)d_stats & 7) != 0) return fail(SPL_E_INVALID_ARG, "d_stats must be 8-byte aligned");
+    spl_status vs = check_run_args(B, d_blocks, pitches, d_cands, capacity, d_stats);
+    if (vs != SPL_OK) return vs;
     bool changed = false;
-    for (int b = 0; b < B->nb; ++b) {
-        const spl_plan &p = *B->plans[b];
-        if (!d_blocks[b]) return fail(SPL_E_INVALID_ARG, "block of beam %d is NULL", b);
-        if (((uintptr_t)d_blocks[b] & 15) != 0) return fail(SPL_E_INVALID_ARG, "block of beam %d is not 16-byte aligned", b);
-        if (pitches[b] < p.n_in || (pitches[b] & 15) != 0)
-            return fail(SPL_E_INVALID_ARG, "pitch of beam %d must be a multiple of 16 and >= n_in = %d", b, p.n_in);
+    for (int b = 0; b < B->nb; ++b)
         if (d_blocks[b] != B->cur_x[b] || pitches[b] != B->cur_pitch[b]) changed = true;
-    }
     if (changed) {
         if (B->staging_pending) HIP_TRY(hipEventSynchronize(B->staging_done));
         for (int b = 0; b < B->nb; ++b) {
@@ -908,6 +934,75 @@ extern "C" spl_status spl_batch_run(spl_batch *B, const uint8_t *const *d_blocks
         return SPL_OK;
     }
     return enqueue_all(B, d_cands, capacity, d_stats, stream);
+}
+
+// ------------------------------------------------- search without allocation
+// The workspace of spl_batch_run_static: one copy of this array per GPU, at its own
+// address on each, held until the process ends.  Host code never uses the array's name
+// as an address: it takes each device's address once from hipGetSymbolAddress.
+static constexpr size_t kStaticScratchBytes = SPL_STATIC_SCRATCH_BYTES;
+static constexpr int kMaxStaticDevices = 64;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kMaxStaticDevices] = {};
+
+// Device address of the current device's copy of the scratch array, looked up on the
+// first call on that device.
+static spl_status scratch_address(char **out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxStaticDevices) return fail(SPL_E_UNSUPPORTED, "device %d: too many devices", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SPL_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPL_OK;
+}
+
+extern "C" spl_status spl_batch_run_static(spl_batch *B, const uint8_t *const *d_blocks, const int64_t *pitches,
+                                           spl_candidate *d_cands, int64_t capacity, spl_run_stats *d_stats,
+                                           hipStream_t stream) {
+    if (!B || !d_blocks || !pitches || !d_stats) return fail(SPL_E_INVALID_ARG, "NULL argument");
+    spl_status st = check_run_args(B, d_blocks, pitches, d_cands, capacity, d_stats);
+    if (st != SPL_OK) return st;
+    if (B->ws_bytes > kStaticScratchBytes)
+        return fail(SPL_E_UNSUPPORTED, "the batch needs %zu workspace bytes, the static scratch holds %zu "
+                    "(lower the hit capacity or the batch size)", B->ws_bytes, kStaticScratchBytes);
+    char *sp = nullptr;
+    st = scratch_address(&sp);
+    if (st != SPL_OK) return st;
+    // an earlier call's kernels on this stream may still read the scratch
+    HIP_TRY(hipStreamSynchronize(stream));
+    // the scratch stands in for the batch's workspace for this call; the batch's own
+    // workspace, descriptors and captured graph are left as they are
+    char *ws = B->ws;
+    const size_t ws_given = B->ws_given;
+    const bool profiling = B->profiling;
+    std::vector<const uint8_t *> cur_x;
+    std::vector<int64_t> cur_pitch;
+    cur_x.swap(B->cur_x);
+    cur_pitch.swap(B->cur_pitch);
+    B->cur_x.assign(d_blocks, d_blocks + B->nb);
+    B->cur_pitch.assign(pitches, pitches + B->nb);
+    B->ws = sp;
+    B->ws_given = kStaticScratchBytes;
+    B->profiling = false;
+    st = copy_tables(B);
+    if (st == SPL_OK) st = prepare_shapes(B);
+    if (st == SPL_OK) st = enqueue_all(B, d_cands, capacity, d_stats, stream);
+    B->ws = ws;
+    B->ws_given = ws_given;
+    B->profiling = profiling;
+    B->cur_x.swap(cur_x);
+    B->cur_pitch.swap(cur_pitch);
+    if (ws) fill_host_beams(B);
+    return st;
 }
 
 extern "C" spl_status spl_batch_dm_transform(const spl_batch *B, int32_t beam, const int32_t **d_X,

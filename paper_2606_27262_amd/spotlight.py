@@ -119,6 +119,8 @@ _sig("spl_batch_moments", [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_P)])
 _sig("spl_batch_get_tiles", [_P, _I32, ctypes.POINTER(_Tiles)])
 _sig("spl_batch_set_tiles", [_P, _I32, ctypes.POINTER(_Tiles)])
 _sig("spl_batch_destroy", [_P], None)
+_sig("spl_batch_run_static", [_P, ctypes.POINTER(_P), ctypes.POINTER(_I64), _P, _I64, _P, _P])
+STATIC_SCRATCH_BYTES = 64 << 20   # SPL_STATIC_SCRATCH_BYTES
 _sig("spl_batch_set_profiling", [_P, _I32])
 _sig("spl_autotune", [_P, ctypes.POINTER(_P), ctypes.POINTER(_I64), ctypes.c_char_p, _I32, _P])
 _sig("spl_batch_stage_times", [_P, _P, _P, _I32])
@@ -328,6 +330,21 @@ class Batch:
         else:
             _check(_lib.spl_batch_run(self._h, ptrs, pitches, cptr, cap, ctypes.c_void_p(stats.data_ptr()),
                                       _stream_handle(stream)))
+        return cands, stats
+
+    def run_static(self, blocks, cands, stats, stream=None):
+        """spl_batch_run_static: one search with the library's static device scratch as
+        the workspace (no device allocation by the library; the caller passes the
+        candidate and statistics tensors).  The batch needs no attached workspace."""
+        import torch
+        nb = len(self.plans)
+        assert len(blocks) == nb
+        for b in blocks:
+            assert b.dtype == torch.uint8 and b.is_cuda and b.dim() == 2 and b.stride(1) == 1
+        ptrs = (_P * nb)(*[b.data_ptr() for b in blocks])
+        pitches = (_I64 * nb)(*[b.stride(0) for b in blocks])
+        _check(_lib.spl_batch_run_static(self._h, ptrs, pitches, ctypes.c_void_p(cands.data_ptr()), cands.shape[0],
+                                         ctypes.c_void_p(stats.data_ptr()), _stream_handle(stream)))
         return cands, stats
 
     def autotune(self, blocks, cache_path=None, force=False, stream=None):

@@ -255,3 +255,19 @@ def test_fine_snippets_argument_checks():
     assert lib.spl_ranker_snippets_fine(None, None, 0, 1.5, None, None) == spl.SPL_E_INVALID_ARG
     assert lib.spl_ranker_snippets_fine(None, None, 0, 0.0, None, None) == spl.SPL_E_INVALID_ARG
     assert lib.spl_ranker_snippets_fine(None, None, 0, 0.1, None, None) == spl.SPL_E_INVALID_ARG   # no batch
+
+
+def test_static_entry_point_rejects_a_batch_beyond_its_scratch():
+    """spl_batch_run_static refuses, before any device work, a batch whose workspace
+    exceeds the static scratch (the 24-beam 4096-channel batch needs gigabytes)."""
+    plan = spl.Plan.from_dict(W.plan_c2())
+    batch = spl.Batch([plan] * 2)
+    assert batch.workspace_bytes() > spl.STATIC_SCRATCH_BYTES
+    nb = 2
+    fake = 1 << 40    # aligned stand-ins: the size check comes before any device access
+    ptrs = (ctypes.c_void_p * nb)(fake, fake)
+    pitches = (ctypes.c_int64 * nb)(*[(plan.info["n_in"] + 15) // 16 * 16] * nb)
+    st = spl._lib.spl_batch_run_static(batch._h, ptrs, pitches, ctypes.c_void_p(fake), 16,
+                                       ctypes.c_void_p(fake), None)
+    assert st == spl.SPL_E_UNSUPPORTED
+    assert b"static scratch" in spl._lib.spl_last_error()
