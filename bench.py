@@ -81,25 +81,64 @@ def make_workload(name, spl, W, keep_host=False):
     return pds, plans, blocks, pulses, host
 
 
-def end_to_end_leg(spl, pds, host, pulses, args, n_blocks=8, warmup=2):
-    """Sustained stream of blocks (paper_2606_27262_amd.streaming): pinned host-to-device
-    copy of the next block and the candidate stage of the previous block overlap the
-    search of the current one.  The stream repeats the workload's blocks.  ms_per_block
-    is the steady-state period on the search stream (first measured block's start to the
-    last block's searched and copied records); the host wall time, which also holds the
-    last block's unoverlapped candidate stage, is reported beside it."""
+def end_to_end_leg(spl, W, pds, args, n_blocks=8, warmup=2, seed=33):
+    """Sustained search of continuous beam streams (paper_2606_27262_amd.streaming): each
+    beam's stream repeats a synthetic series of two blocks' owned samples (2 n_out, ten
+    pulses per block, 2 % RFI channels; no pulse crosses the period end), so the stream
+    alternates between two block contents.  The first block is uploaded whole; every
+    later block receives the previous block's overlap tail on the device and only its
+    n_out new samples from pinned host memory, overlapped with the search of the current
+    block (one contiguous pinned copy per beam into a staging buffer; spl_stream_assemble
+    then writes the block from the previous block's tail and the staged samples on the
+    search stream), while the candidate stage of the previous block runs on the host.
+    ms_per_block is the steady-state period on the search stream (first measured
+    block's start to the last block's searched and copied records); the host wall time,
+    which also holds the last block's unoverlapped candidate stage, is reported beside
+    it.  Recall counts each block's own bursts; a candidate matching a burst of the
+    neighbouring blocks is not a false alarm."""
     import tempfile
 
     import numpy as np
+    import torch
 
     from paper_2606_27262_amd import ranking, streaming
     block_s = max(pd["n_out"] * pd["tsamp"] for pd in pds)
     ss = streaming.StreamingSearch(spl, pds)
     ss.attach(tile_cache=None if args.no_autotune else
               (args.tile_cache or os.path.join(tempfile.gettempdir(), "spotlight_tiles.txt")))
-    out = {"blocks": n_blocks, "warmup": warmup,
-           "h2d_bytes_per_block": int(sum(h.numel() for h in host)),
-           "h2d_GBps_alone": ss.copy_rate(host) / 1e9}
+    first, chunks, truth = [], [[], []], [[], []]
+    for b, (pd, p) in enumerate(zip(pds, ss.plans)):
+        n_in, n_out = p.info["n_in"], p.info["n_out"]
+        series, per_block = W.stream_series(pd, 0, n_in, seed, b, 10, period=2, device="cuda")
+        idx0 = torch.arange(n_in, device="cuda") % series.shape[1]
+        h = torch.zeros(tuple(ss.dev[0][b].shape), dtype=torch.uint8, pin_memory=True)
+        h[:, :n_in].copy_(series[:, idx0])
+        first.append(h)
+        for j, k in enumerate((1, 2)):
+            idx = (k * n_out + (n_in - n_out) + torch.arange(n_out, device="cuda")) % series.shape[1]
+            c = torch.empty((series.shape[0], n_out), dtype=torch.uint8, pin_memory=True)
+            c.copy_(series[:, idx])
+            chunks[j].append(c)
+        truth[0].append(per_block[0])
+        truth[1].append(per_block[1])
+        del series
+    torch.cuda.synchronize()
+
+    def shifted(ps, dt):
+        return [type(p)(t0=p.t0 + dt, dm=p.dm, fwhm=p.fwhm, snr=p.snr) for p in ps]
+
+    n_outs = [p.info["n_out"] for p in ss.plans]
+    context = [[shifted(truth[1 - q][b], -n_outs[b]) + shifted(truth[1 - q][b], n_outs[b]) for b in range(len(pds))]
+               for q in (0, 1)]
+
+    def on_block(k, final, ncand, recs):
+        q = k % 2
+        return ranking.recall_and_false_alarms(final, truth[q], pds, context_by_beam=context[q])
+
+    out = {"blocks": n_blocks, "warmup": warmup, "stream": "period of two blocks per beam (GPU-made series)",
+           "h2d_bytes_first_block": int(sum(h.numel() for h in first)),
+           "h2d_GBps_alone": ss.copy_rate(chunks[0]) / 1e9,
+           "assemble_ms_alone": ss.assemble_time() * 1e3}
     legs = [("plain", None)]
     if not args.no_ranker and all(pd["nchans"] % 64 == 0 for pd in pds):
         r = spl.Ranker(max_batch=256)
@@ -109,13 +148,15 @@ def end_to_end_leg(spl, pds, host, pulses, args, n_blocks=8, warmup=2):
     for name, ranker in legs:
         ss.ranker = ranker
         tm = {}
-        wall, res = ss.run([host], n_blocks, warmup, timing=tm,
-                           on_block=lambda k, f, nc: ranking.recall_and_false_alarms(f, pulses, pds))
+        wall, res = ss.run(first, chunks, n_blocks, warmup, timing=tm, on_block=on_block)
         steady = tm["steady_s"]
+        out["h2d_bytes_per_block"] = tm["h2d_bytes_per_block"]
         out[name] = {"ms_per_block": steady * 1e3, "real_time_beams_per_gpu": len(pds) * block_s / steady,
                      "wall_ms_per_block_with_drain": wall * 1e3, "drain_ms": tm["drain_s"] * 1e3,
                      "recall": float(np.mean([q["recall"] for q in res])),
-                     "false_alarms_per_beam_block": float(np.mean([q["false_alarms"] for q in res])) / len(pds)}
+                     "false_alarms_per_beam_block": float(np.mean([q["false_alarms"] for q in res])) / len(pds),
+                     "side_lobes_per_beam_block": float(np.mean([q["side_lobes"] for q in res])) / len(pds)}
+    out["h2d_bytes_whole_blocks"] = int(sum(p.info["nchans"] * p.info["n_in"] for p in ss.plans))
     del ss
     return out
 
@@ -166,6 +207,21 @@ def cpu_baseline(pd, plan, W, target_s=12.0):
                       f"{i['nchans']}-channel block" if blocks == 1 else
                       f"all {k2} DM trials x {i['n_out']} samples of {blocks} {i['nchans']}-channel blocks "
                       f"(beams of the workload)") + ": dedispersion + boxcar search + peak filters"}
+    # the same oracle on one core: the first k trials of the first block, about 8 s
+    n_all = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        k1 = max(1, int(k2 * 8.0 / max(t2 / blocks, 1e-3) / n_all))
+        k1 = min(k1, i["ndm"])
+        t1 = run(k1)
+        if t1 < 2.0 and k1 < i["ndm"]:
+            k1 = min(i["ndm"], int(k1 * 8.0 / max(t1, 1e-3)))
+            t1 = run(k1)
+    finally:
+        oracle.set_threads(n_all)
+    out["one_core"] = {"value": k1 * i["n_out"] / t1, "cores": 1, "seconds": round(t1, 3),
+                       "sample": f"first {k1} of {i['ndm']} DM trials x {i['n_out']} samples of one "
+                                 f"{i['nchans']}-channel block: dedispersion + boxcar search + peak filters"}
     if i["nchans"] % 64 == 0 and r["cands"].size and k2 == i["ndm"]:
         from oracle import cnn
         cs = r["cands"][:8]
@@ -333,7 +389,7 @@ def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, arg
         dev = torch.from_numpy(np.ascontiguousarray(r).view(np.int32).reshape(-1, 8).copy()).cuda()
         return ranker.score(spl.snippets(batch, dev)).cpu().numpy()
 
-    kept, surv, _ = ranking.ranker_path(spl, recs, tsamp, nb, score)
+    kept, surv, lg = ranking.ranker_path(spl, recs, tsamp, nb, score)
     n_scored = surv.size
     t_rank = time.perf_counter() - t0
     snip_leg = None
@@ -383,6 +439,7 @@ def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, arg
                                                       int(sel_w.max())]}
     pr = ranking.recall_and_false_alarms(fp, pulses, pds)
     rr = ranking.recall_and_false_alarms(kept, pulses, pds)
+    matched = ranking.at_false_alarms(spl, surv, lg, pulses, pds, pr["false_alarms"], nb)
 
     # throughput of the network itself
     rng = np.random.default_rng(0)
@@ -410,6 +467,7 @@ def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, arg
         "weights": "trained" if trained else "untrained (initial weights)",
         "plain_path": {**pr, "host_ms": t_plain * 1e3},
         "ranker_path": {**rr, "scored": int(n_scored), "stage_ms": t_rank * 1e3},
+        "ranker_at_plain_false_alarms": matched,
         "snippets": snip_leg,
         # the candidate stage after the search of the same block (serial), or overlapped
         # with the search of the next block (the stage runs on the host and the GPU's
@@ -426,6 +484,180 @@ def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, arg
                 "train_tflops": 3 * n * flop_fwd / t_trn / 1e12,
                 "mfma_peak_tflops_bf16": 2500.0},
     }
+
+
+def growth_leg(spl, W, pd, tiles, block_s, sizes=(96, 384, 768), steps=2, seed=77):
+    """Real-time beams measured by growing the batch of the 24-beam shape: batches of
+    `sizes` beams of the same plan, blocks made on the GPU (the same recipe as the
+    workload's: ten pulses and 2 % RFI channels per beam, torch's noise), one persistent
+    launch captured in a hipGraph with the tiles the autotuner chose for the plan.  A size
+    is skipped when its blocks and workspace do not fit the free device memory."""
+    import torch
+    plan = spl.Plan.from_dict(pd)
+    n_in = plan.info["n_in"]
+    rows = []
+    for nb in sizes:
+        probe = spl.Batch([plan] * nb, mode=spl.MODE_PERSISTENT_GRAPH)
+        need = probe.workspace_bytes() + nb * pd["nchans"] * ((n_in + 255) // 256 * 256) + (4 << 30)
+        free, _ = torch.cuda.mem_get_info()
+        if need > free:
+            rows.append({"beams": nb, "skipped": f"needs {need / 2**30:.1f} GiB, {free / 2**30:.1f} GiB free"})
+            del probe
+            continue
+        blocks = [W.c2_like_block_torch(pd, n_in, seed, b, 10)[1] for b in range(nb)]
+        probe.set_tiles(0, tiles["dm_per_wave"], tiles["time_groups"], tiles["chan_chunk"], waves=tiles["waves"])
+        probe.attach()
+        cands = spl.new_candidates(1 << 20)
+        stats = torch.zeros(spl.STATS_WORDS, dtype=torch.int64, device="cuda")
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            probe.run(blocks, cands, stats, stream=s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(s):
+            for _ in range(steps):
+                probe.run(blocks, cands, stats, stream=s)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        st = spl.stats_dict(stats)
+        rtf = ms / 1e3 / block_s
+        rows.append({"beams": nb, "ms_per_step": ms, "ms_per_beam": ms / nb, "real_time_factor": rtf,
+                     "dm_trial_samples_per_s": nb * plan.info["ndm"] * plan.info["n_out"] / (ms / 1e3),
+                     "hit_overflow": st["hit_overflow"]})
+        log(f"growth: {nb} beams {ms:.1f} ms per step (real-time factor {rtf:.4f})")
+        del probe, blocks, cands, stats
+        torch.cuda.empty_cache()
+    done = [r for r in rows if "ms_per_step" in r and r["real_time_factor"] <= 1.0]
+    out = {"sizes": rows}
+    if done:
+        big = max(done, key=lambda r: r["beams"])
+        out["largest_measured_beams"] = big["beams"]
+        out["real_time_beams_measured_at_least"] = big["beams"]
+        out["real_time_beams_extrapolated"] = big["beams"] / big["real_time_factor"]
+        out["extrapolation"] = (f"linear from the largest measured batch ({big['beams']} beams, real-time factor "
+                                f"{big['real_time_factor']:.4f}); the blocks and workspace of that many beams "
+                                f"exceed one GPU's memory, so they would run as successive batches")
+    return out
+
+
+def uneven_leg(spl, W, args, steps=5, warmup=2, seed=4):
+    """The 32-beam uneven batch (16 beams of the 2048-channel 300-500 MHz plan, 16 of the
+    4096-channel 550-750 MHz plan with 3072 trials), blocks made on the GPU with the
+    workload's recipe (ten pulses, 2 % RFI channels, zero-DM bursts; torch's noise), one
+    persistent graph launch with autotuned tiles: ms per step, throughput, the
+    dedispersion launch against the add peak, and per band the plain path against the
+    ranker path on the step's candidates (recall and false alarms of the injected pulses,
+    at the ranker's own operating point and at the plain path's false-alarm count)."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    from paper_2606_27262_amd import ranking
+    pds = W.batch_c4_plans()
+    cache = {}
+    plans = []
+    for pd in pds:
+        key = json.dumps(pd, sort_keys=True, default=str)
+        if key not in cache:
+            cache[key] = spl.Plan.from_dict(pd)
+        plans.append(cache[key])
+    blocks, pulses = [], []
+    for b, (pd, p) in enumerate(zip(pds, plans)):
+        spec, x = W.c2_like_block_torch(pd, p.info["n_in"], seed, b, 10, dm_max_pulse=0.9 * W.dm_max(pd),
+                                        zero_dm_rate=0.2)
+        blocks.append(x)
+        pulses.append(list(spec.pulses))
+    batch = spl.Batch(plans, mode=spl.MODE_PERSISTENT_GRAPH)
+    batch.attach()
+    if not args.no_autotune:
+        batch.autotune(blocks, cache_path=args.tile_cache or os.path.join(tempfile.gettempdir(), "spotlight_tiles.txt"))
+    cands = spl.new_candidates(1 << 22)
+    stats = torch.zeros(spl.STATS_WORDS, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for _ in range(warmup):
+            batch.run(blocks, cands, stats, stream=s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        for _ in range(steps):
+            batch.run(blocks, cands, stats, stream=s)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    st = spl.stats_dict(stats)
+    batch.set_profiling(True)
+    with torch.cuda.stream(s):
+        for _ in range(steps):
+            batch.run(blocks, cands, stats, stream=s)
+    torch.cuda.synchronize()
+    stages = batch.stage_times(reset=True)
+    batch.set_profiling(False)
+    dd_ms, dd_n = stages["dedisp"]
+    adds = sum(p.info["ndm"] * p.info["nchans"] * p.info["n_out"] for p in plans)
+    block_s = max(pd["n_out"] * pd["tsamp"] for pd in pds)
+    out = {"workload": "c4", "beams": len(pds), "ms_per_step": ms,
+           "value": sum(p.info["ndm"] * p.info["n_out"] for p in plans) / (ms / 1e3),
+           "unit": "DM-trial·samples/s", "real_time_factor": ms / 1e3 / block_s,
+           "dedisp_ms_per_step": dd_ms / steps, "dedisp_adds_per_s": adds / (dd_ms / steps / 1e3),
+           "dedisp_frac_add_peak": adds / (dd_ms / steps / 1e3) / PEAK_ADDS,
+           "tiles": {f"{p.info['nchans']}ch": batch.tiles(b) for b, p in ((0, plans[0]), (1, plans[1]))},
+           "candidates": st["n_candidates"], "hits": st["n_hits"], "cand_overflow": st["cand_overflow"]}
+    if not args.no_ranker:
+        with torch.cuda.stream(s):
+            batch.run(blocks, cands, stats, stream=s)
+        torch.cuda.synchronize()
+        recs = spl.candidates_to_numpy(cands, stats)
+        tsamp = np.array([pd["tsamp"] for pd in pds], np.float64)
+        ranker = spl.Ranker(max_batch=256)
+        ranker.set_weights(np.load(args.ranker_weights) if os.path.exists(args.ranker_weights)
+                           else ranking.initial_weights(0))
+
+        def score(r):
+            dev = torch.from_numpy(np.ascontiguousarray(r).view(np.int32).reshape(-1, 8).copy()).cuda()
+            return ranker.score(spl.snippets(batch, dev)).cpu().numpy()
+
+        fp = spl.optimise_plain(recs, tsamp, len(pds))
+        fr, scored, lg = ranking.ranker_path(spl, recs, tsamp, len(pds), score)
+        out["ranker"] = per_band_comparison(spl, pds, pulses, fp, fr, scored, lg)
+    del batch, blocks
+    torch.cuda.empty_cache()
+    return out
+
+
+def per_band_comparison(spl, pds, pulses, fp, fr, scored, lg):
+    """Per band (beams sharing channel count and band): recall and false alarms of the
+    plain path and the ranker path, and the ranker at the plain path's false-alarm count
+    (thresholds on its logits, anti-coincidence among that band's beams)."""
+    import numpy as np
+
+    from paper_2606_27262_amd import ranking
+    bands = {}
+    for b, pd in enumerate(pds):
+        bands.setdefault(f"{pd['nchans']}ch/{pd['fch1'] + (pd['nchans'] - 1) * pd['foff']:.0f}-{pd['fch1']:.0f}MHz",
+                         []).append(b)
+    out = {}
+    for name, beams in bands.items():
+        remap = np.full(len(pds), -1, np.int64)
+        remap[beams] = np.arange(len(beams))
+
+        def sub(c):
+            c = c[np.isin(c["beam"], beams)].copy()
+            c["beam"] = remap[c["beam"]]
+            return c
+
+        ps = [pulses[b] for b in beams]
+        pdb = [pds[b] for b in beams]
+        p_ = ranking.recall_and_false_alarms(sub(fp), ps, pdb)
+        r_ = ranking.recall_and_false_alarms(sub(fr), ps, pdb)
+        sel = np.isin(scored["beam"], beams)
+        m = ranking.at_false_alarms(spl, sub(scored), lg[sel], ps, pdb, p_["false_alarms"], len(beams))
+        nbb = len(beams)
+        out[name] = {"beams": nbb,
+                     "plain": {**p_, "false_alarms_per_beam_block": p_["false_alarms"] / nbb},
+                     "ranker": {**r_, "false_alarms_per_beam_block": r_["false_alarms"] / nbb},
+                     "ranker_at_plain_false_alarms": m}
+    return out
 
 
 def main():
@@ -445,6 +677,9 @@ def main():
                     help="blocks of the end-to-end stream leg of a multi-beam workload (0: skip)")
     ap.add_argument("--no-per-beam", action="store_true",
                     help="skip the comparison run of a multi-beam workload in plain per-beam mode")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the 32-beam uneven-batch leg of the c3 run")
+    ap.add_argument("--growth", default="96,384,768",
+                    help="beam counts of the growing-batch leg of the c3 run (comma-separated; empty: skip)")
     ap.add_argument("--ranker-weights", default=os.path.join(ROOT, "paper_2606_27262_amd", "data",
                                                              "ranker_weights.npy"))
     args = ap.parse_args()
@@ -468,7 +703,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     e2e = args.e2e_blocks > 0 and args.workload in ("c3", "c4", "c3s")
-    pds, plans, blocks, pulses, host = make_workload(args.workload, spl, W, keep_host=e2e)
+    pds, plans, blocks, pulses, _ = make_workload(args.workload, spl, W)
     nb = len(plans)
     mode = args.mode
     if mode == "auto":
@@ -549,7 +784,11 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_dedisp", "achieved": achieved / 1e12,
                      "peak": PEAK_ADDS / 1e12, "unit": "Tadd/s (int32)", "frac": achieved / PEAK_ADDS,
                      "traffic": None, "launch_ms": avg_launch_s * 1e3,
-                     "adds_per_launch": adds_per_launch},
+                     "adds_per_launch": adds_per_launch,
+                     # two exact adds per lane and clock (v_add3_u32, or two 16-bit lanes of a
+                     # 32-bit add): the kernel's instruction mix reaches for this one
+                     "peak_two_adds_per_lane": 2 * PEAK_ADDS / 1e12,
+                     "frac_two_adds_per_lane": achieved / (2 * PEAK_ADDS)},
     }
     tr = counter_traffic(args.workload, [batch.tiles(b) for b in range(nb)])
     if tr is not None and launches_per_step == 1:
@@ -571,10 +810,22 @@ def main():
         log("ranker leg")
         out["ranker"] = ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, args, ms_step,
                                    block_s)
+    tiles0 = batch.tiles(0)
+    del batch, blocks
+    torch.cuda.empty_cache()
     if e2e:
         log("end-to-end stream")
-        del batch
-        out["end_to_end"] = end_to_end_leg(spl, pds, host, pulses, args, n_blocks=args.e2e_blocks)
+        out["end_to_end"] = end_to_end_leg(spl, W, pds, args, n_blocks=args.e2e_blocks)
+        torch.cuda.empty_cache()
+    if args.workload == "c3" and not args.no_uneven:
+        log("uneven 32-beam batch")
+        out["uneven_batch"] = uneven_leg(spl, W, args)
+    if args.workload == "c3" and args.growth:
+        log("growing the batch")
+        out["real_time_beams"] = growth_leg(spl, W, pds[0], tiles0, block_s,
+                                            sizes=tuple(int(v) for v in args.growth.split(",")))
+        out["real_time_beams"]["sizes"].insert(0, {"beams": nb, "ms_per_step": ms_step, "ms_per_beam": ms_step / nb,
+                                                   "real_time_factor": rtf, "dm_trial_samples_per_s": value})
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(pds[0], plans[0], W)

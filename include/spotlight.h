@@ -367,6 +367,30 @@ spl_status spl_optimise_plain(const spl_candidate *cands, int64_t n, const doubl
                               int32_t n_beams, const spl_opt_params *params, spl_candidate *out,
                               int64_t capacity, int64_t *n_out);
 
+/* --------------------------------------------------------- stream device ring */
+/*
+ * Continuous beam streams (the paper reads each block with an overlap so that every
+ * dispersion sweep and boxcar of its owned samples is complete): block k of a beam reads
+ * stream samples [k n_out, k n_out + n_in) (n_out, n_in of the beam's plan), so the next
+ * block starts with the last carry = n_in - n_out = s_max + w_max - 1 samples of the
+ * previous one.  Only the n_out new samples cross the host link: the caller copies them
+ * into a device staging buffer (one contiguous copy from pinned memory), and
+ *   d_next[c][j] = d_prev[c][n_out + j]        for j <  carry
+ *   d_next[c][j] = d_stage[c][j - carry]       for carry <= j < n_in
+ * for every channel c < nch.  d_next, d_prev: device blocks uint8 [nch][pitch]
+ * (pitches >= n_in, multiples of 16; pointers 16-byte aligned; not overlapping; d_prev
+ * may be NULL when carry = 0).  d_stage: device uint8 [nch][stage_pitch], stage_pitch >=
+ * n_out and a multiple of 4, pointer 4-byte aligned, with at least 16 readable bytes
+ * after the last row's n_out-th byte (rows are read in aligned dwords).  n_out a
+ * multiple of 16.  Bytes of d_next beyond n_in are left unchanged.  Asynchronous on
+ * `stream`: the caller orders it after the copy into d_stage and before the search of
+ * d_next, and keeps d_prev unchanged until it has run.  SPL_E_INVALID_ARG on NULL
+ * pointers, sizes or alignments out of range, or overlapping buffers.
+ */
+spl_status spl_stream_assemble(uint8_t *d_next, int64_t next_pitch, const uint8_t *d_prev, int64_t prev_pitch,
+                               const uint8_t *d_stage, int64_t stage_pitch, int32_t nch, int64_t n_out,
+                               int64_t n_in, hipStream_t stream);
+
 /* ------------------------------------------------------------------ corner turn */
 /*
  * Filterbank files hold one spectrum after another (time-major: all channels of

@@ -65,12 +65,19 @@ def _load():
         lib.orc_dbscan.restype = i32
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = i32
+        lib.orc_set_threads.argtypes = [i32]
+        lib.orc_set_threads.restype = None
         _lib = lib
     return _lib
 
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    _load().orc_set_threads(int(n))
 
 
 def _p(a: np.ndarray):

@@ -50,6 +50,16 @@ int32_t orc_num_threads(void)
 #endif
 }
 
+/* Set the threads of the oracle's parallel loops (n >= 1). */
+void orc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Eq. (1): integer delay table                                               */
 /* ------------------------------------------------------------------------ */

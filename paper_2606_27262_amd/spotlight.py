@@ -144,6 +144,7 @@ INJECT_SAMPLE, INJECT_ARGMAX = 0, 1
 
 _F32 = ctypes.c_float
 _sig("spl_corner_turn", [_P, _I64, _I32, _I64, _P, _I64, _P])
+_sig("spl_stream_assemble", [_P, _I64, _P, _I64, _P, _I64, _I32, _I64, _I64, _P])
 _sig("spl_inject_quantised", [_P, _I64, _I64, _I32, _P, _P, _P, _I32, _I32, ctypes.POINTER(_Quantiser), _I32, _P])
 _sig("spl_ranker_snippets", [_P, _P, _I64, _P, _P])
 _sig("spl_ranker_snippets_fine", [_P, _P, _I64, _F64, _P, _P])
@@ -475,6 +476,30 @@ def upload_block(x_np, device="cuda", pitch=None):
     t = torch.zeros((nch, p), dtype=torch.uint8, device=device)
     t[:, :n] = torch.from_numpy(np.ascontiguousarray(x_np)).to(device)
     return t
+
+
+def stream_assemble(d_next, d_prev, d_stage, n_out, n_in, stream=None):
+    """spl_stream_assemble: device block d_next (uint8 CUDA tensor [nch][pitch]) = the last
+    n_in - n_out samples of device block d_prev, then the n_out new samples of d_stage
+    (uint8 CUDA tensor [nch][stage_pitch], stage_pitch >= n_out, whose storage extends at
+    least 16 bytes past its last row's n_out-th byte)."""
+    nch = d_next.shape[0]
+    assert d_prev.shape[0] == nch and d_stage.shape[0] == nch
+    assert d_next.stride(1) == 1 and d_prev.stride(1) == 1 and d_stage.stride(1) == 1
+    end = d_stage.storage_offset() + (nch - 1) * d_stage.stride(0) + int(n_out) + 16
+    assert end <= d_stage.untyped_storage().nbytes(), "the staging buffer needs 16 bytes of slack after its last row"
+    _check(_lib.spl_stream_assemble(ctypes.c_void_p(d_next.data_ptr()), d_next.stride(0),
+                                    ctypes.c_void_p(d_prev.data_ptr()), d_prev.stride(0),
+                                    ctypes.c_void_p(d_stage.data_ptr()), d_stage.stride(0), nch, int(n_out),
+                                    int(n_in), _stream_handle(stream)))
+
+
+def new_stage(nch, n_out, device="cuda"):
+    """Device staging buffer [nch][n_out] for stream_assemble, with the 16 bytes of slack
+    its last row needs (an allocation of nch * n_out + 256 bytes)."""
+    import torch
+    flat = torch.empty(nch * n_out + 256, dtype=torch.uint8, device=device)
+    return flat[:nch * n_out].view(nch, n_out)
 
 
 def corner_turn(x_tc, out=None, pitch=None, stream=None):

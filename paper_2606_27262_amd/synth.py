@@ -114,13 +114,16 @@ def pulse_template(spec: BlockSpec, p: Pulse, amp: float):
     return starts, vals
 
 
-def _chunk_rows(spec: BlockSpec, seed: int, beam: int, ci: int, widths) -> np.ndarray:
+def _chunk_rows(spec: BlockSpec, seed: int, beam: int, ci: int, widths, noise: bool = True) -> np.ndarray:
     c0 = ci * _CHUNK
     c1 = min(spec.nch, c0 + _CHUNK)
-    rng = _rng(seed, beam, ci)
-    v = rng.standard_normal((c1 - c0, spec.n_in), dtype=np.float32)
-    v *= NOISE_SIGMA
-    v += NOISE_MEAN
+    if noise:
+        rng = _rng(seed, beam, ci)
+        v = rng.standard_normal((c1 - c0, spec.n_in), dtype=np.float32)
+        v *= NOISE_SIGMA
+        v += NOISE_MEAN
+    else:
+        v = np.full((c1 - c0, spec.n_in), NOISE_MEAN, np.float32)
     # persistent RFI: +3 sigma offset, twice the variance
     for c in spec.rfi_channels_persistent:
         if c0 <= c < c1:
@@ -154,14 +157,15 @@ def _chunk_rows(spec: BlockSpec, seed: int, beam: int, ci: int, widths) -> np.nd
 
 
 def make_block(spec: BlockSpec, seed: int, beam: int = 0, widths=(1, 2, 4, 8, 16, 32, 64),
-               threads: int = 8) -> np.ndarray:
-    """uint8 block [nch][pitch]; samples beyond n_in in each row are 0."""
+               threads: int = 8, noise: bool = True) -> np.ndarray:
+    """uint8 block [nch][pitch]; samples beyond n_in in each row are 0.  noise=False
+    leaves the receiver noise out (every sample starts at the mean)."""
     pitch = spec.row_pitch()
     out = np.zeros((spec.nch, pitch), np.uint8)
     nchunks = (spec.nch + _CHUNK - 1) // _CHUNK
 
     def work(ci):
-        rows = _chunk_rows(spec, seed, beam, ci, widths)
+        rows = _chunk_rows(spec, seed, beam, ci, widths, noise)
         out[ci * _CHUNK: ci * _CHUNK + rows.shape[0], :spec.n_in] = rows
 
     if threads > 1 and nchunks > 1:
@@ -170,6 +174,63 @@ def make_block(spec: BlockSpec, seed: int, beam: int = 0, widths=(1, 2, 4, 8, 16
     else:
         for ci in range(nchunks):
             work(ci)
+    return out
+
+
+def make_block_torch(spec: BlockSpec, seed: int, beam: int = 0, widths=(1, 2, 4, 8, 16, 32, 64),
+                     device="cuda", noise: bool = True):
+    """The same recipe as make_block, evaluated with torch on `device` (for training sets
+    of many blocks): Gaussian noise from torch's generator seeded by (seed, beam) (so the
+    noise differs from make_block's Philox stream; everything else is the same sky
+    model), RFI channels, zero-DM bursts and pulses added in float32 before rounding to
+    the nearest integer (ties to even) and clipping to 0..255.  noise=False leaves the
+    noise out (the deterministic part, for checking against make_block).  Returns a
+    uint8 tensor [nch][pitch] on `device`; samples beyond n_in are 0."""
+    import torch
+    nch, n_in = spec.nch, spec.n_in
+    if noise:
+        g = torch.Generator(device=device)
+        g.manual_seed((int(seed) * 1000003 + int(beam) * 7919 + 12345) & 0x7FFFFFFFFFFFFFFF)
+        v = torch.randn((nch, n_in), generator=g, device=device, dtype=torch.float32)
+        v.mul_(NOISE_SIGMA).add_(NOISE_MEAN)
+    else:
+        v = torch.full((nch, n_in), NOISE_MEAN, device=device, dtype=torch.float32)
+    for c in spec.rfi_channels_persistent:
+        v[c] = (v[c] - NOISE_MEAN) * math.sqrt(2.0) + NOISE_MEAN + 3 * NOISE_SIGMA
+    if spec.rfi_channels_intermittent:
+        add = np.zeros((len(spec.rfi_channels_intermittent), n_in), np.float32)
+        for i, c in enumerate(spec.rfi_channels_intermittent):
+            r = _rng(seed, beam, c, salt=1)
+            t = int(r.integers(0, 500))
+            while t < n_in:
+                length = int(r.integers(10, 501))
+                amp = math.exp(r.uniform(0.0, math.log(8.0))) * NOISE_SIGMA
+                add[i, t:t + length] += amp
+                t += length + int(length * 4 * r.uniform(0.5, 1.5))
+        idx = torch.tensor(spec.rfi_channels_intermittent, device=device, dtype=torch.long)
+        v.index_add_(0, idx, torch.from_numpy(add).to(device))
+    for (t0, width, amp) in spec.zero_dm_bursts:
+        lo, hi = max(0, int(t0)), min(n_in, int(t0) + int(width))
+        if hi > lo:
+            v[:, lo:hi] += float(amp) * NOISE_SIGMA
+    flat = v.view(-1)
+    rows = torch.arange(nch, device=device, dtype=torch.long)[:, None]
+    for p in spec.pulses:
+        amp = pulse_amplitude(p, nch, widths)
+        s = p.fwhm / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+        K = int(math.ceil(12 * s)) + 4
+        centres = torch.from_numpy(p.t0 + arrival_offsets(spec, p.dm)).to(device)
+        starts = torch.floor(centres - 6 * s).to(torch.long) - 1
+        t = starts[:, None] + torch.arange(K + 1, device=device, dtype=torch.long)[None, :]
+        cdf = torch.special.ndtr((t.to(torch.float64) - centres[:, None]) / s)
+        vals = (amp * s * math.sqrt(2.0 * math.pi) * torch.diff(cdf, dim=1)).to(torch.float32)
+        cols = t[:, :K]
+        ok = (cols >= 0) & (cols < n_in)
+        flat.index_add_(0, (rows * n_in + cols)[ok], vals[ok])
+    torch.round(v, out=v)
+    v.clamp_(0.0, 255.0)
+    out = torch.zeros((nch, spec.row_pitch()), dtype=torch.uint8, device=device)
+    out[:, :n_in] = v.to(torch.uint8)
     return out
 
 

@@ -81,6 +81,71 @@ def c2_like_block(plan, n_in, seed, beam, n_pulses, dm_max_pulse=1800.0, rfi_fra
     return spec, synth.make_block(spec, seed, beam, plan["widths"])
 
 
+def c2_like_block_torch(plan, n_in, seed, beam, n_pulses, dm_max_pulse=1800.0, rfi_frac=0.02,
+                        zero_dm_rate=0.0, fwhm_hi=64.0, device="cuda"):
+    """c2_like_block's recipe (same pulses, RFI channels and zero-DM bursts for the same
+    seed and beam) made with torch on `device` (synth.make_block_torch: torch's noise):
+    a uint8 tensor [nch][pitch]."""
+    rng = np.random.default_rng([seed, beam, 12345])
+    pulses = synth.pulses_evenly(rng, n_pulses, plan["n_out"], 50.0, dm_max_pulse,
+                                 1.0, fwhm_hi, 8.0, 50.0)
+    rfi = synth.rfi_channels(rng, plan["nchans"], rfi_frac) if rfi_frac > 0 else None
+    zd = synth.zero_dm_bursts(rng, n_in, plan["tsamp"], zero_dm_rate) if zero_dm_rate > 0 else ()
+    spec = block_spec(plan, n_in, pulses, rfi, zd)
+    return spec, synth.make_block_torch(spec, seed, beam, plan["widths"], device=device)
+
+
+def stream_series(plan, n_blocks, n_in, seed, beam, n_pulses_per_block, dm_max_pulse=1800.0, rfi_frac=0.02,
+                  zero_dm_rate=0.0, fwhm_hi=64.0, period=0, device=None):
+    """A continuous stream of one beam, in blocks: block k owns stream samples
+    [k n_out, (k+1) n_out) and reads [k n_out, k n_out + n_in) (the overlap tail of the
+    plan).  Pulses with DM ~ U(50, dm_max_pulse), FWHM log-U(1, fwhm_hi), S/N ~ U(8, 50),
+    n_pulses_per_block in evenly spaced slots of every block's owned samples, 2 % RFI
+    channels, optional zero-DM bursts.
+
+    period = 0: the series holds n_in + (n_blocks - 1) n_out samples.  period = m > 0:
+    the series holds m n_out samples and the stream repeats it (block k reads it modulo
+    its length, so blocks k and k + m are equal); a pulse's DM is capped so that its
+    whole sweep ends before the period does (no pulse crosses the wrap).
+    Returns the series uint8 [nch][length] (numpy; with a torch device, a tensor made
+    there by synth.make_block_torch) and, per block of one period (or of the whole
+    series), the pulses with t0 relative to that block's first sample."""
+    n_out = plan["n_out"]
+    length = period * n_out if period else n_in + (n_blocks - 1) * n_out
+    n_own = period if period else n_blocks
+    rng = np.random.default_rng([seed, beam, 54321])
+    probe = block_spec(plan, length)
+    k_bottom = float(synth.arrival_offsets(probe, 1.0).max())    # samples per unit DM, lowest channel
+    pulses, per_block = [], []
+    for k in range(n_own):
+        ps = synth.pulses_evenly(rng, n_pulses_per_block, n_out, 50.0, dm_max_pulse, 1.0, fwhm_hi, 8.0, 50.0)
+        mine = []
+        for p in ps:
+            t0 = p.t0 + k * n_out
+            dm = p.dm
+            if period:
+                dm = min(dm, (length - t0 - 4.0 * p.fwhm - 8.0) / k_bottom)
+            q = synth.Pulse(t0=t0, dm=max(dm, 0.0), fwhm=p.fwhm, snr=p.snr)
+            pulses.append(q)
+            mine.append(synth.Pulse(t0=p.t0, dm=q.dm, fwhm=p.fwhm, snr=p.snr))
+        per_block.append(mine)
+    rfi = synth.rfi_channels(rng, plan["nchans"], rfi_frac) if rfi_frac > 0 else None
+    zd = synth.zero_dm_bursts(rng, length, plan["tsamp"], zero_dm_rate) if zero_dm_rate > 0 else ()
+    spec = block_spec(plan, length, pulses, rfi, zd)
+    if device is not None:
+        return synth.make_block_torch(spec, seed, beam, plan["widths"], device=device)[:, :length], per_block
+    x = synth.make_block(spec, seed, beam, plan["widths"])
+    return x[:, :length], per_block
+
+
+def stream_block(series, n_out, n_in, k):
+    """Block k of a stream series (periodic when the series is shorter than the block's
+    end): samples [k n_out, k n_out + n_in) modulo the series length."""
+    L = series.shape[1]
+    idx = (k * n_out + np.arange(n_in)) % L
+    return series[:, idx]
+
+
 def batch_c3_plans():
     """24 beams of the 4096-channel Band-4 plan (one GPU's share of 2000 beams on 90 GPUs)."""
     return [plan_c2() for _ in range(24)]
@@ -115,5 +180,5 @@ def describe(plan):
 
 
 __all__ = ["make_plan", "plan_c1", "plan_c2", "plan_band3_c4", "plan_band4_c4", "block_spec",
-           "c1_block", "c2_like_block", "batch_c3_plans", "batch_c4_plans", "dm_max",
+           "c1_block", "c2_like_block", "c2_like_block_torch", "stream_series", "stream_block", "batch_c3_plans", "batch_c4_plans", "dm_max",
            "real_time_s", "describe"]

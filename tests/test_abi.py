@@ -271,3 +271,22 @@ def test_static_entry_point_rejects_a_batch_beyond_its_scratch():
                                        ctypes.c_void_p(fake), None)
     assert st == spl.SPL_E_UNSUPPORTED
     assert b"static scratch" in spl._lib.spl_last_error()
+
+
+def test_stream_assemble_argument_checks():
+    """spl_stream_assemble refuses, before any device work, pitches below the row
+    lengths, n_out outside [1, n_in], misaligned sizes and overlapping buffers."""
+    lib = spl._lib
+    f = 1 << 40   # stand-in addresses: every check here comes before a device access
+    g, h = f + (1 << 30), f + (2 << 30)
+    E = spl.SPL_E_INVALID_ARG
+    assert lib.spl_stream_assemble(f, 128, g, 256, h, 64, 4, 48, 150, None) == E     # next pitch < n_in
+    assert lib.spl_stream_assemble(f, 256, g, 256, h, 32, 4, 48, 150, None) == E     # stage pitch < n_out
+    assert lib.spl_stream_assemble(f, 256, f + 512, 256, h, 64, 4, 48, 150, None) == E   # blocks overlap
+    assert lib.spl_stream_assemble(f, 256, g, 256, f + 600, 64, 4, 48, 150, None) == E   # stage overlaps next
+    assert lib.spl_stream_assemble(f, 256, g, 256, h, 64, 4, 200, 150, None) == E    # n_out > n_in
+    assert lib.spl_stream_assemble(f, 256, g, 256, h, 64, 4, 40, 150, None) == E     # n_out not a multiple of 16
+    assert lib.spl_stream_assemble(f + 8, 256, g, 256, h, 64, 4, 48, 150, None) == E  # misaligned block
+    assert lib.spl_stream_assemble(f, 256, g, 256, h, 66, 4, 48, 150, None) == E     # stage pitch % 4
+    assert lib.spl_stream_assemble(f, 256, None, 256, h, 64, 4, 48, 150, None) == E  # no previous block
+    assert lib.spl_stream_assemble(f, 256, g, 256, h, 64, 0, 48, 150, None) == E     # no channels

@@ -1,13 +1,17 @@
-"""The streaming driver (copies, search and candidate stage overlapped over three
-rotating batches) returns, block for block, exactly what a direct search of the same
-block followed by the plain optimisation path returns."""
+"""The streaming driver on continuous beam streams: block by block, the stream's
+candidate records equal the oracle's search of the same samples of each beam's series
+(blocks overlapping by s_max + w_max - 1 samples, the overlap carried on the device and
+only the new samples uploaded), and its final list after the plain optimisation path
+equals the oracle's plain path on the oracle's candidates."""
 import os
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_2606_27262_amd import workloads as W
+from plan_tables import assert_library_tables, oracle_plan
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -21,59 +25,126 @@ def spl():
     return spotlight
 
 
-def test_stream_equals_direct_runs(spl):
-    from paper_2606_27262_amd import ranking, streaming
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _pinned(a):
+    h = torch.empty(a.shape, dtype=torch.uint8, pin_memory=True)
+    h.numpy()[:] = a
+    return h
+
+
+@pytest.mark.parametrize("n_out,n_in", [(48, 150), (48, 151), (48, 48), (64, 65), (16, 1041), (32, 53), (2048, 13222)])
+def test_assemble_bytes(spl, n_out, n_in):
+    """spl_stream_assemble byte for byte: carries of every residue mod 4 and 16 (the
+    staged samples start unaligned), no carry, rows whose end is not a multiple of 16;
+    bytes beyond n_in stay unchanged."""
+    rng = np.random.default_rng(n_out * 7 + n_in)
+    nch = 37
+    pitch = (n_in + 255) // 256 * 256
+    prev = rng.integers(0, 256, (nch, pitch), dtype=np.uint8)
+    stage = rng.integers(0, 256, (nch, n_out), dtype=np.uint8)
+    nxt = rng.integers(0, 256, (nch, pitch), dtype=np.uint8)
+    dp, dn = torch.from_numpy(prev).cuda(), torch.from_numpy(nxt).cuda()
+    ds = spl.new_stage(nch, n_out)
+    ds.copy_(torch.from_numpy(stage))
+    spl.stream_assemble(dn, dp, ds, n_out, n_in)
+    torch.cuda.synchronize()
+    got = dn.cpu().numpy()
+    want = nxt.copy()
+    carry = n_in - n_out
+    want[:, :carry] = prev[:, n_out:n_in]
+    want[:, carry:n_in] = stage
+    assert np.array_equal(got, want)
+
+
+def _stream_inputs(spl, pds, plans, n_blocks, seed):
+    """Per beam a continuous series of n_in + (n_blocks - 1) n_out samples; the first
+    block whole (slot pitch) and the new samples of every later block."""
+    series, first, chunks = [], [], [[] for _ in range(n_blocks - 1)]
+    for b, (pd, p) in enumerate(zip(pds, plans)):
+        n_in, n_out = p.info["n_in"], p.info["n_out"]
+        x, _ = W.stream_series(pd, n_blocks, n_in, seed, b, 2, dm_max_pulse=0.8 * W.dm_max(pd), fwhm_hi=8.0)
+        series.append(x)
+        pitch = (n_in + 255) // 256 * 256
+        f = np.zeros((x.shape[0], pitch), np.uint8)
+        f[:, :n_in] = x[:, :n_in]
+        first.append(_pinned(f))
+        for k in range(1, n_blocks):
+            chunks[k - 1].append(_pinned(np.ascontiguousarray(x[:, n_in + (k - 1) * n_out: n_in + k * n_out])))
+    return series, first, chunks
+
+
+def _oracle_block(plan, series, k, beam):
+    o = oracle_plan(plan)
+    x = W.stream_block(series, o["n_out"], o["n_in"], k)
+    return oracle.search_beam(x, o["D"], o["dms"], o["n_out"], o["L"], o["widths"], o["threshold"],
+                              stencils=o["stencils"], beam=beam)["cands"]
+
+
+def test_stream_equals_oracle_block_by_block(spl):
+    from paper_2606_27262_amd import streaming
     pd = W.plan_c1()
     pd["n_out"] = pd["norm_window"] = 2048
     pds = [dict(pd) for _ in range(3)]
-    plan = spl.Plan.from_dict(pd)
-    n_in = plan.info["n_in"]
-    sets, pulses = [], []
-    for seed in (11, 12):
-        blocks, ps = ranking.burst_batch(pds, seed, n_pulses=2, dm_lo=50.0, dm_hi=450.0, fwhm_hi=8.0,
-                                         snr_lo=10.0, snr_hi=30.0, zero_dm_rate=0.0, n_in=[n_in] * 3)
-        hs = []
-        for x in blocks:
-            h = torch.zeros((x.shape[0], (n_in + 255) // 256 * 256), dtype=torch.uint8, pin_memory=True)
-            h[:, :n_in] = torch.from_numpy(np.ascontiguousarray(x))
-            hs.append(h)
-        sets.append(hs)
-        pulses.append(ps)
-    # direct: one batch per set, plain mode, then the plain path on the host
-    ref = []
-    for hs in sets:
-        b = spl.Batch([plan] * 3)
-        dev = [h.cuda() for h in hs]
-        cands, stats = b.run(dev, spl.new_candidates(1 << 16))
-        torch.cuda.synchronize()
-        recs = spl.candidates_to_numpy(cands, stats)
-        ref.append((spl.optimise_plain(recs, [pd["tsamp"]] * 3, 3), recs.size))
-        del b, dev
+    n_blocks = 6
     ss = streaming.StreamingSearch(spl, pds, cand_capacity=1 << 16)
+    for p in ss.plans:
+        assert_library_tables(p)
     ss.attach()
-    _, res = ss.run(sets, 7, warmup=1, on_block=lambda k, f, n: (k, f.copy(), n))
-    assert len(res) == 7
-    for k, final, n in res:
-        rf, rn = ref[k % 2]
-        print(f"block {k}: {n} candidates, {final.size} kept", flush=True)
-        assert n == rn
+    series, first, chunks = _stream_inputs(spl, pds, ss.plans, n_blocks, seed=21)
+    ref = []
+    for k in range(n_blocks):
+        c = np.concatenate([_oracle_block(ss.plans[b], series[b], k, b) for b in range(3)])
+        tsamp = np.array([p["tsamp"] for p in pds])
+        ref.append((c, oracle.plain_optimise(c, tsamp, 3)))
+    tm = {}
+    _, res = ss.run(first, chunks, n_blocks, warmup=1, on_block=lambda k, f, n, r: (k, f.copy(), n, r.copy()),
+                    timing=tm)
+    assert len(res) == n_blocks and tm["h2d_bytes_per_block"] == 3 * 256 * 2048
+    for k, final, n, recs in res:
+        rc, rf = ref[k]
+        say(f"block {k}: {n} candidates (oracle {rc.size}), {final.size} kept (oracle {rf.size})")
+        assert n == rc.size and np.array_equal(recs, rc), k
         assert np.array_equal(final.view(np.int32), rf.view(np.int32)), k
     # a record prefix far smaller than the blocks' candidate counts: the records beyond
     # it are fetched after the statistics, with the same results, and the prefix grows
     ss.copy_hint = 16
-    _, res = ss.run(sets, 4, warmup=1, on_block=lambda k, f, n: (k, f.copy(), n))
-    for k, final, n in res:
-        rf, rn = ref[k % 2]
-        assert n == rn and np.array_equal(final.view(np.int32), rf.view(np.int32)), k
-    assert ss.copy_hint >= min(1 << 16, max(r[1] for r in ref))
+    _, res = ss.run(first, chunks, n_blocks, warmup=1, on_block=lambda k, f, n, r: (k, f.copy(), n, r.copy()))
+    for k, final, n, recs in res:
+        assert np.array_equal(recs, ref[k][0]) and np.array_equal(final.view(np.int32), ref[k][1].view(np.int32))
+    assert ss.copy_hint >= min(1 << 16, max(r[0].size for r in ref))
     # the ranker path runs through the same pipeline and keeps a subset of its inputs
     w = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2606_27262_amd", "data",
                      "ranker_weights.npy")
     r = spl.Ranker(max_batch=64)
-    r.set_weights(np.load(w) if os.path.exists(w) else ranking.initial_weights(0))
+    r.set_weights(np.load(w))
     ss.ranker = r
-    _, res = ss.run(sets, 4, warmup=1, on_block=lambda k, f, n: (k, f.copy(), n))
+    _, res = ss.run(first, chunks, 4, warmup=1, on_block=lambda k, f, n, rr: (k, f.copy(), n))
     for k, final, n in res:
-        assert n == ref[k % 2][1]
-        assert final.size <= n
-    sys.stdout.flush()
+        assert n == ref[k][0].size and final.size <= n
+    # a ranker without weights falls back to the plain path
+    ss.ranker = spl.Ranker(max_batch=64)
+    _, res = ss.run(first, chunks, 3, warmup=1, on_block=lambda k, f, n, rr: (k, f.copy()))
+    for k, final in res:
+        assert np.array_equal(final.view(np.int32), ref[k][1].view(np.int32)), k
+
+
+def test_stream_uneven_plans(spl):
+    """Two plans of different channel counts and block lengths in one stream: every
+    block of every beam equals the oracle's search of its samples."""
+    from paper_2606_27262_amd import streaming
+    a = W.make_plan(128, 300.0, 500.0, 1.31072e-3, 1536, 0.0, 200.0, 40, W.W64)
+    b = W.make_plan(96, 550.0, 750.0, 0.65536e-3, 3072, 0.0, 500.0, 64, (1, 2, 4, 8))
+    pds = [a, b, a]
+    n_blocks = 4
+    ss = streaming.StreamingSearch(spl, pds, cand_capacity=1 << 16)
+    ss.attach()
+    series, first, chunks = _stream_inputs(spl, pds, ss.plans, n_blocks, seed=22)
+    _, res = ss.run(first, chunks, n_blocks, warmup=1, on_block=lambda k, f, n, r: (k, r.copy()))
+    for k, recs in res:
+        want = np.concatenate([_oracle_block(ss.plans[j], series[j], k, j) for j in range(3)])
+        say(f"uneven block {k}: {recs.size} candidates")
+        assert np.array_equal(recs, want), k
