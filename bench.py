@@ -103,7 +103,9 @@ def end_to_end_leg(spl, W, pds, args, n_blocks=8, warmup=2, seed=33):
 
     from paper_2606_27262_amd import ranking, streaming
     block_s = max(pd["n_out"] * pd["tsamp"] for pd in pds)
-    ss = streaming.StreamingSearch(spl, pds)
+    ss = streaming.StreamingSearch(spl, pds,
+                                   thresholds=ranking.beam_thresholds(pds, ranking.load_operating_point(
+                                       args.operating_point)))
     ss.attach(tile_cache=None if args.no_autotune else
               (args.tile_cache or os.path.join(tempfile.gettempdir(), "spotlight_tiles.txt")))
     first, chunks, truth = [], [[], []], [[], []]
@@ -389,7 +391,9 @@ def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, arg
         dev = torch.from_numpy(np.ascontiguousarray(r).view(np.int32).reshape(-1, 8).copy()).cuda()
         return ranker.score(spl.snippets(batch, dev)).cpu().numpy()
 
-    kept, surv, lg = ranking.ranker_path(spl, recs, tsamp, nb, score)
+    op = ranking.load_operating_point(args.operating_point)
+    thr = ranking.beam_thresholds(pds, op)
+    kept, surv, lg = ranking.ranker_path(spl, recs, tsamp, nb, score, threshold=thr)
     n_scored = surv.size
     t_rank = time.perf_counter() - t0
     snip_leg = None
@@ -466,7 +470,10 @@ def ranker_leg(spl, pds, plans, batch, blocks, pulses, cands, stats, stream, arg
     return {
         "weights": "trained" if trained else "untrained (initial weights)",
         "plain_path": {**pr, "host_ms": t_plain * 1e3},
-        "ranker_path": {**rr, "scored": int(n_scored), "stage_ms": t_rank * 1e3},
+        "ranker_path": {**rr, "scored": int(n_scored), "stage_ms": t_rank * 1e3,
+                        "logit_thresholds": sorted(set(float(v) for v in thr))},
+        "ranker_path_p05": ranking.recall_and_false_alarms(
+            spl.anti_coincidence(surv[lg >= 0.0], tsamp, nb), pulses, pds) if surv.size else None,
         "ranker_at_plain_false_alarms": matched,
         "snippets": snip_leg,
         # the candidate stage after the search of the same block (serial), or overlapped
@@ -568,7 +575,8 @@ def uneven_leg(spl, W, args, steps=5, warmup=2, seed=4):
                                         zero_dm_rate=0.2)
         blocks.append(x)
         pulses.append(list(spec.pulses))
-    batch = spl.Batch(plans, mode=spl.MODE_PERSISTENT_GRAPH)
+    # the zero-DM bursts light up every trial near their time: 1.6e8 hits per block
+    batch = spl.Batch(plans, mode=spl.MODE_PERSISTENT_GRAPH, hit_capacity=1 << 28)
     batch.attach()
     if not args.no_autotune:
         batch.autotune(blocks, cache_path=args.tile_cache or os.path.join(tempfile.gettempdir(), "spotlight_tiles.txt"))
@@ -602,7 +610,9 @@ def uneven_leg(spl, W, args, steps=5, warmup=2, seed=4):
            "dedisp_ms_per_step": dd_ms / steps, "dedisp_adds_per_s": adds / (dd_ms / steps / 1e3),
            "dedisp_frac_add_peak": adds / (dd_ms / steps / 1e3) / PEAK_ADDS,
            "tiles": {f"{p.info['nchans']}ch": batch.tiles(b) for b, p in ((0, plans[0]), (1, plans[1]))},
-           "candidates": st["n_candidates"], "hits": st["n_hits"], "cand_overflow": st["cand_overflow"]}
+           "candidates": st["n_candidates"], "hits": st["n_hits"], "hit_overflow": st["hit_overflow"],
+           "cand_overflow": st["cand_overflow"]}
+    assert not (st["hit_overflow"] or st["cand_overflow"]), st
     if not args.no_ranker:
         with torch.cuda.stream(s):
             batch.run(blocks, cands, stats, stream=s)
@@ -618,7 +628,8 @@ def uneven_leg(spl, W, args, steps=5, warmup=2, seed=4):
             return ranker.score(spl.snippets(batch, dev)).cpu().numpy()
 
         fp = spl.optimise_plain(recs, tsamp, len(pds))
-        fr, scored, lg = ranking.ranker_path(spl, recs, tsamp, len(pds), score)
+        thr = ranking.beam_thresholds(pds, ranking.load_operating_point(args.operating_point))
+        fr, scored, lg = ranking.ranker_path(spl, recs, tsamp, len(pds), score, threshold=thr)
         out["ranker"] = per_band_comparison(spl, pds, pulses, fp, fr, scored, lg)
     del batch, blocks
     torch.cuda.empty_cache()
@@ -682,6 +693,9 @@ def main():
                     help="beam counts of the growing-batch leg of the c3 run (comma-separated; empty: skip)")
     ap.add_argument("--ranker-weights", default=os.path.join(ROOT, "paper_2606_27262_amd", "data",
                                                              "ranker_weights.npy"))
+    ap.add_argument("--operating-point", default=os.path.join(ROOT, "paper_2606_27262_amd", "data",
+                                                              "ranker_weights_operating_point.json"),
+                    help="per-band logit thresholds of the ranker path (JSON written by train_ranker)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs each GPU's share of beams "
@@ -708,7 +722,10 @@ def main():
     mode = args.mode
     if mode == "auto":
         mode = "plain" if nb == 1 else "graph"
-    batch = spl.Batch(plans, mode=spl.MODE_PERSISTENT_GRAPH if mode == "graph" else spl.MODE_PLAIN_PER_BEAM)
+    # the uneven batch's zero-DM bursts light up every trial near their time (1.6e8 hits
+    # per block): its hit list is sized for them
+    batch = spl.Batch(plans, mode=spl.MODE_PERSISTENT_GRAPH if mode == "graph" else spl.MODE_PLAIN_PER_BEAM,
+                      hit_capacity=(1 << 28) if args.workload == "c4" else 0)
     batch.attach()
     if not args.no_autotune:
         import tempfile
@@ -730,6 +747,9 @@ def main():
         for _ in range(args.warmup):
             batch.run(blocks, cands, stats, stream=stream)
     torch.cuda.synchronize()
+    st0 = spl.stats_dict(stats)
+    if st0["hit_overflow"] or st0["cand_overflow"]:
+        raise SystemExit(f"capacity exceeded in the warm-up runs: {st0}")
     batch.stage_times(reset=True)
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):

@@ -28,8 +28,8 @@ hipError_t launch_wgrad(int mode, const uint16_t *X, int N, int nvalid, int H, i
 hipError_t launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s);
 hipError_t launch_transpose16(const uint16_t *in, int64_t rows, int64_t cols, int64_t ldi, uint16_t *out, int64_t ldo,
                               hipStream_t s);
-hipError_t launch_unpool(const float *dOut, const uint8_t *arg, int N, int H, int W, uint16_t *dZ, uint16_t *dZT,
-                         int64_t ldT, float *dbias, hipStream_t s);
+hipError_t launch_unpool(const float *dOut, const uint8_t *arg, int N, int H, int W, uint16_t *dZ, float *dbias,
+                         hipStream_t s);
 hipError_t launch_head(const float *Hm, const float *b1, const float *f2w, const float *f2b, int N, int Nb,
                        float *logits, const float *labels, float *loss, float *g_f2w, float *g_f2b, float *g_b1,
                        uint16_t *dH, uint16_t *dHT, int64_t ldT, hipStream_t s);

@@ -490,13 +490,44 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, in
     const uint16_t *b1p = b0p + (size_t)16 * ldw;
     if constexpr (MODE == 0) {
         u16x8 a = zero;
+        if constexpr (POOL) {
+            // the workgroup's four 2 x 8 patches form one 2 x 32 strip of an image (W a
+            // multiple of 32): its input window, 2 channels x 4 rows x 34 columns with the
+            // zero padding, is staged in LDS once and every tap is read from there
+            __shared__ uint16_t win[2 * 4 * 34];
+            const int64_t tile0 = (int64_t)blockIdx.x * 4;
+            const int per_row = W >> 3, per_img = (H >> 1) * per_row;
+            const int n0 = (int)(tile0 / per_img);
+            const int rem0 = (int)(tile0 - (int64_t)n0 * per_img);
+            const int hb = 2 * (rem0 / per_row) - 1, wb = 8 * (rem0 % per_row) - 1;
+            for (int i = threadIdx.x; i < 2 * 4 * 34; i += 256) {
+                const int ci = i / 136, r = (i / 34) & 3, c = i % 34;
+                const int hs = hb + r, ws = wb + c;
+                uint16_t v = 0;
+                if (n0 < nvalid && hs >= 0 && hs < H && ws >= 0 && ws < W)
+                    v = X[(((size_t)n0 * 2 + ci) * H + hs) * W + ws];
+                win[i] = v;
+            }
+            __syncthreads();
+            const int base = (h - hb) * 34 + (w - wb);   // the pixel's place in the window
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = kq + j;
-            if (k < 18 && row_ok) {
-                const int t = k >> 1, ci = k & 1;
-                const int hs = h + t / 3 - 1, ws = w + t % 3 - 1;
-                if (hs >= 0 && hs < H && ws >= 0 && ws < W) a[j] = X[(((size_t)n * 2 + ci) * H + hs) * W + ws];
+            for (int j = 0; j < 8; ++j) {
+                const int k = kq + j;
+                if (k < 18) {
+                    const int t = k >> 1, ci = k & 1;
+                    const int ty = (t * 11) >> 5;        // t / 3 for t < 9
+                    a[j] = win[ci * 136 + base + (ty - 1) * 34 + (t - 3 * ty - 1)];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = kq + j;
+                if (k < 18 && row_ok) {
+                    const int t = k >> 1, ci = k & 1;
+                    const int hs = h + t / 3 - 1, ws = w + t % 3 - 1;
+                    if (hs >= 0 && hs < H && ws >= 0 && ws < W) a[j] = X[(((size_t)n * 2 + ci) * H + hs) * W + ws];
+                }
             }
         }
         const u16x8 x0 = *(const u16x8 *)b0p, x1 = *(const u16x8 *)b1p;
@@ -568,19 +599,17 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, in
 }
 
 // ------------------------------------------------------- weight gradient (LDS)
-// part[blockIdx.x][k][co] (FP32 [gridDim.x][K][32]) = sum over the pixels p of the
+// part[blockIdx.x][k][co] (FP32 [gridDim.x][288][32]) = sum over the pixels p of the
 // workgroup's slabs of A[p][k] * dZ[p][co], A the (implicit) im2col of the layer input:
-// k = t*32 + ci (MODE 1, K = 288, NHWC input) or k = t*2 + ci (MODE 0, K = 32 with 18
-// used, NCHW input of 2 channels, images n >= nvalid read as zero).  A slab is 32
-// consecutive pixels (the MFMA K-step); its dZ and the 9 shifted input tiles are staged
-// transposed in LDS ([channel][pixel]) so that MFMA operands are 16-byte LDS reads.
-// Tiles of the 288 x 32 result (9 taps x 2 x 2 of 16 x 16) are spread over the 4 waves.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ X, int N, int nvalid, int H, int W,
+// k = t*32 + ci (32 input channels, NHWC).  A slab is 32 consecutive pixels (the MFMA
+// K-step); its dZ and the 9 shifted input tiles are staged transposed in LDS
+// ([channel][pixel]) so that MFMA operands are 16-byte LDS reads.  Tiles of the 288 x 32
+// result (9 taps x 2 x 2 of 16 x 16) are spread over the 4 waves.
+__global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ X, int N, int H, int W,
                                                const uint16_t *__restrict__ dZ, float *__restrict__ part) {
-    constexpr int kTiles = MODE == 0 ? 4 : 36;           // 16x16 tiles of the K x 32 result
-    constexpr int kPerWave = (kTiles + 3) / 4;
-    constexpr int kRows = MODE == 0 ? 32 : 9 * 32;       // staged A^T rows
+    constexpr int kTiles = 36;                           // 16x16 tiles of the K x 32 result
+    constexpr int kPerWave = kTiles / 4;
+    constexpr int kRows = 9 * 32;                        // staged A^T rows
     constexpr int kLd = 40;                              // LDS row stride (elements), 80 bytes
     __shared__ __align__(16) uint16_t sA[kRows * kLd];
     __shared__ __align__(16) uint16_t sZ[32 * kLd];
@@ -593,15 +622,14 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ X, i
     const int kq = 8 * (lane >> 4);
     for (int64_t sl = blockIdx.x; sl < nslab; sl += gridDim.x) {
         const int64_t p0 = sl * 32;
-        // dZ^T: thread -> (pixel tid/8, channels 4*(tid%8) .. +3)
+        // dZ^T and the nine input tiles: thread -> (pixel tid/8, channels 4*(tid%8) .. +3)
+        const int px = tid >> 3, c4 = (tid & 7) * 4;
         {
-            const int px = tid >> 3, c4 = (tid & 7) * 4;
             const uint64_t v = *(const uint64_t *)(dZ + (p0 + px) * 32 + c4);
 #pragma unroll
             for (int i = 0; i < 4; ++i) sZ[(c4 + i) * kLd + px] = (uint16_t)(v >> (16 * i));
         }
-        if constexpr (MODE == 1) {
-            const int px = tid >> 3, c4 = (tid & 7) * 4;
+        {
             const int64_t p = p0 + px;
             const int n = (int)(p / ((int64_t)H * W));
             const int hw = (int)(p - (int64_t)n * H * W);
@@ -615,31 +643,11 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ X, i
 #pragma unroll
                 for (int i = 0; i < 4; ++i) sA[(t * 32 + c4 + i) * kLd + px] = (uint16_t)(v >> (16 * i));
             }
-        } else {
-            // rows k = t*2 + ci (18 used, 14 zero) x 32 pixels: 1024 entries, 4 per thread
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int idx = tid + 256 * e;
-                const int k = idx >> 5, px = idx & 31;
-                uint16_t v = 0;
-                if (k < 18) {
-                    const int64_t p = p0 + px;
-                    const int n = (int)(p / ((int64_t)H * W));
-                    const int hw = (int)(p - (int64_t)n * H * W);
-                    const int h = hw / W, w = hw - (hw / W) * W;
-                    const int t = k >> 1, ci = k & 1;
-                    const int hs = h + t / 3 - 1, ws = w + t % 3 - 1;
-                    if (n < nvalid && hs >= 0 && hs < H && ws >= 0 && ws < W)
-                        v = X[(((size_t)n * 2 + ci) * H + hs) * W + ws];
-                }
-                sA[k * kLd + px] = v;
-            }
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kPerWave; ++i) {
             const int tile = wave + 4 * i;
-            if (tile >= kTiles) break;
             const int it = tile >> 1, jt = tile & 1;   // A^T row tile (16 rows of k), dZ^T row tile (co)
             const u16x8 a = *(const u16x8 *)(sA + (it * 16 + (lane & 15)) * kLd + kq);
             const u16x8 b = *(const u16x8 *)(sZ + (jt * 16 + (lane & 15)) * kLd + kq);
@@ -652,7 +660,6 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ X, i
 #pragma unroll
     for (int i = 0; i < kPerWave; ++i) {
         const int tile = wave + 4 * i;
-        if (tile >= kTiles) break;
         const int it = tile >> 1, jt = tile & 1;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -662,12 +669,128 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ X, i
     }
 }
 
-// out[i] = sum over parts j of part[j][i], i < n (fixed order: deterministic).
-__global__ void k_sum_parts(const float *__restrict__ part, int nparts, int64_t n, float *__restrict__ out) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        float s = 0.f;
-        for (int j = 0; j < nparts; ++j) s += part[(size_t)j * n + i];
-        out[i] = s;
+// Weight gradient of the first layer (2 input channels, K = 18 used of 32):
+// part[blockIdx.x][k][co] = sum over the pixels p of the workgroup's slabs of
+// A[p][k] * dZ[p][co], k = t*2 + ci.  Each wavefront works alone on slabs of 32
+// consecutive pixels of one image row (W a multiple of 32): the input is NCHW, so the 32
+// values of row k are 32 neighbouring samples of one plane (shifted by the tap), read
+// straight into the LDS row; dZ (NHWC) is transposed into its LDS rows.  No workgroup
+// barrier in the loop: a wavefront's LDS writes and reads execute in order.  The four
+// wavefronts' sums are added in a fixed order at the end.
+__global__ __launch_bounds__(256) void k_wgrad_first(const uint16_t *__restrict__ X, int N, int nvalid, int H,
+                                                     int W, const uint16_t *__restrict__ dZ,
+                                                     float *__restrict__ part) {
+    constexpr int kLd = 40;
+    __shared__ __align__(16) uint16_t sA[4][32 * kLd];
+    __shared__ __align__(16) uint16_t sZ[4][32 * kLd];
+    __shared__ float red[4][4][64][4];
+    const int lane = lane_id(), wave = wave_id();
+    uint16_t *A = sA[wave], *Zt = sZ[wave];
+    for (int i = lane; i < 32 * kLd; i += 64) A[i] = 0;   // rows 18..31 stay zero
+    __builtin_amdgcn_wave_barrier();
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint32_t HW = (uint32_t)(H * W);
+    const uint32_t nslab = (uint32_t)N * HW / 32u;
+    const uint32_t nwaves = gridDim.x * 4u;
+    const int kq = 8 * (lane >> 4);
+    for (uint32_t sl = blockIdx.x * 4u + (uint32_t)wave; sl < nslab; sl += nwaves) {
+        const uint32_t p0 = sl * 32u;
+        const uint32_t n = p0 / HW, rem = p0 - n * HW, h = rem / (uint32_t)W, w0 = rem - h * (uint32_t)W;
+        // dZ^T: lane -> pixel lane/2, channels 16*(lane%2) .. +15
+        {
+            const int px = lane >> 1, c0 = 16 * (lane & 1);
+            const uint4 *src = (const uint4 *)(dZ + ((size_t)p0 + px) * 32 + c0);
+            const uint4 v0 = src[0], v1 = src[1];
+            const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                Zt[(c0 + 2 * i) * kLd + px] = (uint16_t)(w[i] & 0xFFFFu);
+                Zt[(c0 + 2 * i + 1) * kLd + px] = (uint16_t)(w[i] >> 16);
+            }
+        }
+        // A rows k = 2 t + ci: lane -> pixel lane%32 and channel lane/32, all nine taps
+        {
+            const int px = lane & 31, ci = lane >> 5;
+            const bool img_ok = (int)n < nvalid;
+            const uint16_t *plane = X + ((size_t)n * 2 + ci) * HW;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int hs = (int)h + t / 3 - 1, ws = (int)w0 + px + t % 3 - 1;
+                uint16_t v = 0;
+                if (img_ok && hs >= 0 && hs < H && ws >= 0 && ws < W) v = plane[(size_t)hs * W + ws];
+                A[(2 * t + ci) * kLd + px] = v;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const u16x8 a = *(const u16x8 *)(A + (it * 16 + (lane & 15)) * kLd + kq);
+#pragma unroll
+            for (int jt = 0; jt < 2; ++jt) {
+                const u16x8 b = *(const u16x8 *)(Zt + (jt * 16 + (lane & 15)) * kLd + kq);
+                acc[it][jt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                                      __builtin_bit_cast(bf16x8, b), acc[it][jt], 0,
+                                                                      0, 0);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+#pragma unroll
+        for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wave][2 * it + jt][lane][r] = acc[it][jt][r];
+    __syncthreads();
+    if (wave == 0) {
+        float *out = part + (size_t)blockIdx.x * 32 * 32;
+#pragma unroll
+        for (int it = 0; it < 2; ++it)
+#pragma unroll
+            for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int tl = 2 * it + jt;
+                    const float v = ((red[0][tl][lane][r] + red[1][tl][lane][r]) + red[2][tl][lane][r]) +
+                                    red[3][tl][lane][r];
+                    const int k = it * 16 + 4 * (lane >> 4) + r;
+                    out[(size_t)k * 32 + jt * 16 + (lane & 15)] = v;
+                }
+    }
+}
+
+// out[i] = sum over parts j of part[j][i], i < n, in a fixed order (deterministic).
+// Workgroup = 16 wavefronts over 64 consecutive i: wavefront g adds parts g, g+16, g+32,
+// ... (eight loads in flight), then the 16 partial sums of each i are added in order
+// g = 0..15 through the LDS.
+__global__ __launch_bounds__(1024) void k_sum_parts(const float *__restrict__ part, int nparts, int64_t n,
+                                                    float *__restrict__ out) {
+    __shared__ float red[16][64];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    float s = 0.f;
+    if (i < n) {
+        int j = g;
+        for (; j + 16 * 7 < nparts; j += 16 * 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(j + 16 * u) * n + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; j < nparts; j += 16) s += part[(size_t)j * n + i];
+    }
+    red[g][lane] = s;
+    __syncthreads();
+    if (g == 0 && i < n) {
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) t += red[k][lane];
+        out[i] = t;
     }
 }
 
@@ -689,37 +812,73 @@ __global__ void k_transpose16(const uint16_t *__restrict__ in, int64_t rows, int
 }
 
 // Gradient through pool + ReLU: dZ[p][co] = dOut[pooled][co] at the window's arg position,
-// 0 elsewhere; written as BF16 [P][32] and transposed [32][ldT]; bias gradient accumulated.
-__global__ void k_unpool(const float *__restrict__ dOut, const uint8_t *__restrict__ arg, int N, int H, int W,
-                         uint16_t *__restrict__ dZ, uint16_t *__restrict__ dZT, int64_t ldT,
-                         float *__restrict__ dbias) {
-    __shared__ float sb[32];
-    if (threadIdx.x < 32) sb[threadIdx.x] = 0.f;
-    __syncthreads();
-    const int H2 = H / 2, W2 = W / 2;
-    const int64_t total = (int64_t)N * H2 * W2 * 32;
-    float part = 0.f;
-    const int co = threadIdx.x & 31;   // blockDim is a multiple of 32 and stride keeps co fixed
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t q = i >> 5;
-        const int n = (int)(q / ((int64_t)H2 * W2));
-        const int hw = (int)(q - (int64_t)n * H2 * W2);
-        const int h2 = hw / W2, w2 = hw - h2 * W2;
-        const int a = arg[i];
-        const float g = dOut[i];
-        if (a != 255) part += g;
+// 0 elsewhere (BF16 [P][32]); the bias gradient (the sum of dOut over windows with a
+// chosen element) is accumulated.  Thread = one pooled pixel and 8 channels: two 16-byte
+// loads of dOut, one 8-byte load of the decisions, four 16-byte stores (one per window
+// position).  Bias partial sums are reduced over the wavefront's lanes of the same
+// channel group, then over the workgroup in the LDS, then added to dbias.
+__global__ __launch_bounds__(256) void k_unpool(const float *__restrict__ dOut, const uint8_t *__restrict__ arg,
+                                                int N, int H, int W, uint16_t *__restrict__ dZ,
+                                                float *__restrict__ dbias) {
+    __shared__ float sb[4][32];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int H2 = H >> 1, W2 = W >> 1;
+    const uint32_t per_img = (uint32_t)(H2 * W2);
+    const uint32_t nq = (uint32_t)N * per_img;          // pooled pixels (< 2^31)
+    const int grp = lane & 3;                           // channels 8 grp .. 8 grp + 7
+    float part[8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int h = 2 * h2 + (j >> 1), w = 2 * w2 + (j & 1);
-            const int64_t p = ((int64_t)n * H + h) * W + w;
-            const uint16_t v = (a == j) ? f2bf(g) : (uint16_t)0;
-            dZ[p * 32 + co] = v;
-            if (dZT) dZT[(int64_t)co * ldT + p] = v;
+    for (int c = 0; c < 8; ++c) part[c] = 0.f;
+    const uint32_t stride = gridDim.x * 64u;
+    for (uint32_t q = blockIdx.x * 64u + (uint32_t)(threadIdx.x >> 2); q < nq; q += stride) {
+        const float4 g0 = *(const float4 *)(dOut + (size_t)q * 32 + 8 * grp);
+        const float4 g1 = *(const float4 *)(dOut + (size_t)q * 32 + 8 * grp + 4);
+        const uint2 av = *(const uint2 *)(arg + (size_t)q * 32 + 8 * grp);
+        const float g[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+        uint32_t a[8];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            a[c] = (av.x >> (8 * c)) & 0xFFu;
+            a[c + 4] = (av.y >> (8 * c)) & 0xFFu;
+        }
+        uint16_t b[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            b[c] = f2bf(g[c]);
+            if (a[c] != 255u) part[c] += g[c];
+        }
+        const uint32_t n = q / per_img, hw = q - n * per_img, h2 = hw / (uint32_t)W2, w2 = hw - h2 * (uint32_t)W2;
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            uint32_t w[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t lo = a[2 * c] == j ? b[2 * c] : 0u;
+                const uint32_t hi = a[2 * c + 1] == j ? b[2 * c + 1] : 0u;
+                w[c] = lo | (hi << 16);
+            }
+            const size_t p = ((size_t)n * H + 2 * h2 + (j >> 1)) * W + 2 * w2 + (j & 1);
+            *(uint4 *)(dZ + p * 32 + 8 * grp) = make_uint4(w[0], w[1], w[2], w[3]);
         }
     }
-    atomicAdd(&sb[co], part);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        float v = part[c];
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        part[c] = v;
+    }
+    if (lane < 4) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) sb[wave][8 * lane + c] = part[c];
+    }
     __syncthreads();
-    if (threadIdx.x < 32) atomicAdd(&dbias[threadIdx.x], sb[threadIdx.x]);
+    if (threadIdx.x < 32) {
+        const float t = sb[0][threadIdx.x] + sb[1][threadIdx.x] + sb[2][threadIdx.x] + sb[3][threadIdx.x];
+        atomicAdd(&dbias[threadIdx.x], t);
+    }
 }
 
 // --------------------------------------------------- fully connected head (VALU)
@@ -901,6 +1060,7 @@ hipError_t launch_conv_pool(int mode, const uint16_t *X, int N, int nvalid, int 
     const int64_t P = (int64_t)N * H * W;
     // whole 2 x 8 patches, four per workgroup
     if (P <= 0 || (ldw & 7) || (H & 1) || (W & 7) || (P & 63) || (mode != 0 && mode != 1)) return hipErrorInvalidValue;
+    if (mode == 0 && (W & 31)) return hipErrorInvalidValue;   // a workgroup's strip stays in one image row
     const dim3 grid((unsigned)(P / 64));
     float *nc = nullptr;
     if (mode == 0)
@@ -917,14 +1077,18 @@ hipError_t launch_wgrad(int mode, const uint16_t *X, int N, int nvalid, int H, i
                         int nparts, hipStream_t s) {
     const int64_t P = (int64_t)N * H * W;
     if (P <= 0 || (P & 31) || nparts < 1) return hipErrorInvalidValue;
-    if (mode == 0) hipLaunchKernelGGL(k_wgrad<0>, dim3(nparts), dim3(256), 0, s, X, N, nvalid, H, W, dZ, part);
-    else hipLaunchKernelGGL(k_wgrad<1>, dim3(nparts), dim3(256), 0, s, X, N, nvalid, H, W, dZ, part);
+    if (mode == 0) {
+        if ((W & 31) || (int64_t)N * H * W >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_wgrad_first, dim3(nparts), dim3(256), 0, s, X, N, nvalid, H, W, dZ, part);
+    } else {
+        hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(256), 0, s, X, N, H, W, dZ, part);
+    }
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_parts, dim3(grid_1d(n)), dim3(256), 0, s, part, nparts, n, out);
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, s, part, nparts, n, out);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -938,10 +1102,12 @@ hipError_t launch_transpose16(const uint16_t *in, int64_t rows, int64_t cols, in
     return hipSuccess;
 }
 
-hipError_t launch_unpool(const float *dOut, const uint8_t *arg, int N, int H, int W, uint16_t *dZ, uint16_t *dZT,
-                         int64_t ldT, float *dbias, hipStream_t s) {
-    hipLaunchKernelGGL(k_unpool, dim3(grid_1d((int64_t)N * (H / 2) * (W / 2) * 32)), dim3(256), 0, s, dOut, arg, N, H,
-                       W, dZ, dZT, ldT, dbias);
+hipError_t launch_unpool(const float *dOut, const uint8_t *arg, int N, int H, int W, uint16_t *dZ, float *dbias,
+                         hipStream_t s) {
+    const int64_t nq = (int64_t)N * (H / 2) * (W / 2);
+    if (nq <= 0 || nq >= ((int64_t)1 << 31) || (H & 1) || (W & 1)) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)std::min<int64_t>((nq + 63) / 64, 2048);
+    hipLaunchKernelGGL(k_unpool, dim3(grid), dim3(256), 0, s, dOut, arg, N, H, W, dZ, dbias);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }

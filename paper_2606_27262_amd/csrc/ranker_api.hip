@@ -260,7 +260,7 @@ spl_status backward(spl_ranker *R, const uint16_t *snip, int n, const float *lab
     for (int k = kLayers - 1; k >= 0; --k) {
         const int64_t P = R->P(k);
         const uint16_t *in = k == 0 ? snip : R->at<uint16_t>(R->off_X[k - 1]);
-        RK_TRY(launch_unpool(dX, R->at<uint8_t>(R->off_arg[k]), nb, kH[k], kW[k], dZ, nullptr, 0, G + po.cb[k], s));
+        RK_TRY(launch_unpool(dX, R->at<uint8_t>(R->off_arg[k]), nb, kH[k], kW[k], dZ, G + po.cb[k], s));
         const int parts = (int)std::min<int64_t>(kWgradParts, P / 32);
         RK_TRY(launch_wgrad(k == 0 ? 0 : 1, in, nb, k == 0 ? n : nb, kH[k], kW[k], dZ, part, parts, s));
         RK_TRY(launch_sum_parts(part, parts, (int64_t)kKp[k] * kCout, gc + R->gc_w[k], s));

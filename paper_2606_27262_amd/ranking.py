@@ -42,14 +42,36 @@ DISPERSION_CONSTANT = 4148.8064239   # MHz^2 pc^-1 cm^3 s, Eq. (1)
 RANKER_OPT = {"min_pts": 1, "snr_min": 0.0, "coinc_min_beams": 1 << 30}
 
 
+def band_key(pd) -> str:
+    """Name of a plan's band: its edge frequencies and channel count, e.g. 550-750MHz/4096ch."""
+    half = abs(pd["foff"]) / 2.0
+    f = [pd["fch1"], pd["fch1"] + (pd["nchans"] - 1) * pd["foff"]]
+    return f"{min(f) - half:.0f}-{max(f) + half:.0f}MHz/{pd['nchans']}ch"
+
+
+def load_operating_point(path):
+    """Per-band logit thresholds of the ranker path ({band_key: threshold}), or {}."""
+    import json
+    import os
+    if not path or not os.path.exists(path):
+        return {}
+    return {k: float(v) for k, v in json.load(open(path))["logit_threshold"].items()}
+
+
+def beam_thresholds(pds, operating_point, default=0.0):
+    """Logit threshold of each beam: its band's operating point, else `default` (0: the
+    probability 0.5 the paper's classifier keeps)."""
+    return np.array([operating_point.get(band_key(pd), default) for pd in pds], np.float32)
+
+
 def _by_key(c: np.ndarray) -> np.ndarray:
     return c[np.lexsort((c["t_sample"], c["dm_index"], c["beam"]))] if c.size else c
 
 
 def ranker_path(spl, cands, tsamp, n_beams, score_fn, threshold=0.0, max_scored=None):
     """Optimisation with RANKER_OPT, the CNN (score_fn: records -> logits), then the
-    anti-coincidence filter on the records whose logit is >= threshold.  Returns
-    (final records, scored records, their logits).
+    anti-coincidence filter on the records whose logit is >= threshold (a number, or one
+    per beam).  Returns (final records, scored records, their logits).
 
     The plain path is the fallback: when the ranker has no weights (score_fn raises
     SPL_E_NO_WEIGHTS) every beam takes it; when the representatives number more than
@@ -75,7 +97,11 @@ def ranker_path(spl, cands, tsamp, n_beams, score_fn, threshold=0.0, max_scored=
             if e.status != spl.SPL_E_NO_WEIGHTS:
                 raise
             return spl.optimise_plain(cands, tsamp, n_beams), scored[:0], lg
-    kept = scored[lg >= threshold] if scored.size else scored
+    thr = np.asarray(threshold, np.float32)
+    if scored.size:
+        kept = scored[lg >= (thr[scored["beam"]] if thr.ndim else thr)]
+    else:
+        kept = scored
     if plain_beams.any():
         raw = cands[plain_beams[cands["beam"]]]
         pf = spl.optimise_plain(raw, tsamp, n_beams, coinc_min_beams=1 << 30)
@@ -201,23 +227,39 @@ def burst_batch(pds, seed: int, n_pulses: int = 8, dm_lo: float = 20.0, dm_hi: f
 class Stage:
     """Search + optimisation + optional ranker for a fixed batch of plans."""
 
-    def __init__(self, spl, pds, cand_capacity=1 << 20, mode=0, fine_keep=None):
+    def __init__(self, spl, pds, cand_capacity=1 << 20, mode=0, fine_keep=None, hit_capacity=0):
         import torch
         self.spl, self.pds = spl, pds
         self.fine_keep = fine_keep   # None: DM-time plane on the search grid; else fine-DM plane
         self.plans = [spl.Plan.from_dict(pd) for pd in pds]
         self.n_in = [p.info["n_in"] for p in self.plans]
-        self.batch = spl.Batch(self.plans, mode=mode)
+        self.mode = mode
+        self.batch = spl.Batch(self.plans, mode=mode, hit_capacity=hit_capacity)
         self.cands = spl.new_candidates(cand_capacity)
         self.stats = torch.zeros(spl.STATS_WORDS, dtype=torch.int64, device="cuda")
         self.tsamp = np.array([pd["tsamp"] for pd in pds], np.float64)
+        self.regrown = 0
 
     def search(self, blocks):
-        """Search numpy blocks [nch][n_in] (uploaded) or device blocks [nch][pitch]."""
+        """Search numpy blocks [nch][n_in] (uploaded) or device blocks [nch][pitch].  A run
+        whose hits or candidates exceed the capacities (the statistics carry the true
+        counts) is searched again with capacities that hold them."""
         import torch
         dev = [x if isinstance(x, torch.Tensor) else self.spl.upload_block(x) for x in blocks]
         self.batch.run(dev, self.cands, self.stats)
         torch.cuda.synchronize()
+        st = self.spl.stats_dict(self.stats)
+        if st["hit_overflow"] or st["cand_overflow"]:
+            def room(n):
+                return 1 << max(20, int(math.ceil(math.log2(max(2, 1.25 * n)))))
+            self.batch = self.spl.Batch(self.plans, mode=self.mode, hit_capacity=room(st["n_hits"]))
+            if st["cand_overflow"]:
+                self.cands = self.spl.new_candidates(room(st["n_candidates"]))
+            self.regrown += 1
+            self.batch.run(dev, self.cands, self.stats)
+            torch.cuda.synchronize()
+            st = self.spl.stats_dict(self.stats)
+            assert not (st["hit_overflow"] or st["cand_overflow"]), st
         self._dev_blocks = dev   # the snippets read these blocks
         return self.spl.candidates_to_numpy(self.cands, self.stats)
 
@@ -246,7 +288,7 @@ def mine(spl, pds, n_batches, seed0, neg_ratio=1.0, log=print, fine_keep=None, p
     device: make the blocks there (see burst_batch).  Also returns the number of bursts
     injected and of bursts with at least one positive."""
     import torch
-    st = Stage(spl, pds, fine_keep=fine_keep, mode=mode)
+    st = Stage(spl, pds, fine_keep=fine_keep, mode=mode, hit_capacity=1 << 26)
     xs, ys = [], []
     n_bursts = n_found = 0
     t_log = time.time()
@@ -286,6 +328,8 @@ def mine(spl, pds, n_batches, seed0, neg_ratio=1.0, log=print, fine_keep=None, p
                 f"(gen {t1 - t0:.2f}s, search+snip {time.time() - t1:.2f}s)")
     x = torch.cat(xs) if xs else torch.zeros((0, 2, 64, 256), dtype=torch.int16, device="cuda")
     y = np.concatenate(ys) if ys else np.zeros(0, np.float32)
+    if st.regrown:
+        log(f"capacities regrown {st.regrown} times")
     return x, y, n_bursts, n_found
 
 
@@ -327,7 +371,7 @@ def evaluate(spl, pds, ranker, n_batches, seed0, log=print, fine_keep=None, devi
     """Recall and false alarms of the plain path and of the ranker path on fresh blocks
     (made on `device` when given, see burst_batch)."""
     import torch
-    st = Stage(spl, pds, fine_keep=fine_keep, mode=mode)
+    st = Stage(spl, pds, fine_keep=fine_keep, mode=mode, hit_capacity=1 << 26)
     plain_all, rank_all, pulses_all, cand_all, scored_all, logit_all = [], [], [], 0, [], []
     t_rank = 0.0
     for i in range(n_batches):

@@ -44,7 +44,8 @@ from . import ranking
 
 
 class StreamingSearch:
-    def __init__(self, spl, pds, ranker=None, mode=None, cand_capacity=1 << 20, max_scored=16384):
+    def __init__(self, spl, pds, ranker=None, mode=None, cand_capacity=1 << 20, max_scored=16384, hit_capacity=0,
+                 thresholds=0.0):
         import torch
         self.spl, self.pds, self.ranker = spl, pds, ranker
         self.nb = len(pds)
@@ -56,7 +57,7 @@ class StreamingSearch:
             plans.append(cache[key])
         self.plans = plans
         mode = spl.MODE_PERSISTENT_GRAPH if mode is None else mode
-        self.batches = [spl.Batch(plans, mode=mode) for _ in range(3)]
+        self.batches = [spl.Batch(plans, mode=mode, hit_capacity=hit_capacity) for _ in range(3)]
         self.cands = [spl.new_candidates(cand_capacity) for _ in range(3)]
         self.stats = [torch.zeros(spl.STATS_WORDS, dtype=torch.int64, device="cuda") for _ in range(3)]
         self.dev = [[torch.empty((p.info["nchans"], (p.info["n_in"] + 255) // 256 * 256), dtype=torch.uint8,
@@ -80,6 +81,7 @@ class StreamingSearch:
         self.copy_hint = min(cand_capacity, 1 << 17)
         self.copied = [0, 0, 0]
         self.tsamp = np.array([pd["tsamp"] for pd in pds], np.float64)
+        self.thresholds = thresholds   # the ranker path's logit threshold (a number or one per beam)
 
     def attach(self, tile_cache=None):
         for b, dev in zip(self.batches, self.dev):
@@ -124,6 +126,13 @@ class StreamingSearch:
         total."""
         import torch
         n = int(self.h_stats[slot][1])
+        ov = int(self.h_stats[slot][6])
+        if ov & 0xFFFFFFFF:
+            raise RuntimeError(f"a block had {int(self.h_stats[slot][0])} boxcar hits, more than the batch's hit "
+                               "capacity: create the stream with a larger hit_capacity")
+        if ov >> 32:
+            raise RuntimeError(f"a block had {n} candidates, more than the candidate capacity: create the stream "
+                               "with a larger cand_capacity")
         cap = self.h_cands[slot].shape[0]
         m = min(n, cap)
         c = self.copied[slot]
@@ -155,7 +164,8 @@ class StreamingSearch:
             self.rank_stream.synchronize()
             return self.h_logits[:k].numpy().copy()
 
-        final, _, _ = ranking.ranker_path(spl, recs, self.tsamp, self.nb, score, max_scored=self.max_scored)
+        final, _, _ = ranking.ranker_path(spl, recs, self.tsamp, self.nb, score, threshold=self.thresholds,
+                                          max_scored=self.max_scored)
         return final, n
 
     def run(self, first_set, chunk_sets, n_blocks, warmup=2, on_block=None, timing=None):

@@ -50,6 +50,9 @@ def main(argv=None):
     ap.add_argument("--fine-keep", type=float, default=None,
                     help="train and evaluate on fine-DM planes (DM* +- the offset keeping this S/N fraction)")
     ap.add_argument("--json", default=None)
+    ap.add_argument("--op-out", default=None, metavar="JSON",
+                    help="write the per-band operating point (the logit threshold at the plain path's false-alarm "
+                         "count on the evaluation blocks); default: next to --out")
     ap.add_argument("--eval-only", default=None, metavar="WEIGHTS",
                     help="skip training: evaluate these weights (.npy) against the plain path")
     a = ap.parse_args(argv)
@@ -114,6 +117,16 @@ def main(argv=None):
         log(f"{name}: plain recall {res['plain']['recall']:.3f} ({res['plain']['false_alarms']} false alarms), "
             f"ranker recall {res['ranker']['recall']:.3f} ({res['ranker']['false_alarms']}), at the plain "
             f"path's false alarms {m['recall'] if m else float('nan'):.3f}")
+    if not a.eval_only:
+        op_path = a.op_out or os.path.splitext(a.out)[0] + "_operating_point.json"
+        op = {"source": "held-out evaluation of train_ranker (fresh seeds): the lowest logit threshold whose final "
+                        "list holds no more unmatched candidates than the plain path's",
+              "logit_threshold": {name: b["eval"]["ranker_at_plain_false_alarms"]["threshold_logit"]
+                                  for name, b in out["bands"].items()
+                                  if b.get("eval", {}).get("ranker_at_plain_false_alarms")}}
+        with open(op_path, "w") as f:
+            f.write(json.dumps(op, indent=1) + "\n")
+        out["operating_point"] = op_path
     out["wall_s"] = round(time.time() - t_start, 1)
     line = json.dumps(out)
     print(line, flush=True)

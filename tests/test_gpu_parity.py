@@ -409,3 +409,30 @@ def test_autotune_keeps_results_and_caches(spl, tmp_path):
     # a second batch reuses the cached choice
     b2 = spl.Batch([p])
     assert b2.autotune([tb[0]], cache_path=str(cache))[0] == tiles[0]
+
+
+def test_graph_batch_follows_new_block_pointers(spl):
+    """A graph-mode batch given other block tensors on each run (new device pointers, as
+    a caller that allocates blocks per run does): every run equals the plain mode's on
+    the same blocks."""
+    plans = [make_plan(spl, 0, 0, 0, None, 0, plan_dict=W.plan_c1()) for _ in range(2)]
+    n_in = plans[0].info["n_in"]
+    gb = spl.Batch(plans, mode=spl.MODE_PERSISTENT_GRAPH)
+    eb = spl.Batch(plans, mode=spl.MODE_PLAIN_PER_BEAM)
+    cg, ce = spl.new_candidates(1 << 14), spl.new_candidates(1 << 14)
+    sg = torch.zeros(spl.STATS_WORDS, dtype=torch.int64, device="cuda")
+    se = torch.zeros(spl.STATS_WORDS, dtype=torch.int64, device="cuda")
+    keep = []
+    for rep in range(4):
+        bufs = []
+        for b in range(2):
+            _, x = W.c1_block(n_in, seed=300 + 10 * rep + b, beam=b)
+            bufs.append(spl.upload_block(x[:, :n_in]))
+        keep.append(bufs)   # earlier tensors stay allocated: every run sees new addresses
+        gb.run(bufs, cg, sg)
+        eb.run(bufs, ce, se)
+        torch.cuda.synchronize()
+        a = spl.candidates_to_numpy(cg, sg)
+        e = spl.candidates_to_numpy(ce, se)
+        say("new pointers", rep, a.size)
+        assert a.size > 0 and np.array_equal(a, e)
