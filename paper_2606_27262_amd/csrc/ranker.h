@@ -25,7 +25,10 @@ hipError_t launch_conv(int mode, const uint16_t *X, int N, int nvalid, int H, in
 // Weight gradient partials part[nparts][K][32] (mode 0: K = 32, first layer; 1: K = 288).
 hipError_t launch_wgrad(int mode, const uint16_t *X, int N, int nvalid, int H, int W, const uint16_t *dZ, float *part,
                         int nparts, hipStream_t s);
-hipError_t launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s);
+// Deterministic sum of nparts partial arrays of n floats; above 256 parts in two passes
+// through tmp (room for kSumPartsMaxGroups * n floats).
+constexpr int kSumPartsMaxGroups = 160;
+hipError_t launch_sum_parts(const float *part, int nparts, int64_t n, float *out, float *tmp, hipStream_t s);
 hipError_t launch_transpose16(const uint16_t *in, int64_t rows, int64_t cols, int64_t ldi, uint16_t *out, int64_t ldo,
                               hipStream_t s);
 hipError_t launch_unpool(const float *dOut, const uint8_t *arg, int N, int H, int W, uint16_t *dZ, float *dbias,

@@ -449,59 +449,71 @@ __global__ __launch_bounds__(256) void k_gemm(const uint16_t *__restrict__ A, in
 // MODE 1: 32 input channels, NHWC, src = (h + ky - 1, w + kx - 1)   (forward).
 // MODE 2: 32 input channels, NHWC, src = (h - ky + 1, w - kx + 1)   (input gradient: the
 //         input is dZ and Wt the weights repacked as [ci][t*32 + co]).
-// Workgroup = 4 wavefronts x 16 pixels; each wavefront computes all 32 columns.
-// POOL (forward only): a wavefront's 16 rows are a 2 x 8 pixel patch (rows 2ph, 2ph+1,
-// columns 8c .. 8c+7) instead of 16 consecutive pixels, so the result holds four whole
-// 2 x 2 windows: lane l keeps rows 4(l/16) .. +3, i.e. two horizontal pairs of one image
-// row, and lane l ^ 32 the pairs below them.  Bias, ReLU and the max pool (with the
-// window position of the first maximum, 255 when no element is positive) then run in
-// registers and only the pooled BF16 activation and the decision bytes are written.
+// Workgroup = 4 wavefronts; each wavefront computes kConvTiles tiles of 16 pixels x all 32
+// columns, so a tap's weight operands are loaded once for 64 pixels.  Tile T (of the
+// wavefront's T0 .. T0+3) is pixels 16T .. 16T+15, or with POOL (forward only) a 2 x 8
+// pixel patch (rows 2ph, 2ph+1, columns 8c .. 8c+7; patches row-major per image), so the
+// result holds four whole 2 x 2 windows: lane l keeps rows 4(l/16) .. +3, i.e. two
+// horizontal pairs of one image row, and lane l ^ 32 the pairs below them.  Bias, ReLU
+// and the max pool (with the window position of the first maximum, 255 when no element
+// is positive) then run in registers and only the pooled BF16 activation and the decision
+// bytes are written.
+constexpr int kConvTiles = 4;
 template <int MODE, bool POOL>
 __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, int N, int nvalid, int H, int W,
                                               const uint16_t *__restrict__ Wt, int ldw, float *__restrict__ C,
                                               const float *__restrict__ bias, uint16_t *__restrict__ pooled,
                                               uint8_t *__restrict__ arg) {
+    constexpr int MT = kConvTiles;
     const int lane = lane_id(), wave = wave_id();
     const int64_t P = (int64_t)N * H * W;
-    const int64_t m_base = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int64_t t0 = ((int64_t)blockIdx.x * 4 + wave) * MT;
     const int kq = 8 * (lane >> 4);
-    int64_t p;
-    int n, h, w;
-    if constexpr (POOL) {
-        const int64_t tile = m_base >> 4;                 // 2 x 8 patches, row-major per image
-        const int per_row = W >> 3, per_img = (H >> 1) * per_row;
-        n = (int)(tile / per_img);
-        const int rem = (int)(tile - (int64_t)n * per_img);
-        const int r = lane & 15;
-        h = 2 * (rem / per_row) + (r >> 3);
-        w = 8 * (rem % per_row) + (r & 7);
-        p = ((int64_t)n * H + h) * W + w;
-    } else {
-        p = m_base + (lane & 15);
-        n = (int)(p / ((int64_t)H * W));
-        const int hw = (int)(p - (int64_t)n * H * W);
-        h = hw / W;
-        w = hw - h * W;
+    const int per_row = W >> 3, per_img = (H >> 1) * per_row;
+    int n[MT], h[MT], w[MT];
+    bool row_ok[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int64_t tile = t0 + mt;
+        int64_t p;
+        if constexpr (POOL) {
+            n[mt] = (int)(tile / per_img);
+            const int rem = (int)(tile - (int64_t)n[mt] * per_img);
+            const int r = lane & 15;
+            h[mt] = 2 * (rem / per_row) + (r >> 3);
+            w[mt] = 8 * (rem % per_row) + (r & 7);
+            p = ((int64_t)n[mt] * H + h[mt]) * W + w[mt];
+        } else {
+            p = tile * 16 + (lane & 15);
+            n[mt] = (int)(p / ((int64_t)H * W));
+            const int hw = (int)(p - (int64_t)n[mt] * H * W);
+            h[mt] = hw / W;
+            w[mt] = hw - h[mt] * W;
+        }
+        row_ok[mt] = p < P && n[mt] < nvalid;
     }
-    const bool row_ok = p < P && n < nvalid;
-    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    f32x4 acc0[MT], acc1[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc0[mt] = acc1[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
     const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
     const uint16_t *b0p = Wt + (size_t)(lane & 15) * ldw + kq;
     const uint16_t *b1p = b0p + (size_t)16 * ldw;
     if constexpr (MODE == 0) {
-        u16x8 a = zero;
+        u16x8 a[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) a[mt] = zero;
         if constexpr (POOL) {
-            // the workgroup's four 2 x 8 patches form one 2 x 32 strip of an image (W a
-            // multiple of 32): its input window, 2 channels x 4 rows x 34 columns with the
-            // zero padding, is staged in LDS once and every tap is read from there
-            __shared__ uint16_t win[2 * 4 * 34];
-            const int64_t tile0 = (int64_t)blockIdx.x * 4;
-            const int per_row = W >> 3, per_img = (H >> 1) * per_row;
-            const int n0 = (int)(tile0 / per_img);
-            const int rem0 = (int)(tile0 - (int64_t)n0 * per_img);
+            // the workgroup's 16 patches form one 2 x 128 strip of an image (W a multiple of
+            // 128): its input window, 2 channels x 4 rows x 130 columns with the zero
+            // padding, is staged in LDS once and every tap is read from there
+            constexpr int kWc = 8 * 4 * MT + 2;
+            __shared__ uint16_t win[2 * 4 * kWc];
+            const int64_t tw = (int64_t)blockIdx.x * 4 * MT;
+            const int n0 = (int)(tw / per_img);
+            const int rem0 = (int)(tw - (int64_t)n0 * per_img);
             const int hb = 2 * (rem0 / per_row) - 1, wb = 8 * (rem0 % per_row) - 1;
-            for (int i = threadIdx.x; i < 2 * 4 * 34; i += 256) {
-                const int ci = i / 136, r = (i / 34) & 3, c = i % 34;
+            for (int i = threadIdx.x; i < 2 * 4 * kWc; i += 256) {
+                const int ci = i / (4 * kWc), r = (i / kWc) & 3, c = i % kWc;
                 const int hs = hb + r, ws = wb + c;
                 uint16_t v = 0;
                 if (n0 < nvalid && hs >= 0 && hs < H && ws >= 0 && ws < W)
@@ -509,91 +521,109 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, in
                 win[i] = v;
             }
             __syncthreads();
-            const int base = (h - hb) * 34 + (w - wb);   // the pixel's place in the window
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = kq + j;
-                if (k < 18) {
-                    const int t = k >> 1, ci = k & 1;
-                    const int ty = (t * 11) >> 5;        // t / 3 for t < 9
-                    a[j] = win[ci * 136 + base + (ty - 1) * 34 + (t - 3 * ty - 1)];
+            for (int mt = 0; mt < MT; ++mt) {
+                const int base = (h[mt] - hb) * kWc + (w[mt] - wb);   // the pixel's place in the window
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int k = kq + j;
+                    if (k < 18) {
+                        const int t = k >> 1, ci = k & 1;
+                        const int ty = (t * 11) >> 5;        // t / 3 for t < 9
+                        a[mt][j] = win[ci * 4 * kWc + base + (ty - 1) * kWc + (t - 3 * ty - 1)];
+                    }
                 }
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = kq + j;
-                if (k < 18 && row_ok) {
-                    const int t = k >> 1, ci = k & 1;
-                    const int hs = h + t / 3 - 1, ws = w + t % 3 - 1;
-                    if (hs >= 0 && hs < H && ws >= 0 && ws < W) a[j] = X[(((size_t)n * 2 + ci) * H + hs) * W + ws];
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int k = kq + j;
+                    if (k < 18 && row_ok[mt]) {
+                        const int t = k >> 1, ci = k & 1;
+                        const int hs = h[mt] + t / 3 - 1, ws = w[mt] + t % 3 - 1;
+                        if (hs >= 0 && hs < H && ws >= 0 && ws < W)
+                            a[mt][j] = X[(((size_t)n[mt] * 2 + ci) * H + hs) * W + ws];
+                    }
                 }
-            }
         }
         const u16x8 x0 = *(const u16x8 *)b0p, x1 = *(const u16x8 *)b1p;
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, x0),
-                                                       acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, x1),
-                                                       acc1, 0, 0, 0);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            acc0[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[mt]),
+                                                               __builtin_bit_cast(bf16x8, x0), acc0[mt], 0, 0, 0);
+            acc1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[mt]),
+                                                               __builtin_bit_cast(bf16x8, x1), acc1[mt], 0, 0, 0);
+        }
     } else {
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int ky = t / 3, kx = t % 3;
-            const int hs = MODE == 1 ? h + ky - 1 : h - ky + 1;
-            const int ws = MODE == 1 ? w + kx - 1 : w - kx + 1;
-            u16x8 a = zero;
-            if (row_ok && hs >= 0 && hs < H && ws >= 0 && ws < W)
-                a = *(const u16x8 *)(X + (((size_t)n * H + hs) * W + ws) * 32 + kq);
             const u16x8 x0 = *(const u16x8 *)(b0p + 32 * t), x1 = *(const u16x8 *)(b1p + 32 * t);
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                           __builtin_bit_cast(bf16x8, x0), acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                           __builtin_bit_cast(bf16x8, x1), acc1, 0, 0, 0);
-        }
-    }
-    if constexpr (POOL) {
-        // window k (0, 1) of this lane: own pair i = 2k, 2k+1 (window positions 0, 1),
-        // the partner lane's pair below it (positions 2, 3); positions tried in order
-        const int g = lane >> 4, co = lane & 15;
-        const int64_t tile = m_base >> 4;
-        const int per_row = W >> 3, per_img = (H >> 1) * per_row;
-        const int nn = (int)(tile / per_img);
-        const int rem = (int)(tile - (int64_t)nn * per_img);
-        const int ph = rem / per_row, pw0 = 4 * (rem % per_row) + 2 * (g & 1);
-        const int H2 = H >> 1, W2 = W >> 1;
+            u16x8 a[MT];
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-            const f32x4 a = half ? acc1 : acc0;
-            const float b = bias[co + 16 * half];
-            float below[4];
+            for (int mt = 0; mt < MT; ++mt) {
+                const int hs = MODE == 1 ? h[mt] + ky - 1 : h[mt] - ky + 1;
+                const int ws = MODE == 1 ? w[mt] + kx - 1 : w[mt] - kx + 1;
+                a[mt] = zero;
+                if (row_ok[mt] && hs >= 0 && hs < H && ws >= 0 && ws < W)
+                    a[mt] = *(const u16x8 *)(X + (((size_t)n[mt] * H + hs) * W + ws) * 32 + kq);
+            }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) below[i] = __shfl_xor(a[i], 32);
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const float z[4] = {a[2 * k] + b, a[2 * k + 1] + b, below[2 * k] + b, below[2 * k + 1] + b};
-                float best = 0.f;
-                int ba = 255;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (z[j] > best) {
-                        best = z[j];
-                        ba = j;
-                    }
-                }
-                if (g < 2 && tile * 16 < P) {
-                    const size_t o = (((size_t)nn * H2 + ph) * W2 + pw0 + k) * 32 + co + 16 * half;
-                    pooled[o] = f2bf(best);
-                    arg[o] = (uint8_t)ba;
-                }
+            for (int mt = 0; mt < MT; ++mt) {
+                acc0[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[mt]),
+                                                                   __builtin_bit_cast(bf16x8, x0), acc0[mt], 0, 0, 0);
+                acc1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[mt]),
+                                                                   __builtin_bit_cast(bf16x8, x1), acc1[mt], 0, 0, 0);
             }
         }
-    } else {
+    }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t m = m_base + 4 * (lane >> 4) + i;
-            if (m >= P) continue;
-            C[m * 32 + (lane & 15)] = acc0[i];
-            C[m * 32 + 16 + (lane & 15)] = acc1[i];
+    for (int mt = 0; mt < MT; ++mt) {
+        const int64_t tile = t0 + mt;
+        if constexpr (POOL) {
+            // window k (0, 1) of this lane: own pair i = 2k, 2k+1 (window positions 0, 1),
+            // the partner lane's pair below it (positions 2, 3); positions tried in order
+            const int g = lane >> 4, co = lane & 15;
+            const int nn = (int)(tile / per_img);
+            const int rem = (int)(tile - (int64_t)nn * per_img);
+            const int ph = rem / per_row, pw0 = 4 * (rem % per_row) + 2 * (g & 1);
+            const int H2 = H >> 1, W2 = W >> 1;
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const f32x4 av = half ? acc1[mt] : acc0[mt];
+                const float b = bias[co + 16 * half];
+                float below[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) below[i] = __shfl_xor(av[i], 32);
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const float z[4] = {av[2 * k] + b, av[2 * k + 1] + b, below[2 * k] + b, below[2 * k + 1] + b};
+                    float best = 0.f;
+                    int ba = 255;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if (z[j] > best) {
+                            best = z[j];
+                            ba = j;
+                        }
+                    }
+                    if (g < 2 && tile * 16 < P) {
+                        const size_t o = (((size_t)nn * H2 + ph) * W2 + pw0 + k) * 32 + co + 16 * half;
+                        pooled[o] = f2bf(best);
+                        arg[o] = (uint8_t)ba;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t m = tile * 16 + 4 * (lane >> 4) + i;
+                if (m >= P) continue;
+                C[m * 32 + (lane & 15)] = acc0[mt][i];
+                C[m * 32 + 16 + (lane & 15)] = acc1[mt][i];
+            }
         }
     }
 }
@@ -614,37 +644,39 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ X, i
     __shared__ __align__(16) uint16_t sA[kRows * kLd];
     __shared__ __align__(16) uint16_t sZ[32 * kLd];
     const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-    const int64_t P = (int64_t)N * H * W;
-    const int64_t nslab = P / 32;   // P is a multiple of 32
+    const uint32_t HW = (uint32_t)(H * W);
+    const uint32_t nslab = (uint32_t)N * HW / 32u;       // N H W is a multiple of 32 (< 2^31)
     f32x4 acc[kPerWave];
 #pragma unroll
     for (int i = 0; i < kPerWave; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int kq = 8 * (lane >> 4);
-    for (int64_t sl = blockIdx.x; sl < nslab; sl += gridDim.x) {
-        const int64_t p0 = sl * 32;
-        // dZ^T and the nine input tiles: thread -> (pixel tid/8, channels 4*(tid%8) .. +3)
-        const int px = tid >> 3, c4 = (tid & 7) * 4;
-        {
-            const uint64_t v = *(const uint64_t *)(dZ + (p0 + px) * 32 + c4);
+    // thread -> (pixel tid/8, channels 4*(tid%8) .. +3) of a slab; the next slab's dZ and
+    // nine input tiles are loaded into registers while the current one is multiplied
+    const int px = tid >> 3, c4 = (tid & 7) * 4;
+    uint64_t vz = 0, va[9];
+    auto load = [&](uint32_t sl) {
+        const uint32_t p = sl * 32u + (uint32_t)px;
+        vz = *(const uint64_t *)(dZ + (size_t)p * 32 + c4);
+        const uint32_t n = p / HW, hw = p - n * HW, h = hw / (uint32_t)W, w = hw - h * (uint32_t)W;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) sZ[(c4 + i) * kLd + px] = (uint16_t)(v >> (16 * i));
+        for (int t = 0; t < 9; ++t) {
+            const int hs = (int)h + t / 3 - 1, ws = (int)w + t % 3 - 1;
+            va[t] = 0;
+            if (hs >= 0 && hs < H && ws >= 0 && ws < W)
+                va[t] = *(const uint64_t *)(X + (((size_t)n * H + hs) * W + ws) * 32 + c4);
         }
-        {
-            const int64_t p = p0 + px;
-            const int n = (int)(p / ((int64_t)H * W));
-            const int hw = (int)(p - (int64_t)n * H * W);
-            const int h = hw / W, w = hw - (hw / W) * W;
+    };
+    uint32_t sl = blockIdx.x;
+    if (sl < nslab) load(sl);
+    for (; sl < nslab; sl += gridDim.x) {
 #pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int hs = h + t / 3 - 1, ws = w + t % 3 - 1;
-                uint64_t v = 0;
-                if (hs >= 0 && hs < H && ws >= 0 && ws < W)
-                    v = *(const uint64_t *)(X + (((size_t)n * H + hs) * W + ws) * 32 + c4);
+        for (int i = 0; i < 4; ++i) sZ[(c4 + i) * kLd + px] = (uint16_t)(vz >> (16 * i));
 #pragma unroll
-                for (int i = 0; i < 4; ++i) sA[(t * 32 + c4 + i) * kLd + px] = (uint16_t)(v >> (16 * i));
-            }
-        }
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sA[(t * 32 + c4 + i) * kLd + px] = (uint16_t)(va[t] >> (16 * i));
         __syncthreads();
+        if (sl + gridDim.x < nslab) load(sl + gridDim.x);
 #pragma unroll
         for (int i = 0; i < kPerWave; ++i) {
             const int tile = wave + 4 * i;
@@ -681,11 +713,9 @@ __global__ __launch_bounds__(256) void k_wgrad_first(const uint16_t *__restrict_
                                                      int W, const uint16_t *__restrict__ dZ,
                                                      float *__restrict__ part) {
     constexpr int kLd = 40;
-    __shared__ __align__(16) uint16_t sA[4][32 * kLd];
-    __shared__ __align__(16) uint16_t sZ[4][32 * kLd];
-    __shared__ float red[4][4][64][4];
+    __shared__ __align__(16) uint16_t lds[2 * 4 * 32 * kLd];   // per wave: A rows, then dZ^T rows
     const int lane = lane_id(), wave = wave_id();
-    uint16_t *A = sA[wave], *Zt = sZ[wave];
+    uint16_t *A = lds + wave * 2 * 32 * kLd, *Zt = A + 32 * kLd;
     for (int i = lane; i < 32 * kLd; i += 64) A[i] = 0;   // rows 18..31 stay zero
     __builtin_amdgcn_wave_barrier();
     f32x4 acc[2][2];
@@ -697,35 +727,40 @@ __global__ __launch_bounds__(256) void k_wgrad_first(const uint16_t *__restrict_
     const uint32_t nslab = (uint32_t)N * HW / 32u;
     const uint32_t nwaves = gridDim.x * 4u;
     const int kq = 8 * (lane >> 4);
-    for (uint32_t sl = blockIdx.x * 4u + (uint32_t)wave; sl < nslab; sl += nwaves) {
+    // lane -> dZ: pixel lane/2, channels 16*(lane%2) .. +15; A: pixel lane%32, channel
+    // lane/32, all nine taps.  The next slab is loaded into registers while the current
+    // one is multiplied.
+    const int zpx = lane >> 1, zc0 = 16 * (lane & 1);
+    const int apx = lane & 31, aci = lane >> 5;
+    uint4 z0, z1;
+    uint16_t av[9];
+    auto load = [&](uint32_t sl) {
         const uint32_t p0 = sl * 32u;
+        const uint4 *src = (const uint4 *)(dZ + ((size_t)p0 + zpx) * 32 + zc0);
+        z0 = src[0];
+        z1 = src[1];
         const uint32_t n = p0 / HW, rem = p0 - n * HW, h = rem / (uint32_t)W, w0 = rem - h * (uint32_t)W;
-        // dZ^T: lane -> pixel lane/2, channels 16*(lane%2) .. +15
-        {
-            const int px = lane >> 1, c0 = 16 * (lane & 1);
-            const uint4 *src = (const uint4 *)(dZ + ((size_t)p0 + px) * 32 + c0);
-            const uint4 v0 = src[0], v1 = src[1];
-            const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        const bool img_ok = (int)n < nvalid;
+        const uint16_t *plane = X + ((size_t)n * 2 + aci) * HW;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                Zt[(c0 + 2 * i) * kLd + px] = (uint16_t)(w[i] & 0xFFFFu);
-                Zt[(c0 + 2 * i + 1) * kLd + px] = (uint16_t)(w[i] >> 16);
-            }
+        for (int t = 0; t < 9; ++t) {
+            const int hs = (int)h + t / 3 - 1, ws = (int)w0 + apx + t % 3 - 1;
+            av[t] = (img_ok && hs >= 0 && hs < H && ws >= 0 && ws < W) ? plane[(size_t)hs * W + ws] : (uint16_t)0;
         }
-        // A rows k = 2 t + ci: lane -> pixel lane%32 and channel lane/32, all nine taps
-        {
-            const int px = lane & 31, ci = lane >> 5;
-            const bool img_ok = (int)n < nvalid;
-            const uint16_t *plane = X + ((size_t)n * 2 + ci) * HW;
+    };
+    uint32_t sl = blockIdx.x * 4u + (uint32_t)wave;
+    if (sl < nslab) load(sl);
+    for (; sl < nslab; sl += nwaves) {
+        const uint32_t w[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
 #pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int hs = (int)h + t / 3 - 1, ws = (int)w0 + px + t % 3 - 1;
-                uint16_t v = 0;
-                if (img_ok && hs >= 0 && hs < H && ws >= 0 && ws < W) v = plane[(size_t)hs * W + ws];
-                A[(2 * t + ci) * kLd + px] = v;
-            }
+        for (int i = 0; i < 8; ++i) {
+            Zt[(zc0 + 2 * i) * kLd + zpx] = (uint16_t)(w[i] & 0xFFFFu);
+            Zt[(zc0 + 2 * i + 1) * kLd + zpx] = (uint16_t)(w[i] >> 16);
         }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) A[(2 * t + aci) * kLd + apx] = av[t];
         __builtin_amdgcn_wave_barrier();
+        if (sl + nwaves < nslab) load(sl + nwaves);
 #pragma unroll
         for (int it = 0; it < 2; ++it) {
             const u16x8 a = *(const u16x8 *)(A + (it * 16 + (lane & 15)) * kLd + kq);
@@ -739,50 +774,53 @@ __global__ __launch_bounds__(256) void k_wgrad_first(const uint16_t *__restrict_
         }
         __builtin_amdgcn_wave_barrier();
     }
+    // the four wavefronts' sums, added in a fixed order (the staging area is reused)
+    __syncthreads();
+    float *red = (float *)lds;   // [4 waves][4 tiles][4][64]: 16 KiB of the 20 KiB
 #pragma unroll
     for (int it = 0; it < 2; ++it)
 #pragma unroll
         for (int jt = 0; jt < 2; ++jt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) red[wave][2 * it + jt][lane][r] = acc[it][jt][r];
+            for (int r = 0; r < 4; ++r) red[((wave * 4 + 2 * it + jt) * 4 + r) * 64 + lane] = acc[it][jt][r];
     __syncthreads();
     if (wave == 0) {
         float *out = part + (size_t)blockIdx.x * 32 * 32;
 #pragma unroll
-        for (int it = 0; it < 2; ++it)
+        for (int tl = 0; tl < 4; ++tl)
 #pragma unroll
-            for (int jt = 0; jt < 2; ++jt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int tl = 2 * it + jt;
-                    const float v = ((red[0][tl][lane][r] + red[1][tl][lane][r]) + red[2][tl][lane][r]) +
-                                    red[3][tl][lane][r];
-                    const int k = it * 16 + 4 * (lane >> 4) + r;
-                    out[(size_t)k * 32 + jt * 16 + (lane & 15)] = v;
-                }
+            for (int r = 0; r < 4; ++r) {
+                const float v = ((red[((0 * 4 + tl) * 4 + r) * 64 + lane] + red[((1 * 4 + tl) * 4 + r) * 64 + lane]) +
+                                 red[((2 * 4 + tl) * 4 + r) * 64 + lane]) + red[((3 * 4 + tl) * 4 + r) * 64 + lane];
+                const int it = tl >> 1, jt = tl & 1;
+                const int k = it * 16 + 4 * (lane >> 4) + r;
+                out[(size_t)k * 32 + jt * 16 + (lane & 15)] = v;
+            }
     }
 }
 
-// out[i] = sum over parts j of part[j][i], i < n, in a fixed order (deterministic).
-// Workgroup = 16 wavefronts over 64 consecutive i: wavefront g adds parts g, g+16, g+32,
-// ... (eight loads in flight), then the 16 partial sums of each i are added in order
-// g = 0..15 through the LDS.
-__global__ __launch_bounds__(1024) void k_sum_parts(const float *__restrict__ part, int nparts, int64_t n,
+// out[g][i] = sum over the parts j of group g (j in [g*group, min((g+1)*group, nparts)),
+// g = blockIdx.y) of part[j][i], i < n, in a fixed order (deterministic).  Workgroup =
+// 16 wavefronts over 64 consecutive i: wavefront w adds the group's parts w, w+16, ...
+// (eight loads in flight), then the 16 partial sums of each i are added in order through
+// the LDS.
+__global__ __launch_bounds__(1024) void k_sum_parts(const float *__restrict__ part, int nparts, int group, int64_t n,
                                                     float *__restrict__ out) {
     __shared__ float red[16][64];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const int j0 = blockIdx.y * group, j1 = min(nparts, j0 + group);
     float s = 0.f;
     if (i < n) {
-        int j = g;
-        for (; j + 16 * 7 < nparts; j += 16 * 8) {
+        int j = j0 + g;
+        for (; j + 16 * 7 < j1; j += 16 * 8) {
             float v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(j + 16 * u) * n + i];
 #pragma unroll
             for (int u = 0; u < 8; ++u) s += v[u];
         }
-        for (; j < nparts; j += 16) s += part[(size_t)j * n + i];
+        for (; j < j1; j += 16) s += part[(size_t)j * n + i];
     }
     red[g][lane] = s;
     __syncthreads();
@@ -790,7 +828,7 @@ __global__ __launch_bounds__(1024) void k_sum_parts(const float *__restrict__ pa
         float t = 0.f;
 #pragma unroll
         for (int k = 0; k < 16; ++k) t += red[k][lane];
-        out[i] = t;
+        out[(size_t)blockIdx.y * n + i] = t;
     }
 }
 
@@ -884,17 +922,20 @@ __global__ __launch_bounds__(256) void k_unpool(const float *__restrict__ dOut, 
 // --------------------------------------------------- fully connected head (VALU)
 // H [Nb][64] FP32 (GEMM output), b1, f2w, f2b -> logits; with labels: mean BCE loss,
 // gradients of f2w, f2b, b1 and dH (BF16 [Nb][64] and transposed [64][ldT]).  One
-// workgroup of 256 threads; rows n >= N (batch padding) produce zero gradients.
-__global__ __launch_bounds__(256) void k_head(const float *__restrict__ Hm, const float *__restrict__ b1,
-                                              const float *__restrict__ f2w, const float *__restrict__ f2b, int N,
-                                              int Nb, float *__restrict__ logits, const float *__restrict__ labels,
-                                              float *__restrict__ loss, float *__restrict__ g_f2w,
-                                              float *__restrict__ g_f2b, float *__restrict__ g_b1,
-                                              uint16_t *__restrict__ dH, uint16_t *__restrict__ dHT, int64_t ldT) {
+// workgroup of 1024 threads; rows n >= N (batch padding) produce zero gradients.  Sums
+// over the candidates run in a fixed order: per hidden unit j, 16 threads add every 16th
+// candidate and their partial sums are added in order.
+__global__ __launch_bounds__(1024) void k_head(const float *__restrict__ Hm, const float *__restrict__ b1,
+                                               const float *__restrict__ f2w, const float *__restrict__ f2b, int N,
+                                               int Nb, float *__restrict__ logits, const float *__restrict__ labels,
+                                               float *__restrict__ loss, float *__restrict__ g_f2w,
+                                               float *__restrict__ g_f2b, float *__restrict__ g_b1,
+                                               uint16_t *__restrict__ dH, uint16_t *__restrict__ dHT, int64_t ldT) {
     __shared__ float zl[1024];
     __shared__ float dl[1024];
+    __shared__ float pw[16][64], pb[16][64];
     const int tid = threadIdx.x;
-    for (int n = tid; n < Nb; n += 256) {
+    for (int n = tid; n < Nb; n += 1024) {
         float z = 0.f;
         if (n < N) {
             z = f2b[0];
@@ -908,7 +949,7 @@ __global__ __launch_bounds__(256) void k_head(const float *__restrict__ Hm, cons
     }
     if (!labels) return;
     __syncthreads();
-    for (int n = tid; n < Nb; n += 256) {
+    for (int n = tid; n < Nb; n += 1024) {
         float g = 0.f, l = 0.f;
         if (n < N) {
             const float z = zl[n], y = labels[n];
@@ -919,28 +960,38 @@ __global__ __launch_bounds__(256) void k_head(const float *__restrict__ Hm, cons
         zl[n] = l;
     }
     __syncthreads();
-    if (tid == 0) {
-        float s = 0.f, sg = 0.f;
-        for (int n = 0; n < N; ++n) {
-            s += zl[n];
-            sg += dl[n];
-        }
-        loss[0] = s / (float)N;
-        g_f2b[0] = sg;
-    }
-    if (tid < 64) {
-        const int j = tid;
+    {
+        const int j = tid & 63, q = tid >> 6;
         float gw = 0.f, gb = 0.f;
-        for (int n = 0; n < N; ++n) {
+        for (int n = q; n < N; n += 16) {
             const float pre = Hm[(size_t)n * 64 + j] + b1[j];
-            const float h = fmaxf(pre, 0.f);
-            gw += dl[n] * h;
+            gw += dl[n] * fmaxf(pre, 0.f);
             gb += pre > 0.f ? dl[n] * f2w[j] : 0.f;
         }
-        g_f2w[j] = gw;
-        g_b1[j] = gb;
+        pw[q][j] = gw;
+        pb[q][j] = gb;
     }
-    for (int i = tid; i < Nb * 64; i += 256) {
+    if (tid == 1023) {   // the loss and the output bias gradient: one thread, candidates in order
+        float sl = 0.f, sg = 0.f;
+        for (int n = 0; n < N; ++n) {
+            sl += zl[n];
+            sg += dl[n];
+        }
+        loss[0] = sl / (float)N;
+        g_f2b[0] = sg;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        float gw = 0.f, gb = 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            gw += pw[q][tid];
+            gb += pb[q][tid];
+        }
+        g_f2w[tid] = gw;
+        g_b1[tid] = gb;
+    }
+    for (int i = tid; i < Nb * 64; i += 1024) {
         const int n = i >> 6, j = i & 63;
         float g = 0.f;
         if (n < N) {
@@ -1041,7 +1092,7 @@ hipError_t launch_conv(int mode, const uint16_t *X, int N, int nvalid, int H, in
                        float *C, hipStream_t s) {
     const int64_t P = (int64_t)N * H * W;
     if (P <= 0 || (ldw & 7)) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((P + 63) / 64));
+    const dim3 grid((unsigned)((P + 64 * kConvTiles - 1) / (64 * kConvTiles)));
     float *nb = nullptr;
     uint16_t *np = nullptr;
     uint8_t *na = nullptr;
@@ -1058,10 +1109,11 @@ hipError_t launch_conv(int mode, const uint16_t *X, int N, int nvalid, int H, in
 hipError_t launch_conv_pool(int mode, const uint16_t *X, int N, int nvalid, int H, int W, const uint16_t *Wt, int ldw,
                             const float *bias, uint16_t *pooled, uint8_t *arg, hipStream_t s) {
     const int64_t P = (int64_t)N * H * W;
-    // whole 2 x 8 patches, four per workgroup
-    if (P <= 0 || (ldw & 7) || (H & 1) || (W & 7) || (P & 63) || (mode != 0 && mode != 1)) return hipErrorInvalidValue;
-    if (mode == 0 && (W & 31)) return hipErrorInvalidValue;   // a workgroup's strip stays in one image row
-    const dim3 grid((unsigned)(P / 64));
+    // whole 2 x 8 patches, 4 x kConvTiles per workgroup
+    if (P <= 0 || (ldw & 7) || (H & 1) || (W & 7) || (P % (64 * kConvTiles)) || (mode != 0 && mode != 1))
+        return hipErrorInvalidValue;
+    if (mode == 0 && (W % (32 * kConvTiles))) return hipErrorInvalidValue;   // a workgroup's strip stays in one row
+    const dim3 grid((unsigned)(P / (64 * kConvTiles)));
     float *nc = nullptr;
     if (mode == 0)
         hipLaunchKernelGGL((k_conv<0, true>), grid, dim3(256), 0, s, X, N, nvalid, H, W, Wt, ldw, nc, bias, pooled,
@@ -1087,8 +1139,19 @@ hipError_t launch_wgrad(int mode, const uint16_t *X, int N, int nvalid, int H, i
     return hipSuccess;
 }
 
-hipError_t launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, s, part, nparts, n, out);
+hipError_t launch_sum_parts(const float *part, int nparts, int64_t n, float *out, float *tmp, hipStream_t s) {
+    const unsigned gx = (unsigned)((n + 63) / 64);
+    if (nparts <= 256) {
+        hipLaunchKernelGGL(k_sum_parts, dim3(gx), dim3(1024), 0, s, part, nparts, nparts, n, out);
+        SPL_HIP_LAUNCH_CHECK();
+        return hipSuccess;
+    }
+    // two passes: groups of 128 parts into tmp [groups][n], then the groups
+    const int groups = (nparts + 127) / 128;
+    if (groups > kSumPartsMaxGroups) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sum_parts, dim3(gx, (unsigned)groups), dim3(1024), 0, s, part, nparts, 128, n, tmp);
+    SPL_HIP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_parts, dim3(gx), dim3(1024), 0, s, (const float *)tmp, groups, groups, n, out);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1116,7 +1179,7 @@ hipError_t launch_head(const float *Hm, const float *b1, const float *f2w, const
                        float *logits, const float *labels, float *loss, float *g_f2w, float *g_f2b, float *g_b1,
                        uint16_t *dH, uint16_t *dHT, int64_t ldT, hipStream_t s) {
     if (Nb > 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_head, dim3(1), dim3(256), 0, s, Hm, b1, f2w, f2b, N, Nb, logits, labels, loss, g_f2w, g_f2b,
+    hipLaunchKernelGGL(k_head, dim3(1), dim3(1024), 0, s, Hm, b1, f2w, f2b, N, Nb, logits, labels, loss, g_f2w, g_f2b,
                        g_b1, dH, dHT, ldT);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;

@@ -57,7 +57,10 @@ constexpr int kW[kLayers] = {256, 128, 64, 32};
 constexpr int kCin[kLayers] = {2, 32, 32, 32};
 constexpr int kKp[kLayers] = {32, 288, 288, 288};
 constexpr int kFcIn = 2048, kFcHidden = 64;
-constexpr int kWgradParts = 512;   // workgroups (and partial sums) of a weight-gradient pass
+// workgroups (and partial sums) of a weight-gradient pass: 32-channel layers use up to
+// kWgradParts, the first layer (a 32 x 32 result) up to kWgradPartsFirst in the same buffer
+constexpr int kWgradParts = 2048;
+constexpr int kWgradPartsFirst = kWgradParts * 9;
 
 // Offsets of the parameters in their fixed order.
 struct ParamOffsets {
@@ -103,7 +106,7 @@ struct spl_ranker {
     // per-pass buffers
     size_t off_X[kLayers] = {}, off_arg[kLayers] = {};
     size_t off_Hm = 0, off_logits = 0, off_dH = 0, off_dHT = 0, off_X4T = 0, off_dX = 0;
-    size_t off_dZ = 0, off_part = 0;
+    size_t off_dZ = 0, off_part = 0, off_part2 = 0;
     std::vector<int32_t> pack_idx, gc_idx;
 
     template <class T>
@@ -204,6 +207,7 @@ void layout(spl_ranker *R) {
     R->off_dX = take((size_t)max_dx * 4);
     R->off_dZ = take((size_t)max_dz * 2);
     R->off_part = take((size_t)kWgradParts * 288 * kCout * 4);
+    R->off_part2 = take((size_t)kSumPartsMaxGroups * 288 * kCout * 4);
     R->ws_bytes = align256(off);
 }
 
@@ -261,9 +265,12 @@ spl_status backward(spl_ranker *R, const uint16_t *snip, int n, const float *lab
         const int64_t P = R->P(k);
         const uint16_t *in = k == 0 ? snip : R->at<uint16_t>(R->off_X[k - 1]);
         RK_TRY(launch_unpool(dX, R->at<uint8_t>(R->off_arg[k]), nb, kH[k], kW[k], dZ, G + po.cb[k], s));
-        const int parts = (int)std::min<int64_t>(kWgradParts, P / 32);
+        // first layer: about 16 slabs of 32 pixels per wavefront; the others: one
+        // workgroup per slab up to kWgradParts
+        const int parts = (int)std::max<int64_t>(
+            1, std::min<int64_t>(k == 0 ? kWgradPartsFirst : kWgradParts, k == 0 ? P / 32 / 64 : P / 32));
         RK_TRY(launch_wgrad(k == 0 ? 0 : 1, in, nb, k == 0 ? n : nb, kH[k], kW[k], dZ, part, parts, s));
-        RK_TRY(launch_sum_parts(part, parts, (int64_t)kKp[k] * kCout, gc + R->gc_w[k], s));
+        RK_TRY(launch_sum_parts(part, parts, (int64_t)kKp[k] * kCout, gc + R->gc_w[k], R->at<float>(R->off_part2), s));
         if (k > 0) RK_TRY(launch_conv(2, dZ, nb, nb, kH[k], kW[k], packed + R->pk_wd[k], 288, dX, s));
     }
     RK_TRY(launch_scatter_idx(gc, R->at<int32_t>(R->off_gc_idx), R->n_gc, G, s));
