@@ -85,11 +85,14 @@ def test_random_windows_match_oracle(spl, name, mode):
     assert np.any(got != block)
 
 
-def test_full_size_beam_sampled_channels(spl):
+FULL_GROUPS = 8
+
+
+@pytest.fixture(scope="module")
+def full_size(spl):
     """Ten bursts of the 4096-channel, 16384-sample workload (DM 50-1800, FWHM 1-64,
     S/N 8-50) injected into one quantised noise block of 26305 samples per channel in
-    SAMPLE mode: the oracle recomputes 32 sampled channels, and every byte outside the
-    windows is unchanged."""
+    SAMPLE mode on the GPU, once for the tests below."""
     plan = W.plan_c2()
     n_in = 26305
     rng = np.random.default_rng(31)
@@ -101,18 +104,36 @@ def test_full_size_beam_sampled_channels(spl):
     q = inj.synthetic_quantiser()
     say(f"inject full size: {sig.shape} values")
     got = _gpu_inject(spl, block, n_in, t_start, sig, words, q, inj.SAMPLE)
-    chans = np.sort(rng.choice(plan["nchans"], 32, replace=False))
-    want = inj.inject(block[chans], n_in, t_start[:, chans], sig[:, chans], words[:, chans], q, inj.SAMPLE)
-    assert np.array_equal(got[chans], want)
+    return {"plan": plan, "n_in": n_in, "block": block, "t_start": t_start, "sig": sig, "words": words, "q": q,
+            "got": got}
+
+
+@pytest.mark.parametrize("group", range(FULL_GROUPS))
+def test_full_size_beam_every_channel(spl, full_size, group):
+    """Channels 512 g .. 512 g + 511 of the full-size injection equal the oracle's, byte for
+    byte (the eight groups together cover all 4096 channels)."""
+    f = full_size
+    nch = f["plan"]["nchans"]
+    chans = np.arange(group * nch // FULL_GROUPS, (group + 1) * nch // FULL_GROUPS)
+    want = inj.inject(f["block"][chans], f["n_in"], f["t_start"][:, chans], f["sig"][:, chans],
+                      f["words"][:, chans], f["q"], inj.SAMPLE)
+    bad = np.argwhere(f["got"][chans] != want)
+    assert bad.size == 0, (group, bad[:5])
+
+
+def test_full_size_beam_outside_windows(spl, full_size):
+    """Every byte outside the windows is unchanged, and a positive signal only raises a
+    sample."""
+    f = full_size
+    block, got, t_start, sig, n_in = f["block"], f["got"], f["t_start"], f["sig"], f["n_in"]
     covered = np.zeros(block.shape, bool)
     for w in range(sig.shape[0]):
-        for c in range(plan["nchans"]):
+        for c in range(block.shape[0]):
             a = max(0, int(t_start[w, c]))
             b = min(n_in, int(t_start[w, c]) + sig.shape[2])
             if b > a:
                 covered[c, a:b] = True
     assert np.array_equal(got[~covered], block[~covered])
-    # a positive signal only raises a sample
     assert np.all(got >= block) and np.count_nonzero(got != block) > 0
 
 
