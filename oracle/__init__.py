@@ -20,7 +20,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# SPL_ORACLE_LIBRARY names another build of oracle.c (the sanitizer test's)
+_LIB_PATH = os.environ.get("SPL_ORACLE_LIBRARY") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 # Candidate record, field for field the 32-byte record of the search output.
@@ -37,6 +38,15 @@ def build(force: bool = True) -> str:
                                "-fPIC", "-shared", "-std=c11", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def build_sanitized(out: str) -> str:
+    """Compile oracle.c with clang's AddressSanitizer and UndefinedBehaviorSanitizer
+    (no OpenMP) into `out`, for runs with clang's ASan runtime preloaded."""
+    subprocess.check_call(["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-fno-omit-frame-pointer",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-ffp-contract=off", "-fPIC", "-shared", "-std=c11", _SRC, "-o", out, "-lm"])
+    return out
 
 
 def _load():

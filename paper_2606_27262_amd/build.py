@@ -54,5 +54,48 @@ def build(jobs: int = 8) -> str:
     return LIB
 
 
+def build_host_sanitized(out_dir: str, jobs: int = 8) -> str:
+    """The library with its host-only sources (the C ABI, plan and layout code, tiling,
+    autotuner cache, ranker host code, plain path, plan generator) built with
+    AddressSanitizer and UndefinedBehaviorSanitizer on the host side, linked with the
+    ordinary objects of the kernel sources (built by build() if absent), into
+    out_dir/libspotlight_hostsan.so.  Load it with SPL_LIBRARY and clang's ASan runtime
+    preloaded."""
+    os.makedirs(out_dir, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+    # device code (the static scratch array of the C ABI) is compiled as in build()
+    flags = [f"--offload-arch={ARCH}", "-O1", "-g", "-std=c++17", "-fPIC", "-ffp-contract=off",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC, *san]
+
+    def has_kernels(src):
+        with open(src) as f:
+            return "__global__" in f.read()
+
+    srcs = sources()
+    kernel_objs = [os.path.join(BUILD_DIR, os.path.basename(s) + ".o") for s in srcs if has_kernels(s)]
+    if not all(os.path.exists(o) for o in kernel_objs):
+        build(jobs)
+
+    def one(src):
+        obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+        lang = ["-x", "hip"] if src.endswith(".cpp") else []
+        r = subprocess.run([HIPCC, *flags, *lang, "-c", src, "-o", obj], capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError(f"hipcc (host, sanitized) failed on {src}")
+        return obj
+
+    with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        objs = list(ex.map(one, [s for s in srcs if not has_kernels(s)]))
+    lib = os.path.join(out_dir, "libspotlight_hostsan.so")
+    r = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *san, "-o", lib, *objs, *kernel_objs],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("link of the sanitized host library failed")
+    return lib
+
+
 if __name__ == "__main__":
     print(build())

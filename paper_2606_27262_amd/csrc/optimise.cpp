@@ -45,7 +45,10 @@ std::vector<int> dbscan(const std::vector<Pt> &pts, double eps, int min_pts) {
     if (n == 0) return label;
     // grid of cell size eps; neighbours are searched in the 5x5 surrounding cells, a
     // margin that covers every rounding of the cell index
-    auto key = [](long long cx, long long cy) { return (cx << 32) ^ (cy & 0xffffffffLL); };
+    // (cell indices can be negative: the shift is done on their two's-complement bits)
+    auto key = [](long long cx, long long cy) {
+        return (long long)(((unsigned long long)cx << 32) ^ ((unsigned long long)cy & 0xffffffffULL));
+    };
     std::unordered_map<long long, std::vector<int>> grid;
     grid.reserve(n * 2);
     std::vector<long long> cxs(n), cys(n);

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libspotlight.so")
+# SPL_LIBRARY names another build of the library (the host-sanitizer test's)
+LIB_PATH = os.environ.get("SPL_LIBRARY") or os.path.join(_HERE, "libspotlight.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2606_27262_amd.build.build() "
                       "(or __graft_entry__.build()) before using the search")
