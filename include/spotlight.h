@@ -219,8 +219,14 @@ typedef struct spl_batch spl_batch;
  */
 spl_status spl_batch_create(const spl_plan *const *plans, int32_t n_beams,
                             const spl_batch_opts *opts, spl_batch **out);
-/* Device workspace bytes the batch needs (plan tables + scratch). */
-spl_status spl_batch_workspace_size(const spl_batch *batch, size_t *bytes);
+/*
+ * Device workspace of the batch, one allocation of *persistent + *scratch bytes: the
+ * first *persistent bytes hold the plan tables, work items and beam descriptors
+ * (written by spl_batch_set_workspace, read by every run); the *scratch bytes after
+ * them hold each run's intermediates (DM transforms, moments, thresholds, hit lists,
+ * peak-filter state, run counters), overwritten by every run.
+ */
+spl_status spl_batch_workspace_size(const spl_batch *batch, size_t *persistent, size_t *scratch);
 /*
  * Attach a caller-owned device workspace of at least the size above (256-byte
  * aligned) and upload the plan tables into it (synchronous).  Must be called

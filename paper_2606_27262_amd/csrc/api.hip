@@ -47,7 +47,7 @@ static spl_status fail(spl_status st, const char *fmt, ...) {
 spl_status spl_internal_fail(spl_status st, const char *msg) { return fail(st, "%s", msg); }
 
 extern "C" const char *spl_last_error(void) { return g_err.c_str(); }
-extern "C" int32_t spl_version(void) { return 100; }
+extern "C" int32_t spl_version(void) { return 200; }
 
 // --------------------------------------------------------------------- plans
 static constexpr double kDispersionConstant = 4148.8064239;  // MHz^2 pc^-1 cm^3 s
@@ -270,6 +270,7 @@ struct spl_batch {
     std::vector<size_t> beam_lds;          // per beam (plain per-beam launches)
     // workspace
     size_t ws_bytes = 0, ws_given = 0;
+    size_t ws_persistent = 0;   // the plan tables, work items and beam descriptors at the start
     char *ws = nullptr;
     size_t off_beams = 0, off_items = 0;
     std::vector<size_t> off_X, off_S, off_mu, off_sigma, off_T;   // per beam
@@ -507,6 +508,7 @@ static spl_status build_layout(spl_batch *B) {
         L.off_dms = take((size_t)p.ndm * sizeof(double));
         L.off_delays = take(p.delays.size() * sizeof(int32_t));
     }
+    B->ws_persistent = align_up(off, 256);   // everything below is per-run scratch
     B->off_X.assign(nb, 0);
     B->off_S.assign(nb, 0);
     B->off_mu.assign(nb, 0);
@@ -608,9 +610,10 @@ extern "C" spl_status spl_batch_create(const spl_plan *const *plans, int32_t n_b
     return SPL_OK;
 }
 
-extern "C" spl_status spl_batch_workspace_size(const spl_batch *B, size_t *bytes) {
-    if (!B || !bytes) return fail(SPL_E_INVALID_ARG, "NULL argument");
-    *bytes = B->ws_bytes;
+extern "C" spl_status spl_batch_workspace_size(const spl_batch *B, size_t *persistent, size_t *scratch) {
+    if (!B || !persistent || !scratch) return fail(SPL_E_INVALID_ARG, "NULL argument");
+    *persistent = B->ws_persistent;
+    *scratch = B->ws_bytes - B->ws_persistent;
     return SPL_OK;
 }
 

@@ -112,7 +112,7 @@ _sig("spl_plan_destroy", [_P], None)
 _sig("spl_plan_smearing_ranges", [ctypes.POINTER(_Band), ctypes.POINTER(_SmearingOpts), _P, _I32,
                                   ctypes.POINTER(_I32)])
 _sig("spl_batch_create", [ctypes.POINTER(_P), _I32, ctypes.POINTER(_BatchOpts), ctypes.POINTER(_P)])
-_sig("spl_batch_workspace_size", [_P, ctypes.POINTER(_SZ)])
+_sig("spl_batch_workspace_size", [_P, ctypes.POINTER(_SZ), ctypes.POINTER(_SZ)])
 _sig("spl_batch_set_workspace", [_P, _P, _SZ])
 _sig("spl_batch_run", [_P, ctypes.POINTER(_P), ctypes.POINTER(_I64), _P, _I64, _P, _P])
 _sig("spl_batch_dm_transform", [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_I64)])
@@ -276,10 +276,14 @@ class Batch:
         self.ws = None
         self._stream = None
 
+    def workspace_parts(self) -> tuple:
+        """(persistent, scratch) bytes of the device workspace (see spl_batch_workspace_size)."""
+        p, s = _SZ(), _SZ()
+        _check(_lib.spl_batch_workspace_size(self._h, ctypes.byref(p), ctypes.byref(s)))
+        return int(p.value), int(s.value)
+
     def workspace_bytes(self) -> int:
-        n = _SZ()
-        _check(_lib.spl_batch_workspace_size(self._h, ctypes.byref(n)))
-        return int(n.value)
+        return sum(self.workspace_parts())
 
     def tiles(self, beam=0) -> dict:
         t = _Tiles()

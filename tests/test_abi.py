@@ -91,9 +91,13 @@ def test_batch_layout_host_only():
     plans = [spl.Plan.from_dict(W.plan_band3_c4()), spl.Plan.from_dict(W.plan_band4_c4())]
     b = spl.Batch([plans[0], plans[1], plans[0]], mode=spl.MODE_PERSISTENT_GRAPH, hit_capacity=1 << 20)
     n = b.workspace_bytes()
-    # at least the three DM transforms
+    # at least the three DM transforms, all of them in the per-run scratch part; the
+    # persistent part holds at least both plans' delay tables
     need = sum(p.info["ndm"] * p.info["n_dd"] * 4 for p in (plans[0], plans[1], plans[0]))
     assert n > need
+    persistent, scratch = b.workspace_parts()
+    assert persistent + scratch == n and scratch > need and persistent % 256 == 0
+    assert persistent >= sum(p.info["ndm"] * p.info["nchans"] * 4 for p in plans)
     t = b.tiles(1)
     assert t["chan_chunk"] >= 4 and t["dm_per_wave"] in (2, 4, 8, 16)
     with pytest.raises(spl.SplError):
