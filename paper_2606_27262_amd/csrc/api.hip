@@ -278,6 +278,7 @@ struct spl_batch {
     size_t off_counts = 0, off_chunk_off = 0, off_block_sums = 0, off_row_start = 0;
     size_t off_hits = 0, off_alive0 = 0, off_alive1 = 0, off_pos = 0, off_run = 0;
     size_t off_nms_blk = 0;   // block index of the hit rows [n_rows][nms_nblk] int32
+    size_t off_hit_t = 0;     // the hits' times, packed int32 [hit_cap]
     int nms_nblk = 0;
     int n_block_sums = 0;
     std::vector<int> xpitch;
@@ -542,6 +543,7 @@ static spl_status build_layout(spl_batch *B) {
         B->off_nms_blk = take((size_t)B->n_rows * B->nms_nblk * sizeof(int32_t));
     }
     B->off_hits = take((size_t)B->hit_cap * sizeof(Hit));
+    B->off_hit_t = take((size_t)B->hit_cap * sizeof(int32_t));
     B->off_alive0 = take((size_t)B->hit_cap);
     B->off_alive1 = take((size_t)B->hit_cap);
     B->off_pos = take((size_t)B->hit_cap * sizeof(int64_t));
@@ -835,13 +837,15 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
     // 4. peak filters, then ordered compaction into candidate records
     StageTimer t_pk(B, s, SPL_STAGE_PEAKS);
     int32_t *blk = (int32_t *)(B->ws + B->off_nms_blk);
+    int32_t *hit_t = (int32_t *)(B->ws + B->off_hit_t);
     if (max_nst)
-        HIP_TRY(launch_nms_index(row_lo, row_hi - row_lo, hits, &run->n_hits, cap, row_start, blk, B->nms_nblk, s));
+        HIP_TRY(launch_nms_index(row_lo, row_hi - row_lo, hits, &run->n_hits, cap, row_start, blk, B->nms_nblk, hit_t,
+                                 s));
     const uint8_t *in = nullptr;
     for (int k = 0; k < max_nst; ++k) {
         uint8_t *o = alive[k & 1];
         HIP_TRY(launch_nms(beams, b_lo, b_hi, row_lo, hits, &run->n_hits, cap, row_start, blk, B->nms_nblk, k, in, o,
-                           &run->n_alive[k], s));
+                           &run->n_alive[k], hit_t, s));
         in = o;
     }
     if (max_nst) {

@@ -31,10 +31,11 @@ hipError_t launch_row_start(const DevBeam *beams, int beam_lo, int beam_hi, int 
 // of its first hit with t >= 64 b (the row's count when none); nblk even, 64 nblk > the
 // largest t.
 hipError_t launch_nms_index(int row_lo, int n_rows, const Hit *hits, const int64_t *n_hits, int64_t cap,
-                            const int64_t *row_start, int32_t *blk, int nblk, hipStream_t s);
+                            const int64_t *row_start, int32_t *blk, int nblk, int32_t *hit_t, hipStream_t s);
 hipError_t launch_nms(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, const Hit *hits,
                       const int64_t *n_hits, int64_t cap, const int64_t *row_start, const int32_t *blk, int nblk,
-                      int stencil, const uint8_t *alive_in, uint8_t *alive_out, int64_t *n_alive, hipStream_t s);
+                      int stencil, const uint8_t *alive_in, uint8_t *alive_out, int64_t *n_alive,
+                      const int32_t *hit_t, hipStream_t s);
 hipError_t launch_scatter(const DevBeam *beams, int beam_lo, int beam_hi, const Hit *hits, const int64_t *n_hits,
                           int64_t cap, const uint8_t *alive, const int64_t *pos, const int64_t *base,
                           spl_candidate *cands, int64_t cand_cap, hipStream_t s);

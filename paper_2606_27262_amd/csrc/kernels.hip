@@ -651,14 +651,17 @@ __global__ void k_row_start(const DevBeam *__restrict__ beams, int beam_lo, int 
 // ------------------------------------------------------- block index of hit rows
 // blk[r][b] = index (within row r) of the first hit with t >= 64 b, or the row's hit count.
 // k_nms_mark writes the first hit of every occupied block (the table holds INT32_MAX
-// elsewhere); k_nms_suffix then takes the suffix minimum along each row.
+// elsewhere) and the hits' times as a packed int32 array (the peak filter's searches
+// and window scans read 4 bytes per hit instead of a 24-byte record); k_nms_suffix then
+// takes the suffix minimum along each row.
 __global__ __launch_bounds__(kThreads) void k_nms_mark(int row_lo, const Hit *__restrict__ hits,
                                                        const int64_t *n_hits, int64_t cap,
                                                        const int64_t *__restrict__ row_start, int32_t *blk,
-                                                       int nblk) {
+                                                       int nblk, int32_t *__restrict__ hit_t) {
     const int64_t n = min(*n_hits, cap);
     for (int64_t q = blockIdx.x * (int64_t)kThreads + threadIdx.x; q < n; q += (int64_t)gridDim.x * kThreads) {
         const Hit h = hits[q];
+        hit_t[q] = h.t;
         const int r = h.row - row_lo;
         const int b = h.t >> kNmsBlockShift;
         const bool first = q == 0 || hits[q - 1].row != h.row || (hits[q - 1].t >> kNmsBlockShift) != b;
@@ -695,14 +698,15 @@ __global__ __launch_bounds__(kThreads) void k_nms_suffix(const int64_t *__restri
 // 64-sample block and of the next (the block index, built once per run by k_nms_mark and
 // k_nms_suffix): at most 6 dependent loads instead of one per halving of the row.  A row
 // holds at most one hit per sample, so in p's own row the window starts no more than rt
-// entries before p and needs no search.
+// entries before p and needs no search.  Searches and scans read the packed times; a
+// hit's S/N is loaded only when it lies in the window.
 __global__ __launch_bounds__(kThreads) void k_nms(const DevBeam *__restrict__ beams, int beam_lo, int beam_hi,
                                                   int row_lo, const Hit *__restrict__ hits,
                                                   const int64_t *n_hits, int64_t cap,
                                                   const int64_t *__restrict__ row_start,
                                                   const int32_t *__restrict__ blk, int nblk, int stencil,
                                                   const uint8_t *alive_in, uint8_t *alive_out,
-                                                  int64_t *n_alive) {
+                                                  int64_t *n_alive, const int32_t *__restrict__ hit_t) {
     __shared__ int64_t sh[kThreads / 64];
     // first rows of the beams, for the bisection from a hit's row to its beam in the LDS
     // (when the batch has more beams than fit, the bisection reads the descriptors)
@@ -766,14 +770,15 @@ __global__ __launch_bounds__(kThreads) void k_nms(const DevBeam *__restrict__ be
                 }
                 while (lo < hi) {
                     const int64_t m = (lo + hi) >> 1;
-                    if (hits[m].t < tmin) lo = m + 1; else hi = m;
+                    if (hit_t[m] < tmin) lo = m + 1; else hi = m;
                 }
             }
             for (int64_t q = lo; q < end; ++q) {
-                const Hit g = hits[q];
-                if (g.t > h.t + rt) break;
-                if (g.t < tmin || q == p || (alive_in && !alive_in[q])) continue;
-                const bool beats = g.snr != h.snr ? g.snr > h.snr : (d2 != d ? d2 < d : g.t < h.t);
+                const int gt = hit_t[q];
+                if (gt > h.t + rt) break;
+                if (gt < tmin || q == p || (alive_in && !alive_in[q])) continue;
+                const double gs = hits[q].snr;
+                const bool beats = gs != h.snr ? gs > h.snr : (d2 != d ? d2 < d : gt < h.t);
                 if (beats) {
                     keep = false;
                     break;
@@ -990,13 +995,13 @@ static int grid_for(int64_t cap) {
 }
 
 hipError_t launch_nms_index(int row_lo, int n_rows, const Hit *hits, const int64_t *n_hits, int64_t cap,
-                            const int64_t *row_start, int32_t *blk, int nblk, hipStream_t s) {
+                            const int64_t *row_start, int32_t *blk, int nblk, int32_t *hit_t, hipStream_t s) {
     if (n_rows <= 0) return hipSuccess;
     if (nblk & 1) return hipErrorInvalidValue;   // filled in 8-byte words
     hipError_t e = launch_fill_u64((uint64_t *)blk, (int64_t)n_rows * nblk / 2, 0x7FFFFFFF7FFFFFFFull, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_nms_mark, dim3(grid_for(cap)), dim3(kThreads), 0, s, row_lo, hits, n_hits, cap, row_start,
-                       blk, nblk);
+                       blk, nblk, hit_t);
     SPL_HIP_LAUNCH_CHECK();
     const int waves = kThreads / 64;
     hipLaunchKernelGGL(k_nms_suffix, dim3((unsigned)((n_rows + waves - 1) / waves)), dim3(kThreads), 0, s, row_start,
@@ -1007,9 +1012,10 @@ hipError_t launch_nms_index(int row_lo, int n_rows, const Hit *hits, const int64
 
 hipError_t launch_nms(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, const Hit *hits,
                       const int64_t *n_hits, int64_t cap, const int64_t *row_start, const int32_t *blk, int nblk,
-                      int stencil, const uint8_t *alive_in, uint8_t *alive_out, int64_t *n_alive, hipStream_t s) {
+                      int stencil, const uint8_t *alive_in, uint8_t *alive_out, int64_t *n_alive,
+                      const int32_t *hit_t, hipStream_t s) {
     hipLaunchKernelGGL(k_nms, dim3(grid_for(cap)), dim3(kThreads), 0, s, beams, beam_lo, beam_hi, row_lo, hits,
-                       n_hits, cap, row_start, blk, nblk, stencil, alive_in, alive_out, n_alive);
+                       n_hits, cap, row_start, blk, nblk, stencil, alive_in, alive_out, n_alive, hit_t);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }
