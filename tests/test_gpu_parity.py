@@ -291,6 +291,69 @@ def test_c3_batch_full_size(spl, c3_batch, group):
         say(f"  snippets of {len(pick)} candidates bit-exact")
 
 
+C4_BEAMS = 32
+C4_GROUP = 4
+
+
+@pytest.fixture(scope="module")
+def c4_batch(spl):
+    """The 32-beam uneven workload as the benchmark's uneven leg searches it: beams
+    alternating the 2048-channel 300-500 MHz plan (even) and the 4096-channel 550-750 MHz
+    plan with 3072 trials (odd), blocks made on the GPU with the workload's recipe (seed
+    4, ten pulses, 2% RFI channels, zero-DM bursts), one persistent launch per band in one
+    hipGraph with the tiles the autotuner picks for these plans."""
+    pds = W.batch_c4_plans()
+    uniq = {}
+    plans = []
+    for pd in pds:
+        key = repr(sorted(pd.items()))
+        if key not in uniq:
+            uniq[key] = make_plan(spl, 0, 0, 0, None, 0, plan_dict=pd)
+            assert_library_tables(uniq[key])
+        plans.append(uniq[key])
+    dev = []
+    for b, (pd, p) in enumerate(zip(pds, plans)):
+        _, x = W.c2_like_block_torch(pd, p.info["n_in"], 4, b, 10, dm_max_pulse=0.9 * W.dm_max(pd), zero_dm_rate=0.2)
+        dev.append(x)
+    batch = spl.Batch(plans, mode=spl.MODE_PERSISTENT_GRAPH, hit_capacity=1 << 28)
+    batch.set_tiles(0, 2, 2, 16, waves=16)
+    batch.set_tiles(1, 4, 2, 32, waves=16)
+    cands = spl.new_candidates(1 << 22)
+    cands, stats = batch.run(dev, cands)
+    torch.cuda.synchronize()
+    st = spl.stats_dict(stats)
+    say("c4 batch searched:", st, batch.tiles(0), batch.tiles(1))
+    assert st["hit_overflow"] == 0 and st["cand_overflow"] == 0
+    return {"plans": plans, "batch": batch, "dev": dev, "cands": spl.candidates_to_numpy(cands, stats), "stats": st}
+
+
+def _host_block(c4, b):
+    p = c4["plans"][b]
+    return c4["dev"][b][:, :p.info["n_in"]].cpu().numpy()
+
+
+@pytest.mark.parametrize("group", range(C4_BEAMS // C4_GROUP))
+def test_c4_batch_full_size(spl, c4_batch, group):
+    """Beams 4g .. 4g+3 of the 32-beam uneven persistent graph batch (two of each band):
+    the whole DM transform, the moments and the candidate list of every beam equal the
+    oracle's own search of its block, bit for bit."""
+    batch = c4_batch["batch"]
+    assert len(c4_batch["plans"]) == C4_BEAMS
+    for beam in range(group * C4_GROUP, (group + 1) * C4_GROUP):
+        p = c4_batch["plans"][beam]
+        x = _host_block(c4_batch, beam)
+        r = oracle_search(p, x, beam=beam)
+        X = batch.dm_transform(beam)[:, :p.info["n_dd"]].cpu().numpy().astype(np.int64)
+        assert np.array_equal(X, r["X"]), f"X differs (beam {beam})"
+        del X
+        s1, s2 = batch.moments(beam)
+        assert np.array_equal(s1.cpu().numpy(), r["S1"]) and np.array_equal(s2.cpu().numpy(), r["S2"]), beam
+        got = c4_batch["cands"][c4_batch["cands"]["beam"] == beam]
+        say(f"c4 beam {beam} ({p.info['nchans']} ch): hits {r['hits']['d'].size}, "
+            f"candidates {got.size} / {r['cands'].size}")
+        assert np.array_equal(got, r["cands"]), f"candidates differ (beam {beam})"
+
+
 @pytest.mark.parametrize("band", ["300-500", "300-500-fine", "550-750"])
 @pytest.mark.parametrize("nch", [512, 37])
 def test_tile_shapes_give_identical_results(spl, nch, band):
