@@ -243,12 +243,22 @@ def cpu_baseline(pd, plan, W, target_s=12.0):
 
 
 def dedisp_source_hash():
-    """SHA-256 over the sources the dedispersion kernel is compiled from (the kernel
-    file and the headers that define its descriptors), in a fixed order."""
+    """SHA-256 over what the dedispersion kernel is compiled from, in a fixed order: its
+    section of kernels.hip (from the dedispersion banner to the next kernel's), the
+    staging-depth constant of kernels.h, and the headers that define its descriptors
+    and device helpers.  Edits to the other kernels leave it unchanged."""
     import hashlib
+    import re
+    csrc = os.path.join(ROOT, "paper_2606_27262_amd", "csrc")
+    src = open(os.path.join(csrc, "kernels.hip")).read()
+    i = src.index("// ------------------------------------------------------------- dedispersion")
+    j = src.index("// ------------------------------------------------------- moments + thresholds")
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.h", "spl_internal.h", "spl_device.h"):
-        h.update(open(os.path.join(ROOT, "paper_2606_27262_amd", "csrc", f), "rb").read())
+    h.update(src[i:j].encode())
+    h.update("\n".join(re.findall(r"^constexpr int kDedispStageRows.*$", open(os.path.join(csrc, "kernels.h")).read(),
+                                   re.M)).encode())
+    for f in ("spl_internal.h", "spl_device.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()
 
 
