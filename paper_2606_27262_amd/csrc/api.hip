@@ -279,6 +279,8 @@ struct spl_batch {
     size_t off_hits = 0, off_alive0 = 0, off_alive1 = 0, off_pos = 0, off_run = 0;
     size_t off_nms_blk = 0;   // block index of the hit rows [n_rows][nms_nblk] int32
     size_t off_hit_t = 0;     // the hits' times, packed int32 [hit_cap]
+    size_t off_surv = 0;      // survivors of the first peak filter [hit_cap] Hit
+    size_t off_surv_start = 0;   // their row starts [n_rows + 1] int64
     int nms_nblk = 0;
     int n_block_sums = 0;
     std::vector<int> xpitch;
@@ -544,6 +546,8 @@ static spl_status build_layout(spl_batch *B) {
     }
     B->off_hits = take((size_t)B->hit_cap * sizeof(Hit));
     B->off_hit_t = take((size_t)B->hit_cap * sizeof(int32_t));
+    B->off_surv = take((size_t)B->hit_cap * sizeof(Hit));
+    B->off_surv_start = take((size_t)(B->n_rows + 1) * sizeof(int64_t));
     B->off_alive0 = take((size_t)B->hit_cap);
     B->off_alive1 = take((size_t)B->hit_cap);
     B->off_pos = take((size_t)B->hit_cap * sizeof(int64_t));
@@ -841,17 +845,35 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
     if (max_nst)
         HIP_TRY(launch_nms_index(row_lo, row_hi - row_lo, hits, &run->n_hits, cap, row_start, blk, B->nms_nblk, hit_t,
                                  s));
+    // The first filter runs over every hit.  The later ones (wider windows, over the few
+    // survivors) run over the survivors compacted in order, with their own block index,
+    // so that their searches and scans never meet a hit already filtered out.
+    const Hit *fh = hits;
+    const int64_t *fn = &run->n_hits;
+    const int64_t *fstart = row_start;
     const uint8_t *in = nullptr;
     for (int k = 0; k < max_nst; ++k) {
         uint8_t *o = alive[k & 1];
-        HIP_TRY(launch_nms(beams, b_lo, b_hi, row_lo, hits, &run->n_hits, cap, row_start, blk, B->nms_nblk, k, in, o,
+        if (k == 1) {
+            Hit *surv = (Hit *)(B->ws + B->off_surv);
+            int64_t *surv_start = (int64_t *)(B->ws + B->off_surv_start) + row_lo;
+            HIP_TRY(launch_scan_u8(in, &run->n_hits, cap, block_sums, pos, &run->n_surv, s));
+            HIP_TRY(launch_compact_hits(hits, &run->n_hits, cap, in, pos, surv, row_start, row_hi - row_lo,
+                                        &run->n_surv, surv_start, s));
+            HIP_TRY(launch_nms_index(row_lo, row_hi - row_lo, surv, &run->n_surv, cap, surv_start, blk,
+                                     B->nms_nblk, hit_t, s));
+            fh = surv;
+            fn = &run->n_surv;
+            fstart = surv_start;
+            in = nullptr;
+        }
+        HIP_TRY(launch_nms(beams, b_lo, b_hi, row_lo, fh, fn, cap, fstart, blk, B->nms_nblk, k, in, o,
                            &run->n_alive[k], hit_t, s));
         in = o;
     }
     if (max_nst) {
-        HIP_TRY(launch_scan_u8(in, &run->n_hits, cap, block_sums, pos, &run->n_cand_beam, s));
-        HIP_TRY(launch_scatter(beams, b_lo, b_hi, hits, &run->n_hits, cap, in, pos, &run->n_cand_total, cands,
-                               cand_cap, s));
+        HIP_TRY(launch_scan_u8(in, fn, cap, block_sums, pos, &run->n_cand_beam, s));
+        HIP_TRY(launch_scatter(beams, b_lo, b_hi, fh, fn, cap, in, pos, &run->n_cand_total, cands, cand_cap, s));
     } else {
         HIP_TRY(launch_scatter(beams, b_lo, b_hi, hits, &run->n_hits, cap, nullptr, nullptr, &run->n_cand_total,
                                cands, cand_cap, s));

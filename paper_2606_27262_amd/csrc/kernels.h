@@ -30,6 +30,11 @@ hipError_t launch_row_start(const DevBeam *beams, int beam_lo, int beam_hi, int 
 // Block index of the hit rows [row_lo, row_lo + n_rows): blk[r][b] = index within row r
 // of its first hit with t >= 64 b (the row's count when none); nblk even, 64 nblk > the
 // largest t.
+// The survivors of a peak filter (alive flags, pos their exclusive scan, *n_surv their
+// count) compacted in order into out, with the row starts of the compacted list.
+hipError_t launch_compact_hits(const Hit *hits, const int64_t *n_hits, int64_t cap, const uint8_t *alive,
+                               const int64_t *pos, Hit *out, const int64_t *row_start, int n_rows,
+                               const int64_t *n_surv, int64_t *out_start, hipStream_t s);
 hipError_t launch_nms_index(int row_lo, int n_rows, const Hit *hits, const int64_t *n_hits, int64_t cap,
                             const int64_t *row_start, int32_t *blk, int nblk, int32_t *hit_t, hipStream_t s);
 hipError_t launch_nms(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, const Hit *hits,

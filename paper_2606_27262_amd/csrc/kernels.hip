@@ -648,6 +648,29 @@ __global__ void k_row_start(const DevBeam *__restrict__ beams, int beam_lo, int 
     if (r == row_hi) row_start[r - row_lo] = stored;
 }
 
+// ------------------------------------------------------- survivors of the first filter
+// The later peak filters see only the survivors of the first, compacted in order
+// (out[pos[p]] = hits[p] for alive p, pos the exclusive scan of the flags), with row
+// starts out_start[r] = pos[row_start[r]] (the count of survivors before the row).
+__global__ __launch_bounds__(kThreads) void k_compact_hits(const Hit *__restrict__ hits, const int64_t *n_hits,
+                                                           int64_t cap, const uint8_t *__restrict__ alive,
+                                                           const int64_t *__restrict__ pos, Hit *__restrict__ out) {
+    const int64_t n = min(*n_hits, cap);
+    for (int64_t p = blockIdx.x * (int64_t)kThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kThreads)
+        if (alive[p]) out[pos[p]] = hits[p];
+}
+
+__global__ __launch_bounds__(kThreads) void k_compact_row_start(const int64_t *__restrict__ row_start, int n_rows,
+                                                                const int64_t *n_hits, int64_t cap,
+                                                                const int64_t *__restrict__ pos,
+                                                                const int64_t *n_surv, int64_t *out_start) {
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    if (r > n_rows) return;
+    const int64_t n = min(*n_hits, cap);
+    const int64_t i = row_start[r];
+    out_start[r] = (r < n_rows && i < n) ? pos[i] : *n_surv;
+}
+
 // ------------------------------------------------------- block index of hit rows
 // blk[r][b] = index (within row r) of the first hit with t >= 64 b, or the row's hit count.
 // k_nms_mark writes the first hit of every occupied block (the table holds INT32_MAX
@@ -992,6 +1015,17 @@ static int grid_for(int64_t cap) {
     if (g > 8192) g = 8192;
     if (g < 1) g = 1;
     return (int)g;
+}
+
+hipError_t launch_compact_hits(const Hit *hits, const int64_t *n_hits, int64_t cap, const uint8_t *alive,
+                               const int64_t *pos, Hit *out, const int64_t *row_start, int n_rows,
+                               const int64_t *n_surv, int64_t *out_start, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact_hits, dim3(grid_for(cap)), dim3(kThreads), 0, s, hits, n_hits, cap, alive, pos, out);
+    SPL_HIP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_compact_row_start, dim3((n_rows + 1 + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                       row_start, n_rows, n_hits, cap, pos, n_surv, out_start);
+    SPL_HIP_LAUNCH_CHECK();
+    return hipSuccess;
 }
 
 hipError_t launch_nms_index(int row_lo, int n_rows, const Hit *hits, const int64_t *n_hits, int64_t cap,

@@ -73,6 +73,7 @@ struct DevRun {
     int64_t n_cand_total;  // candidates written so far (all beams)
     int64_t n_cand_beam;   // candidates of the beams in flight
     int64_t n_alive[kMaxStencils];
+    int64_t n_surv;        // survivors of the first peak filter (the compacted list's length)
     int32_t hit_overflow;
     int32_t queue[kMaxShapeGroups];  // persistent-kernel work counters
     int32_t pad;
