@@ -138,7 +138,6 @@ def test_full_size_beam_outside_windows(spl, full_size):
 
 
 def test_degenerate_calls(spl):
-    q = inj.synthetic_quantiser()
     block = np.full((4, 256), 128, np.uint8)
     d = _dev(block)
     ts = _dev(np.zeros((1, 4), np.int32))
@@ -154,7 +153,6 @@ def test_degenerate_calls(spl):
         spl.inject_quantised(d, ts, sig, None, bits=9, mode=spl.INJECT_ARGMAX)
     with pytest.raises(spl.SplError):
         spl.inject_quantised(d, ts, sig, None, sigma=0.0, mode=spl.INJECT_ARGMAX)
-    _ = q
 
 
 def _best_snr(spl, plan_dict, block):
