@@ -7,9 +7,9 @@ Device ring.  Block k of a beam owns stream samples [k n_out, (k+1) n_out) and r
 [k n_out, k n_out + n_in): consecutive blocks share n_in - n_out = s_max + w_max - 1
 samples.  Three device block slots per beam rotate; for block k >= 1 only its n_out new
 samples cross the host link, as one contiguous copy from pinned host memory into a
-device staging buffer on the copy stream; on the compute stream spl_stream_assemble then
+device staging buffer on the copy stream; on the same stream spl_stream_assemble then
 writes slot k % 3 from the previous block's tail (slot (k-1) % 3) and the staged samples,
-right before the search of block k.  The first block of a stream is uploaded whole.
+while block k-1 is searched.  The first block of a stream is uploaded whole.
 The normaliser is not carried: each block's mean and sigma come from its own owned
 samples (a search of block k is a function of block k alone, equal to the oracle's
 search of the same samples).
@@ -17,12 +17,13 @@ search of the same samples).
 Three batches, one per slot, each with its own workspace, rotate with the slots (a batch
 always sees the same block pointers, so a run uploads nothing that could queue behind
 the big copy).  For block k, slot k % 3:
-  compute stream assembly of block k (after its new samples arrived), its search
-                 (persistent launch, hipGraph), then the run statistics and a prefix of
-                 the records to pinned host memory
-  copy stream    new samples of block k+1 -> staging buffer (k+1) % 3, enqueued right
-                 after the search of k: that buffer last fed block k-2, assembled
-                 before the search of k-2
+  compute stream search of block k (after its assembly; persistent launch, hipGraph),
+                 then the run statistics and a prefix of the records to pinned host
+                 memory
+  copy stream    new samples of block k+1 -> staging buffer (k+1) % 3 and the assembly
+                 of slot (k+1) % 3 from them and the tail of slot k % 3, enqueued right
+                 after the search of k: that buffer and that slot last fed block k-2,
+                 whose search the host has waited for
   host           candidate stage of block k-1: plain optimisation path, or the ranker
                  path (grouping, snippets and CNN on a third stream, anti-coincidence)
 So the copy of the next block and the candidate stage of the previous one both overlap
@@ -205,16 +206,16 @@ class StreamingSearch:
                 else:
                     for d, h in zip(self.stage[s], chunk_sets[(k - 1) % len(chunk_sets)]):
                         d.copy_(h, non_blocking=True)
+                    # slot s last held block k-3, whose search the host has waited for; the
+                    # previous slot holds block k-1, assembled earlier on this stream and
+                    # only read (by its search) meanwhile
+                    for b, (dn, dp, st) in enumerate(zip(self.dev[s], self.dev[(k - 1) % 3], self.stage[s])):
+                        spl.stream_assemble(dn, dp, st, n_out[b], n_in[b], stream=self.copy_stream)
                 copied[s].record(self.copy_stream)
 
         def enqueue_search(k):
             s = k % 3
             self.compute_stream.wait_event(copied[s])
-            if k > 0:
-                # slot s last held block k-3 (search and candidate stage done); the previous
-                # slot holds block k-1, overwritten only by the assembly of block k+2
-                for b, (dn, dp, st) in enumerate(zip(self.dev[s], self.dev[(k - 1) % 3], self.stage[s])):
-                    spl.stream_assemble(dn, dp, st, n_out[b], n_in[b], stream=self.compute_stream)
             self.batches[s].run(self.dev[s], self.cands[s], self.stats[s], stream=self.compute_stream)
             c = self.copy_hint
             with torch.cuda.stream(self.compute_stream):
@@ -234,8 +235,8 @@ class StreamingSearch:
             if k < n_blocks:
                 enqueue_search(k)
             if k + 1 < n_blocks:
-                # staging buffer (k+1) % 3 last fed block k-2, assembled before its search,
-                # which the host waited for in the previous iteration
+                # staging buffer and slot (k+1) % 3 last fed block k-2, whose search the
+                # host waited for in the previous iteration
                 enqueue_copy(k + 1)
             if k >= 1:
                 searched[(k - 1) % 3].synchronize()
