@@ -142,6 +142,29 @@ def test_small_random_batches(spl, mode):
         compare(g, ref, rc)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_stencil_sets_of_every_length(spl, mode):
+    """Plans with one to four peak filters of different sizes in one batch: the first
+    filter runs over all hits, the later ones over its compacted survivors (a third and
+    fourth filter read the flags of the compacted pass before), and beams whose plan has
+    fewer filters pass the later ones unchanged.  Candidates bit for bit."""
+    rng = np.random.default_rng(61 + mode)
+    sets = [((1, 1),), ((1, 1), (3, 2), (5, 5)), ((2, 3), (4, 1), (1, 1), (6, 6)), ((1, 1), (5, 5)), ()]
+    plans, blocks = [], []
+    for b, st in enumerate(sets):
+        nch, ndm, n_out = int(rng.integers(8, 48)), int(rng.integers(20, 60)), int(rng.integers(1500, 3000))
+        D = _random_monotone_delays(rng, ndm, nch, int(rng.integers(20, 300)))
+        p = make_plan(spl, nch, ndm, n_out, (1, 2, 4, 8), 2.0, delays=D, stencils=st)
+        x = rng.integers(0, 256, size=(nch, p.info["n_in"]), dtype=np.uint8)
+        plans.append(p)
+        blocks.append(x)
+    g = gpu_run(spl, plans, blocks, mode=mode)
+    ref, rc = oracle_run(plans, blocks)
+    say("stencil sets: hits", g["stats"]["n_hits"], "candidates", rc.size, "after each filter",
+        g["stats"]["n_after_stencil"])
+    compare(g, ref, rc)
+
+
 def test_c1_full(spl):
     p = make_plan(spl, 0, 0, 0, None, 0, plan_dict=W.plan_c1())
     _, x = W.c1_block(p.info["n_in"], seed=1)
