@@ -255,7 +255,7 @@ def dedisp_source_hash():
     j = src.index("// ------------------------------------------------------- moments + thresholds")
     h = hashlib.sha256()
     h.update(src[i:j].encode())
-    h.update("\n".join(re.findall(r"^constexpr int kDedispStageRows.*$", open(os.path.join(csrc, "kernels.h")).read(),
+    h.update("\n".join(re.findall(r"^constexpr int dedisp_stage_rows.*$", open(os.path.join(csrc, "kernels.h")).read(),
                                    re.M)).encode())
     for f in ("spl_internal.h", "spl_device.h"):
         h.update(open(os.path.join(csrc, f), "rb").read())
@@ -271,14 +271,15 @@ def counter_traffic(workload, tiles):
     path = os.path.join(ROOT, "profiles", f"dedisp_{workload}_hbm_counters.md")
     if not os.path.exists(path):
         return None
-    m = re.search(r"^counters: workload=(\S+) kernel=k_dedisp tiles=(\d+),(\d+),(\d+),(\d+) grid=\d+ "
+    m = re.search(r"^counters: workload=(\S+) kernel=k_dedisp tiles=(\d+),(\d+),(\d+),(\d+),(\d+) grid=\d+ "
                   r"fetch_bytes=(\d+) write_bytes=(\d+) dedisp_src_sha256=([0-9a-f]{64})$", open(path).read(), re.M)
-    if not m or m.group(1) != workload or dedisp_source_hash() != m.group(8):
+    if not m or m.group(1) != workload or dedisp_source_hash() != m.group(9):
         return None
-    shape = tuple(int(m.group(i)) for i in range(2, 6))
-    if any((t["dm_per_wave"], t["time_groups"], t["waves"], t["chan_chunk"]) != shape for t in tiles):
+    shape = tuple(int(m.group(i)) for i in range(2, 7))   # trials/wave, groups, waves, chan_chunk, buffers
+    if any((t["dm_per_wave"], t["time_groups"], t["waves"], t["chan_chunk"], t.get("buffers", 1)) != shape
+           for t in tiles):
         return None
-    return {"fetch_bytes": int(m.group(6)), "write_bytes": int(m.group(7))}
+    return {"fetch_bytes": int(m.group(7)), "write_bytes": int(m.group(8))}
 
 
 def corner_turn_leg(spl, plan, reps=12, nbuf=4):
@@ -522,7 +523,8 @@ def growth_leg(spl, W, pd, tiles, block_s, sizes=(96, 384, 768), steps=2, seed=7
             del probe
             continue
         blocks = [W.c2_like_block_torch(pd, n_in, seed, b, 10)[1] for b in range(nb)]
-        probe.set_tiles(0, tiles["dm_per_wave"], tiles["time_groups"], tiles["chan_chunk"], waves=tiles["waves"])
+        probe.set_tiles(0, tiles["dm_per_wave"], tiles["time_groups"], tiles["chan_chunk"], waves=tiles["waves"],
+                        buffers=tiles.get("buffers", 1))
         probe.attach()
         cands = spl.new_candidates(1 << 20)
         stats = torch.zeros(spl.STATS_WORDS, dtype=torch.int64, device="cuda")

@@ -289,13 +289,17 @@ spl_status spl_batch_moments(const spl_batch *batch, int32_t beam, const int64_t
 
 /* Dedispersion tiling of one beam: a workgroup of `waves` wavefronts sums a tile of
  * waves*dm_per_wave DM trials by time_groups*256 samples; chan_chunk channels are staged
- * in LDS per step (a power of two in [2, 2*waves]; 0: the largest that fits a 64 KiB
- * budget). */
+ * in LDS per step (a power of two in [2, 2*waves] with one buffer, [2, waves] with two;
+ * 0: the largest that fits a 64 KiB budget).  With two LDS buffers (16-wavefront tiles
+ * only) the next chunk is staged while the current one is summed.  The compiled shapes
+ * (dm_per_wave, time_groups, waves[, buffers]): (2,2,8) (4,1,4) (4,2,4) (4,1,8) (4,2,8)
+ * (8,1,4) (8,1,8), and (4,1,16) (4,2,16) (2,2,16) with one or two buffers. */
 typedef struct spl_tiles {
     int32_t dm_per_wave;
     int32_t time_groups;
     int32_t chan_chunk;
-    int32_t waves;       /* 4 or 8; 0 selects 4 */
+    int32_t waves;       /* 4, 8 or 16; 0 selects 4 */
+    int32_t buffers;     /* LDS buffers, 1 or 2; 0 selects 1 */
 } spl_tiles;
 spl_status spl_batch_get_tiles(const spl_batch *batch, int32_t beam, spl_tiles *tiles);
 /* Set the tiling of every beam sharing beam's plan; SPL_E_UNSUPPORTED if the shape is

@@ -47,7 +47,7 @@ static spl_status fail(spl_status st, const char *fmt, ...) {
 spl_status spl_internal_fail(spl_status st, const char *msg) { return fail(st, "%s", msg); }
 
 extern "C" const char *spl_last_error(void) { return g_err.c_str(); }
-extern "C" int32_t spl_version(void) { return 200; }
+extern "C" int32_t spl_version(void) { return 201; }
 
 // --------------------------------------------------------------------- plans
 static constexpr double kDispersionConstant = 4148.8064239;  // MHz^2 pc^-1 cm^3 s
@@ -228,6 +228,7 @@ namespace {
 
 struct Tiles {
     int dw = 4, j = 2, nw = 8, cc = 0;
+    int nb = 1;   // LDS buffers: 2 stages the next chunk while the current one is summed
     int sv = 1;   // staged 16-byte vectors per lane and row, from the widest row of the plan
 };
 
@@ -265,7 +266,7 @@ struct spl_batch {
     int max_nst = 0, w_max = 0;
     std::vector<DedispItem> items;
     // shape groups for the persistent launch
-    struct Group { int dw, j, nw, sv; int item_lo, item_hi; size_t lds; int occ; };
+    struct Group { int dw, j, nw, sv, nb; int item_lo, item_hi; size_t lds; int occ; };
     std::vector<Group> groups;
     std::vector<size_t> beam_lds;          // per beam (plain per-beam launches)
     // workspace
@@ -307,12 +308,13 @@ struct spl_batch {
 
 static spl_status layout_plan(PlanLayout &L) {
     const spl_plan &p = *L.plan;
-    if (!dedisp_shape_supported(L.tiles.dw, L.tiles.j, L.tiles.nw, 1))
-        return fail(SPL_E_UNSUPPORTED, "dedispersion tile shape (%d, %d, %d) is not compiled in", L.tiles.dw,
-                    L.tiles.j, L.tiles.nw);
-    if (L.tiles.cc < 0 || L.tiles.cc > kDedispStageRows * L.tiles.nw)
-        return fail(SPL_E_UNSUPPORTED, "chan_chunk must be in [0, %d] for %d wavefronts", kDedispStageRows * L.tiles.nw,
-                    L.tiles.nw);
+    if (!dedisp_shape_supported(L.tiles.dw, L.tiles.j, L.tiles.nw, 1, L.tiles.nb))
+        return fail(SPL_E_UNSUPPORTED, "dedispersion tile shape (%d, %d, %d) with %d LDS buffer(s) is not compiled in",
+                    L.tiles.dw, L.tiles.j, L.tiles.nw, L.tiles.nb);
+    const int cc_max = dedisp_stage_rows(L.tiles.nb) * L.tiles.nw;
+    if (L.tiles.cc < 0 || L.tiles.cc > cc_max)
+        return fail(SPL_E_UNSUPPORTED, "chan_chunk must be in [0, %d] for %d wavefronts and %d LDS buffer(s)", cc_max,
+                    L.tiles.nw, L.tiles.nb);
     L.td = L.tiles.nw * L.tiles.dw;
     L.ndm_pad = (p.ndm + L.td - 1) / L.td * L.td;
     L.ntile_d = L.ndm_pad / L.td;
@@ -344,7 +346,7 @@ static spl_status layout_plan(PlanLayout &L) {
     }
     const int rmax = *std::max_element(L.row_bytes.begin(), L.row_bytes.end());
     L.tiles.sv = rmax <= 1024 ? 1 : 2;
-    if (rmax > 2048 || !dedisp_shape_supported(L.tiles.dw, L.tiles.j, L.tiles.nw, L.tiles.sv))
+    if (rmax > 2048 || !dedisp_shape_supported(L.tiles.dw, L.tiles.j, L.tiles.nw, L.tiles.sv, L.tiles.nb))
         return fail(SPL_E_UNSUPPORTED, "a DM tile spans %d bytes of staged row: too wide for this tile shape "
                     "(use fewer trials per tile)", rmax);
     return SPL_OK;
@@ -391,14 +393,16 @@ static Tiles default_tiles(const spl_plan &p) {
 }
 
 // Channels per staging step: the largest power of two <= 256 whose four shifted copies
-// and offset table fit the LDS budget (a caller-set value is rounded down to a power of
-// two).  Then the table of LDS byte offsets of every delay.
+// and offset table (in each LDS buffer) fit the LDS budget (a caller-set value is rounded
+// down to a power of two).  Then the table of LDS byte offsets of every delay.
 static void choose_chunk(PlanLayout &L, size_t lds_budget) {
     const int rmax = *std::max_element(L.row_bytes.begin(), L.row_bytes.end());
     int cc = L.tiles.cc;
     if (cc <= 0) {
-        cc = kDedispStageRows * L.tiles.nw;
-        while (cc > 2 && (size_t)4 * (cc + 1) * rmax + (size_t)(cc + 4) * 4 * L.td > lds_budget) cc >>= 1;
+        cc = dedisp_stage_rows(L.tiles.nb) * L.tiles.nw;
+        while (cc > 2 &&
+               L.tiles.nb * ((size_t)4 * (cc + 1) * rmax + (size_t)(cc + 4) * 4 * L.td) > lds_budget)
+            cc >>= 1;
     }
     int p2 = 2;   // at least 2: an odd last chunk is padded with a zero row
     while (p2 * 2 <= std::min(cc, 256)) p2 *= 2;
@@ -416,6 +420,13 @@ static void choose_chunk(PlanLayout &L, size_t lds_budget) {
         }
     }
     (void)p;
+}
+
+// Dynamic LDS of one dedispersion workgroup: per buffer, four copies of chan_chunk + 1
+// staged rows and the offset table (dedisp_stage_rows * waves + 4 rows of td entries).
+static size_t dedisp_lds_bytes(const PlanLayout &L) {
+    return (size_t)L.tiles.nb *
+           ((size_t)4 * L.quarter + (size_t)(dedisp_stage_rows(L.tiles.nb) * L.tiles.nw + 4) * L.td * sizeof(int32_t));
 }
 
 static spl_status build_layout(spl_batch *B) {
@@ -440,12 +451,12 @@ static spl_status build_layout(spl_batch *B) {
         int g = -1;
         for (size_t k = 0; k < B->groups.size(); ++k)
             if (B->groups[k].dw == t.dw && B->groups[k].j == t.j && B->groups[k].nw == t.nw &&
-                B->groups[k].sv == t.sv)
+                B->groups[k].sv == t.sv && B->groups[k].nb == t.nb)
                 g = (int)k;
         if (g < 0) {
             if ((int)B->groups.size() >= kMaxShapeGroups)
                 return fail(SPL_E_UNSUPPORTED, "at most %d distinct tile shapes per batch", kMaxShapeGroups);
-            B->groups.push_back({t.dw, t.j, t.nw, t.sv, 0, 0, 0, 0});
+            B->groups.push_back({t.dw, t.j, t.nw, t.sv, t.nb, 0, 0, 0, 0});
         }
     }
     std::vector<std::vector<DedispItem>> per_beam(nb);
@@ -456,7 +467,7 @@ static spl_status build_layout(spl_batch *B) {
         for (int tt = 0; tt < L.ntile_t; ++tt)
             for (int k = 0; k < L.ntile_d; ++k)
                 per_beam[b].push_back({b, k * L.td, tt * TT, L.row_bytes[k]});
-        B->beam_lds[b] = (size_t)4 * L.quarter + (size_t)(kDedispStageRows * L.tiles.nw + 4) * L.td * sizeof(int32_t);
+        B->beam_lds[b] = dedisp_lds_bytes(L);
         B->max_nst = std::max(B->max_nst, p.nst);
         B->w_max = std::max(B->w_max, p.w_max);
     }
@@ -474,7 +485,7 @@ static spl_status build_layout(spl_batch *B) {
         size_t lds = 0;
         for (int b = 0; b < nb; ++b) {
             const Tiles &t = B->layouts[B->layout_of_beam[b]].tiles;
-            if (t.dw != g.dw || t.j != g.j || t.nw != g.nw || t.sv != g.sv) continue;
+            if (t.dw != g.dw || t.j != g.j || t.nw != g.nw || t.sv != g.sv || t.nb != g.nb) continue;
             B->item_base[b] = (int)B->items.size();
             B->items.insert(B->items.end(), per_beam[b].begin(), per_beam[b].end());
             lds = std::max(lds, B->beam_lds[b]);
@@ -705,13 +716,13 @@ static spl_status copy_tables(spl_batch *B) {
 static spl_status prepare_shapes(spl_batch *B) {
     for (auto &g : B->groups) {
         int occ = 0;
-        HIP_TRY(prepare_dedisp(g.dw, g.j, g.nw, g.sv, g.lds, &occ));
+        HIP_TRY(prepare_dedisp(g.dw, g.j, g.nw, g.sv, g.nb, g.lds, &occ));
         g.occ = std::max(1, occ);
     }
     for (int b = 0; b < B->nb; ++b) {
         const Tiles &t = B->layouts[B->layout_of_beam[b]].tiles;
         int occ = 0;
-        HIP_TRY(prepare_dedisp(t.dw, t.j, t.nw, t.sv, B->beam_lds[b], &occ));
+        HIP_TRY(prepare_dedisp(t.dw, t.j, t.nw, t.sv, t.nb, B->beam_lds[b], &occ));
     }
     return SPL_OK;
 }
@@ -807,8 +818,8 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
             const int n = G.item_hi - G.item_lo;
             if (n <= 0) continue;
             const int grid = std::min(n, G.occ * 256);
-            HIP_TRY(launch_dedisp(G.dw, G.j, G.nw, G.sv, beams, items, G.item_lo, G.item_hi, &run->queue[g], grid,
-                                  G.lds, s));
+            HIP_TRY(launch_dedisp(G.dw, G.j, G.nw, G.sv, G.nb, beams, items, G.item_lo, G.item_hi, &run->queue[g],
+                                  grid, G.lds, s));
         }
     } else {
         for (int b = b_lo; b < b_hi; ++b) {
@@ -816,7 +827,8 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
             const int lo = B->item_base[b];
             const PlanLayout &L = B->layouts[B->layout_of_beam[b]];
             const int hi = lo + L.ntile_d * L.ntile_t;
-            HIP_TRY(launch_dedisp(t.dw, t.j, t.nw, t.sv, beams, items, lo, hi, nullptr, hi - lo, B->beam_lds[b], s));
+            HIP_TRY(launch_dedisp(t.dw, t.j, t.nw, t.sv, t.nb, beams, items, lo, hi, nullptr, hi - lo, B->beam_lds[b],
+                                  s));
         }
     }
     HIP_TRY(t_dd.stop());
@@ -1060,28 +1072,30 @@ extern "C" spl_status spl_batch_get_tiles(const spl_batch *B, int32_t beam, spl_
     tiles->time_groups = t.j;
     tiles->chan_chunk = t.cc;
     tiles->waves = t.nw;
+    tiles->buffers = t.nb;
     return SPL_OK;
 }
 
 extern "C" spl_status spl_batch_set_tiles(spl_batch *B, int32_t beam, const spl_tiles *tiles) {
     if (!B || !tiles || beam < 0 || beam >= B->nb) return fail(SPL_E_INVALID_ARG, "bad argument");
     const int nw = tiles->waves ? tiles->waves : 4;
-    if (!dedisp_shape_supported(tiles->dm_per_wave, tiles->time_groups, nw, 1))
-        return fail(SPL_E_UNSUPPORTED, "tile shape (%d, %d, %d) is not compiled in", tiles->dm_per_wave,
-                    tiles->time_groups, nw);
-    if (tiles->chan_chunk < 0 || tiles->chan_chunk > kDedispStageRows * nw)
+    const int nbuf = tiles->buffers ? tiles->buffers : 1;
+    if (!dedisp_shape_supported(tiles->dm_per_wave, tiles->time_groups, nw, 1, nbuf))
+        return fail(SPL_E_UNSUPPORTED, "tile shape (%d, %d, %d) with %d LDS buffer(s) is not compiled in",
+                    tiles->dm_per_wave, tiles->time_groups, nw, nbuf);
+    if (tiles->chan_chunk < 0 || tiles->chan_chunk > dedisp_stage_rows(nbuf) * nw)
         return fail(SPL_E_UNSUPPORTED, "chan_chunk must be in [0, %d] (0: from the LDS budget)",
-                    kDedispStageRows * nw);
+                    dedisp_stage_rows(nbuf) * nw);
     PlanLayout &L = B->layouts[B->layout_of_beam[beam]];
     const Tiles old = L.tiles;
     L.tiles.dw = tiles->dm_per_wave;
     L.tiles.j = tiles->time_groups;
     L.tiles.nw = nw;
+    L.tiles.nb = nbuf;
     L.tiles.cc = tiles->chan_chunk;
     spl_status st = build_layout(B);
     if (st == SPL_OK) {
-        if ((size_t)4 * L.quarter + (size_t)(kDedispStageRows * L.tiles.nw + 4) * L.td * 4 > 160 * 1024 - 256)
-            st = fail(SPL_E_UNSUPPORTED, "tile does not fit the LDS");
+        if (dedisp_lds_bytes(L) > 160 * 1024 - 256) st = fail(SPL_E_UNSUPPORTED, "tile does not fit the LDS");
     }
     if (st != SPL_OK) {
         L.tiles = old;
@@ -1119,16 +1133,21 @@ struct TuneEntry {
     double ms = 0;
 };
 
-// Cache file: one line per plan, "<signature> <trials/wave> <groups> <waves> <chan_chunk> <ms>".
+// Cache file: one line per plan,
+// "<signature> <trials/wave> <groups> <waves> <LDS buffers> <chan_chunk> <ms>"; lines of
+// any other form are dropped (their plans are tuned again).
 std::vector<std::pair<std::string, TuneEntry>> read_cache(const char *path) {
     std::vector<std::pair<std::string, TuneEntry>> out;
     if (!path) return out;
     FILE *f = fopen(path, "r");
     if (!f) return out;
-    char sig[256];
-    TuneEntry e;
-    while (fscanf(f, "%255s %d %d %d %d %lf", sig, &e.t.dw, &e.t.j, &e.t.nw, &e.t.cc, &e.ms) == 6)
-        out.emplace_back(sig, e);
+    char line[512], sig[256], extra[2];
+    while (fgets(line, sizeof line, f)) {
+        TuneEntry e;
+        if (sscanf(line, "%255s %d %d %d %d %d %lf %1s", sig, &e.t.dw, &e.t.j, &e.t.nw, &e.t.nb, &e.t.cc, &e.ms,
+                   extra) == 7)
+            out.emplace_back(sig, e);
+    }
     fclose(f);
     return out;
 }
@@ -1139,8 +1158,8 @@ void write_cache(const char *path, const std::vector<std::pair<std::string, Tune
     FILE *f = fopen(tmp.c_str(), "w");
     if (!f) return;
     for (const auto &kv : c)
-        fprintf(f, "%s %d %d %d %d %.6f\n", kv.first.c_str(), kv.second.t.dw, kv.second.t.j, kv.second.t.nw,
-                kv.second.t.cc, kv.second.ms);
+        fprintf(f, "%s %d %d %d %d %d %.6f\n", kv.first.c_str(), kv.second.t.dw, kv.second.t.j, kv.second.t.nw,
+                kv.second.t.nb, kv.second.t.cc, kv.second.ms);
     fclose(f);
     (void)rename(tmp.c_str(), path);
 }
@@ -1162,9 +1181,11 @@ extern "C" spl_status spl_autotune(spl_batch *B, const uint8_t *const *d_blocks,
     constexpr int kTuneBeams = 4;
     // 16-wavefront tiles (64 trials) share each staged channel row among twice the trials;
     // 16 wavefronts of 2 trials keep 4 wavefronts per SIMD where a band's wide delay
-    // spread leaves room in the LDS for one workgroup per CU only
-    static const int shapes[][3] = {{2, 2, 8}, {4, 1, 4}, {4, 2, 4}, {4, 1, 8}, {4, 2, 8}, {8, 1, 4}, {8, 1, 8},
-                                    {4, 1, 16}, {4, 2, 16}, {2, 2, 16}};
+    // spread leaves room in the LDS for one workgroup per CU only; 16-wavefront tiles
+    // also come with two LDS buffers (trials/wave, groups, waves, buffers)
+    static const int shapes[][4] = {{2, 2, 8, 1},  {4, 1, 4, 1},  {4, 2, 4, 1},  {4, 1, 8, 1},  {4, 2, 8, 1},
+                                    {8, 1, 4, 1},  {8, 1, 8, 1},  {4, 1, 16, 1}, {4, 2, 16, 1}, {2, 2, 16, 1},
+                                    {4, 1, 16, 2}, {4, 2, 16, 2}, {2, 2, 16, 2}};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1192,12 +1213,13 @@ extern "C" spl_status spl_autotune(spl_batch *B, const uint8_t *const *d_blocks,
         bool have_ref = false;
         unsigned long long ref = 0;
         for (const auto &sh : shapes) {
-            for (int cc = 2; cc <= 2 * sh[2]; cc *= 2) {
+            for (int cc = 2; cc <= dedisp_stage_rows(sh[3]) * sh[2]; cc *= 2) {
                 PlanLayout &L = B->layouts[li];
                 L.tiles = Tiles{};
                 L.tiles.dw = sh[0];
                 L.tiles.j = sh[1];
                 L.tiles.nw = sh[2];
+                L.tiles.nb = sh[3];
                 L.tiles.cc = cc;
                 if (build_layout(B) != SPL_OK) continue;
                 if (B->beam_lds[rep] > 160 * 1024 - 256) continue;
@@ -1222,14 +1244,14 @@ extern "C" spl_status spl_autotune(spl_batch *B, const uint8_t *const *d_blocks,
                 }
                 const Tiles t = L.tiles;
                 int occ = 0;
-                HIP_TRY(prepare_dedisp(t.dw, t.j, t.nw, t.sv, B->beam_lds[rep], &occ));
+                HIP_TRY(prepare_dedisp(t.dw, t.j, t.nw, t.sv, t.nb, B->beam_lds[rep], &occ));
                 const int grid = std::min(hi - lo, std::max(1, occ) * 256);
                 int *queue = &((DevRun *)(B->ws + B->off_run))->queue[0];
                 float best_run = 1e30f;
                 for (int r = 0; r < 4; ++r) {
                     HIP_TRY(hipMemsetAsync(queue, 0, sizeof(int), stream));
                     HIP_TRY(hipEventRecord(e0, stream));
-                    HIP_TRY(launch_dedisp(t.dw, t.j, t.nw, t.sv, beams, items, lo, hi, queue, grid,
+                    HIP_TRY(launch_dedisp(t.dw, t.j, t.nw, t.sv, t.nb, beams, items, lo, hi, queue, grid,
                                           B->beam_lds[rep], stream));
                     HIP_TRY(hipEventRecord(e1, stream));
                     HIP_TRY(hipEventSynchronize(e1));
@@ -1248,8 +1270,8 @@ extern "C" spl_status spl_autotune(spl_batch *B, const uint8_t *const *d_blocks,
                     ref = sum;
                     have_ref = true;
                 } else if (sum != ref) {
-                    result = fail(SPL_E_INTERNAL, "tile shape (%d, %d, %d, %d) changed the DM transform", t.dw, t.j,
-                                  t.nw, t.cc);
+                    result = fail(SPL_E_INTERNAL, "tile shape (%d, %d, %d, %d buffer(s), %d) changed the DM transform",
+                                  t.dw, t.j, t.nw, t.nb, t.cc);
                     break;
                 }
                 if (best_run < best.ms) {

@@ -7,12 +7,16 @@
 
 namespace spl {
 
-constexpr int kDedispStageRows = 2;   // staged rows per wavefront and chunk (chan_chunk <= 2 * waves)
-// A staged row holds up to 1024 * sv bytes (sv = 16-byte vectors per lane, 1 or 2).
-bool dedisp_shape_supported(int dw, int j, int nw, int sv);
-hipError_t prepare_dedisp(int dw, int j, int nw, int sv, size_t lds_bytes, int *blocks_per_cu);
-hipError_t launch_dedisp(int dw, int j, int nw, int sv, const DevBeam *beams, const DedispItem *items, int item_lo,
-                         int item_hi, int *queue, int grid, size_t lds_bytes, hipStream_t s);
+// Staged rows per wavefront and chunk: chan_chunk <= dedisp_stage_rows(buffers) * waves
+// (one LDS buffer: two rows; two buffers: one row each, so two buffers of a 16-wavefront
+// tile hold what one buffer of 32 channels holds).
+constexpr int dedisp_stage_rows(int buffers) { return buffers == 2 ? 1 : 2; }
+// A staged row holds up to 1024 * sv bytes (sv = 16-byte vectors per lane, 1 or 2);
+// nbuf = LDS buffers (1 or 2).
+bool dedisp_shape_supported(int dw, int j, int nw, int sv, int nbuf);
+hipError_t prepare_dedisp(int dw, int j, int nw, int sv, int nbuf, size_t lds_bytes, int *blocks_per_cu);
+hipError_t launch_dedisp(int dw, int j, int nw, int sv, int nbuf, const DevBeam *beams, const DedispItem *items,
+                         int item_lo, int item_hi, int *queue, int grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_thresholds(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, int row_hi,
                              hipStream_t s);

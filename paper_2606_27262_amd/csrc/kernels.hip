@@ -62,9 +62,16 @@ __global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
 // 256 channels, then widened into int32 accumulators).  The LDS loads of the next
 // channel are in flight while the current one is summed, and the global loads of the
 // next chunk while the current chunk is summed.
-// SV: 16-byte input vectors staged per lane and row (rows of up to 1024*SV bytes);
-// each wavefront stages up to kDedispStageRows rows per chunk (chan_chunk <= that * NW).
-template <int DW, int J, int NW, int SV>
+// SV: 16-byte input vectors staged per lane and row (rows of up to 1024*SV bytes).
+// NBUF: LDS buffers.  With one, every chunk is staged between two barriers while no
+// wavefront sums.  With two (chunks of at most NW channels, one staged row per
+// wavefront), chunk k+1 is staged into the other buffer while chunk k is summed, behind
+// one barrier per chunk; half of the wavefronts stage before summing and half after,
+// so that the LDS writes and byte shifts of some wavefronts fall in the LDS waits of
+// the others (wavefronts w with w/4 odd stage first: with wavefronts dealt to the four
+// SIMDs in turn, each SIMD holds two of each kind).
+// Each wavefront stages up to dedisp_stage_rows(NBUF) rows per chunk.
+template <int DW, int J, int NW, int SV, int NBUF>
 __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ beams,
                                                     const DedispItem *__restrict__ items,
                                                     int item_lo, int item_hi, int *queue) {
@@ -72,7 +79,8 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
     __shared__ int s_item;
     const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
     constexpr int TD = NW * DW;
-    constexpr int kStageRows = kDedispStageRows;
+    static_assert(NBUF == 1 || NBUF == 2, "one or two LDS buffers");
+    constexpr int kStageRows = dedisp_stage_rows(NBUF);
     constexpr int kStageVecs = SV;
     constexpr int kTabRows = kStageRows * NW + 4;   // chan_chunk rows + 4 rows of prefetch padding
     constexpr int kTabRegs = (kTabRows * TD + 64 * NW - 1) / (64 * NW);
@@ -99,7 +107,8 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
         const uint8_t *__restrict__ x = B.x;
         const int cchunk = B.chan_chunk;
         const int nvec = R >> 4;   // 16-byte vectors per row and copy
-        int32_t *lds_tab = (int32_t *)(lds + 4 * quarter);
+        // buffer b: four copies of chan_chunk + 1 rows, then its slice of the offset table
+        const int buf_bytes = 4 * quarter + kTabRows * TD * 4;
 
         int32_t acc[DW][4 * J];
         uint32_t ae[DW][J], ao[DW][J];
@@ -146,24 +155,27 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
                 }
             }
         };
-        auto store_chunk = [&](int c0) {
+        auto store_chunk = [&](int c0, int b) {
             const int cc = min(cchunk, nch - c0);
+            uint8_t *bl = lds + b * buf_bytes;
+            int32_t *lds_tab = (int32_t *)(bl + 4 * quarter);
 #pragma unroll
             for (int e = 0; e < kTabRegs; ++e) {
                 const int idx = tid + 64 * NW * e;
                 const int r = idx / TD;
                 // rows past cc (read by the branch-free prefetch) point at row cc; the
-                // last register's entries beyond kTabRows rows lie outside the table
-                if (r < kTabRows) lds_tab[idx] = r < cc ? pt[e] + r * R : cc * R;
+                // last register's entries beyond kTabRows rows lie outside the table.
+                // Entries are byte offsets from the start of the LDS.
+                if (r < kTabRows) lds_tab[idx] = (r < cc ? pt[e] + r * R : cc * R) + b * buf_bytes;
             }
             if (cc & 1) {   // an odd chunk ends with a zero row (the pair's second row)
                 for (int v = tid; v < 4 * nvec; v += 64 * NW)
-                    *(uint4 *)(lds + (v / nvec) * quarter + cc * R + 16 * (v % nvec)) = make_uint4(0, 0, 0, 0);
+                    *(uint4 *)(bl + (v / nvec) * quarter + cc * R + 16 * (v % nvec)) = make_uint4(0, 0, 0, 0);
             }
 #pragma unroll
             for (int m = 0; m < kStageRows; ++m) {
                 const int r = wave + NW * m;
-                uint8_t *row = lds + r * R;
+                uint8_t *row = bl + r * R;
 #pragma unroll
                 for (int q = 0; q < kStageVecs; ++q) {
                     const int k = lane + 64 * q;
@@ -192,7 +204,8 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
         };
 
         const uint8_t *lane_lds = lds + 4 * lane;
-        const int32_t *wtab = lds_tab + wave * DW;
+        const int32_t *wtab0 = (const int32_t *)(lds + 4 * quarter) + wave * DW;
+        const int32_t *wtab = wtab0;   // the table of the buffer being summed
         // the wave's DW offsets of one staged row (16-byte LDS reads)
         auto read_tab = [&](int r, int32_t (&t)[DW]) {
             if constexpr (DW % 4 == 0) {
@@ -229,17 +242,10 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
                 }
         };
 
-        load_chunk(0);
-        for (int c0 = 0; c0 < nch; c0 += cchunk) {
-            const int cc = min(cchunk, nch - c0);
-            __syncthreads();          // the previous chunk is no longer read
-            store_chunk(c0);
-            if (c0 + cchunk < nch) load_chunk(c0 + cchunk);
-            __syncthreads();          // the chunk is staged
-
-            // channel pairs (an odd chunk ends with the zero row).  Software pipeline:
-            // while pair k is summed, the samples of pair k+1 and the offsets of pair
-            // k+2 are in flight (ping-pong buffers, branch-free steady state).
+        // the chunk's channel pairs (an odd chunk ends with the zero row).  Software
+        // pipeline: while pair k is summed, the samples of pair k+1 and the offsets of
+        // pair k+2 are in flight (ping-pong buffers, branch-free steady state).
+        auto sum_chunk = [&](const int cc) {
             const int np = (cc + 1) >> 1;
             int32_t ta[DW], tb[DW];
             uint32_t la[DW][J], lb[DW][J], na[DW][J], nb[DW][J];
@@ -270,8 +276,10 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
             } else {
                 add_rows(la, lb);
             }
-            // widen every 256 channels (chan_chunk is a power of two <= 256)
-            if (((c0 + cc) & 255) == 0 || c0 + cc >= nch) {
+        };
+        // widen the 16-bit fields every 256 channels (chan_chunk is a power of two <= 256)
+        auto widen = [&](const int c_end) {
+            if ((c_end & 255) == 0 || c_end >= nch) {
 #pragma unroll
                 for (int i = 0; i < DW; ++i)
 #pragma unroll
@@ -282,6 +290,42 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
                         acc[i][4 * j + 3] += (int32_t)(ao[i][j] >> 16);
                         ae[i][j] = ao[i][j] = 0u;
                     }
+            }
+        };
+
+        load_chunk(0);
+        if constexpr (NBUF == 1) {
+            for (int c0 = 0; c0 < nch; c0 += cchunk) {
+                const int cc = min(cchunk, nch - c0);
+                __syncthreads();          // the previous chunk is no longer read
+                store_chunk(c0, 0);
+                if (c0 + cchunk < nch) load_chunk(c0 + cchunk);
+                __syncthreads();          // the chunk is staged
+                sum_chunk(cc);
+                widen(c0 + cc);
+            }
+        } else {
+            __syncthreads();              // the previous item's last chunk is no longer read
+            store_chunk(0, 0);
+            if (cchunk < nch) load_chunk(cchunk);
+            __syncthreads();              // the first chunk is staged
+            const bool stage_first = ((wave >> 2) & 1) != 0;
+            int buf = 0;
+            for (int c0 = 0; c0 < nch; c0 += cchunk, buf ^= 1) {
+                const int cc = min(cchunk, nch - c0);
+                const bool more = c0 + cchunk < nch;
+                // the other buffer was last read for chunk c0 - cchunk, before the
+                // barrier that ended that chunk
+                auto stage_next = [&]() {
+                    store_chunk(c0 + cchunk, buf ^ 1);
+                    if (c0 + 2 * cchunk < nch) load_chunk(c0 + 2 * cchunk);
+                };
+                wtab = (const int32_t *)((const uint8_t *)wtab0 + buf * buf_bytes);
+                if (more && stage_first) stage_next();
+                sum_chunk(cc);
+                if (more && !stage_first) stage_next();
+                __syncthreads();          // the next chunk is staged, this one no longer read
+                widen(c0 + cc);
             }
         }
 
@@ -889,52 +933,57 @@ __global__ void k_mu_sigma(const int64_t *n, const int64_t *s1, const int64_t *s
 #define SPL_HIP_LAUNCH_CHECK() \
     do { hipError_t e__ = hipGetLastError(); if (e__ != hipSuccess) return e__; } while (0)
 
-template <int DW, int J, int NW, int SV>
+template <int DW, int J, int NW, int SV, int NBUF>
 static hipError_t prepare_dedisp_t(size_t lds_bytes, int *blocks_per_cu) {
     if (lds_bytes > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_dedisp<DW, J, NW, SV>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_dedisp<DW, J, NW, SV, NBUF>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
     }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_dedisp<DW, J, NW, SV>, 64 * NW, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_dedisp<DW, J, NW, SV, NBUF>, 64 * NW,
+                                                        lds_bytes);
 }
 
-template <int DW, int J, int NW, int SV>
+template <int DW, int J, int NW, int SV, int NBUF>
 static hipError_t launch_dedisp_t(const DevBeam *beams, const DedispItem *items, int item_lo, int item_hi,
                                   int *queue, int grid, size_t lds_bytes, hipStream_t s) {
-    hipLaunchKernelGGL((k_dedisp<DW, J, NW, SV>), dim3(grid), dim3(64 * NW), lds_bytes, s, beams, items, item_lo,
-                       item_hi, queue);
+    hipLaunchKernelGGL((k_dedisp<DW, J, NW, SV, NBUF>), dim3(grid), dim3(64 * NW), lds_bytes, s, beams, items,
+                       item_lo, item_hi, queue);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }
 
 // The compiled dedispersion shapes: (DM trials per wavefront, 256-sample groups per
-// lane, wavefronts per workgroup, 16-byte vectors staged per lane and row).
-#define SPL_DEDISP_SHAPES(X) \
-    X(2, 2, 8, 1) X(4, 1, 4, 1) X(4, 2, 4, 1) X(4, 1, 8, 1) X(4, 2, 8, 1) X(8, 1, 4, 1) \
-    X(8, 1, 8, 1) X(2, 2, 8, 2) X(4, 1, 4, 2) X(4, 1, 8, 2) X(4, 2, 8, 2) X(4, 1, 16, 1) X(4, 2, 16, 1) \
-    X(2, 2, 16, 1) X(2, 2, 16, 2)
+// lane, wavefronts per workgroup, 16-byte vectors staged per lane and row, LDS buffers).
+// Double buffering is compiled for the 16-wavefront shapes, which hold one workgroup
+// per CU, so that no other workgroup sums while one stages.
+#define SPL_DEDISP_SHAPES(X)                                                                                 \
+    X(2, 2, 8, 1, 1) X(4, 1, 4, 1, 1) X(4, 2, 4, 1, 1) X(4, 1, 8, 1, 1) X(4, 2, 8, 1, 1) X(8, 1, 4, 1, 1)   \
+    X(8, 1, 8, 1, 1) X(2, 2, 8, 2, 1) X(4, 1, 4, 2, 1) X(4, 1, 8, 2, 1) X(4, 2, 8, 2, 1) X(4, 1, 16, 1, 1)  \
+    X(4, 2, 16, 1, 1) X(2, 2, 16, 1, 1) X(2, 2, 16, 2, 1) X(4, 1, 16, 1, 2) X(4, 2, 16, 1, 2)              \
+    X(2, 2, 16, 1, 2) X(2, 2, 16, 2, 2)
 
-bool dedisp_shape_supported(int dw, int j, int nw, int sv) {
-#define SPL_X(a, b, c, d) if (dw == a && j == b && nw == c && sv == d) return true;
+bool dedisp_shape_supported(int dw, int j, int nw, int sv, int nbuf) {
+#define SPL_X(a, b, c, d, e) if (dw == a && j == b && nw == c && sv == d && nbuf == e) return true;
     SPL_DEDISP_SHAPES(SPL_X)
 #undef SPL_X
     return false;
 }
 
-hipError_t prepare_dedisp(int dw, int j, int nw, int sv, size_t lds_bytes, int *blocks_per_cu) {
-#define SPL_X(a, b, c, d) \
-    if (dw == a && j == b && nw == c && sv == d) return prepare_dedisp_t<a, b, c, d>(lds_bytes, blocks_per_cu);
+hipError_t prepare_dedisp(int dw, int j, int nw, int sv, int nbuf, size_t lds_bytes, int *blocks_per_cu) {
+#define SPL_X(a, b, c, d, e)                                          \
+    if (dw == a && j == b && nw == c && sv == d && nbuf == e)         \
+        return prepare_dedisp_t<a, b, c, d, e>(lds_bytes, blocks_per_cu);
     SPL_DEDISP_SHAPES(SPL_X)
 #undef SPL_X
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_dedisp(int dw, int j, int nw, int sv, const DevBeam *beams, const DedispItem *items, int item_lo,
-                         int item_hi, int *queue, int grid, size_t lds_bytes, hipStream_t s) {
-#define SPL_X(a, b, c, d)                                                                                     \
-    if (dw == a && j == b && nw == c && sv == d)                                                              \
-        return launch_dedisp_t<a, b, c, d>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
+hipError_t launch_dedisp(int dw, int j, int nw, int sv, int nbuf, const DevBeam *beams, const DedispItem *items,
+                         int item_lo, int item_hi, int *queue, int grid, size_t lds_bytes, hipStream_t s) {
+#define SPL_X(a, b, c, d, e)                                                                                 \
+    if (dw == a && j == b && nw == c && sv == d && nbuf == e)                                                \
+        return launch_dedisp_t<a, b, c, d, e>(beams, items, item_lo, item_hi, queue, grid, lds_bytes, s);
     SPL_DEDISP_SHAPES(SPL_X)
 #undef SPL_X
     return hipErrorInvalidValue;

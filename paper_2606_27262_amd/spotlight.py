@@ -69,7 +69,7 @@ class _BatchOpts(ctypes.Structure):
 
 class _Tiles(ctypes.Structure):
     _fields_ = [("dm_per_wave", ctypes.c_int32), ("time_groups", ctypes.c_int32),
-                ("chan_chunk", ctypes.c_int32), ("waves", ctypes.c_int32)]
+                ("chan_chunk", ctypes.c_int32), ("waves", ctypes.c_int32), ("buffers", ctypes.c_int32)]
 
 
 class _SmearingOpts(ctypes.Structure):
@@ -289,10 +289,10 @@ class Batch:
         t = _Tiles()
         _check(_lib.spl_batch_get_tiles(self._h, beam, ctypes.byref(t)))
         return {"dm_per_wave": t.dm_per_wave, "time_groups": t.time_groups, "chan_chunk": t.chan_chunk,
-                "waves": t.waves}
+                "waves": t.waves, "buffers": t.buffers}
 
-    def set_tiles(self, beam, dm_per_wave, time_groups, chan_chunk=0, waves=4):
-        t = _Tiles(int(dm_per_wave), int(time_groups), int(chan_chunk), int(waves))
+    def set_tiles(self, beam, dm_per_wave, time_groups, chan_chunk=0, waves=4, buffers=1):
+        t = _Tiles(int(dm_per_wave), int(time_groups), int(chan_chunk), int(waves), int(buffers))
         _check(_lib.spl_batch_set_tiles(self._h, beam, ctypes.byref(t)))
         if self.ws is not None:
             self.attach()

@@ -99,9 +99,25 @@ def test_batch_layout_host_only():
     assert persistent + scratch == n and scratch > need and persistent % 256 == 0
     assert persistent >= sum(p.info["ndm"] * p.info["nchans"] * 4 for p in plans)
     t = b.tiles(1)
-    assert t["chan_chunk"] >= 4 and t["dm_per_wave"] in (2, 4, 8, 16)
+    assert t["chan_chunk"] >= 4 and t["dm_per_wave"] in (2, 4, 8, 16) and t["buffers"] == 1
     with pytest.raises(spl.SplError):
         b.set_tiles(0, 3, 1)
+    # two LDS buffers: 16-wavefront shapes only, at most one staged row per wavefront
+    b.set_tiles(1, 4, 2, 16, waves=16, buffers=2)
+    assert b.tiles(1) == {"dm_per_wave": 4, "time_groups": 2, "chan_chunk": 16, "waves": 16, "buffers": 2}
+    b.set_tiles(0, 2, 2, 8, waves=16, buffers=2)
+    assert b.tiles(2) == b.tiles(0) == {"dm_per_wave": 2, "time_groups": 2, "chan_chunk": 8, "waves": 16,
+                                        "buffers": 2}   # beams of one plan share its tiling
+    for bad in (dict(waves=8, buffers=2), dict(waves=16, buffers=3), dict(waves=16, buffers=-1)):
+        with pytest.raises(spl.SplError):
+            b.set_tiles(1, 4, 2, 16, **bad)
+    with pytest.raises(spl.SplError):
+        b.set_tiles(1, 4, 2, 32, waves=16, buffers=2)
+    with pytest.raises(spl.SplError):   # two buffers of 16 rows of ~1.9 KB exceed the LDS
+        b.set_tiles(0, 2, 2, 16, waves=16, buffers=2)
+    assert b.tiles(1)["buffers"] == 2 and b.tiles(0)["chan_chunk"] == 8   # refusals keep the tiling
+    b.set_tiles(1, 4, 2, 32, waves=16)
+    assert b.tiles(1)["buffers"] == 1 and b.tiles(1)["chan_chunk"] == 32
 
 
 def _rand_cands(rng, n_beams, per_beam, clustered=True):

@@ -67,15 +67,16 @@ def test_traffic_only_for_the_counted_source_and_tiles(monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
     text = open(os.path.join(ROOT, "profiles", "dedisp_c3_hbm_counters.md")).read()
-    m = re.search(r"^counters: workload=c3 kernel=k_dedisp tiles=(\d+),(\d+),(\d+),(\d+) grid=\d+ "
+    m = re.search(r"^counters: workload=c3 kernel=k_dedisp tiles=(\d+),(\d+),(\d+),(\d+),(\d+) grid=\d+ "
                   r"fetch_bytes=(\d+) write_bytes=(\d+) dedisp_src_sha256=([0-9a-f]{64})$", text, re.M)
     assert m, "the summary carries one machine-readable counters line"
-    dw, j, nw, cc = (int(m.group(i)) for i in range(1, 5))
-    tiles = [{"dm_per_wave": dw, "time_groups": j, "waves": nw, "chan_chunk": cc}] * 2
-    want = {"fetch_bytes": int(m.group(5)), "write_bytes": int(m.group(6))}
-    monkeypatch.setattr(bench, "dedisp_source_hash", lambda: m.group(7))
+    dw, j, nw, cc, nbuf = (int(m.group(i)) for i in range(1, 6))
+    tiles = [{"dm_per_wave": dw, "time_groups": j, "waves": nw, "chan_chunk": cc, "buffers": nbuf}] * 2
+    want = {"fetch_bytes": int(m.group(6)), "write_bytes": int(m.group(7))}
+    monkeypatch.setattr(bench, "dedisp_source_hash", lambda: m.group(8))
     assert bench.counter_traffic("c3", tiles) == want
     assert bench.counter_traffic("c3", tiles[:1] + [dict(tiles[0], chan_chunk=cc // 2)]) is None
+    assert bench.counter_traffic("c3", tiles[:1] + [dict(tiles[0], buffers=3 - nbuf)]) is None
     assert bench.counter_traffic("c4", tiles) is None          # no summary for that workload
     monkeypatch.setattr(bench, "dedisp_source_hash", lambda: "0" * 64)
     assert bench.counter_traffic("c3", tiles) is None

@@ -218,22 +218,22 @@ def test_c2_full_size(spl, mode):
     compare(g, ref, rc)
 
 
-@pytest.mark.parametrize("tiles", ["default", "tuned"])
+@pytest.mark.parametrize("tiles", ["default", "one-buffer"])
 def test_c4_mixed_beams_full_size(spl, tiles):
     """The 32-beam workload's two plans at full size in one persistent, graph-captured
     batch: a 2048-channel 300-500 MHz beam (0.65536 ms, 32768 samples, 1024 trials to
     DM 1000, delays up to 44,946 samples) and a 4096-channel beam with 3072 trials to DM
     3000, each with ten pulses, RFI channels and zero-DM bursts.  Per beam the whole DM
     transform, the moments and the candidate list equal the oracle's own search, bit for
-    bit.  Default tiles, and the tiles the autotuner picks for these plans (16 wavefronts
-    of 2 trials with 16-channel chunks; 16 wavefronts of 4 trials with 32-channel
-    chunks)."""
+    bit.  Default tiles, and 16-wavefront tiles with one LDS buffer (2 trials with
+    16-channel chunks; 4 trials with 32-channel chunks); the 32-beam batch below runs the
+    two-buffer tiles the autotuner picks."""
     pds = [W.plan_band3_c4(), W.plan_band4_c4()]
     plans = [make_plan(spl, 0, 0, 0, None, 0, plan_dict=pd) for pd in pds]
     batch = spl.Batch(plans, mode=1)
-    if tiles == "tuned":
-        batch.set_tiles(0, 2, 2, 16, waves=16)
-        batch.set_tiles(1, 4, 2, 32, waves=16)
+    if tiles == "one-buffer":
+        batch.set_tiles(0, 2, 2, 16, waves=16, buffers=1)
+        batch.set_tiles(1, 4, 2, 32, waves=16, buffers=1)
         say("tiles", batch.tiles(0), batch.tiles(1))
     blocks = []
     for b, (pd, p) in enumerate(zip(pds, plans)):
@@ -250,7 +250,7 @@ def test_c4_mixed_beams_full_size(spl, tiles):
 
 C3_BEAMS = 24
 C3_GROUP = 4
-C3_TILES = (4, 2, 32, 16)    # trials per wavefront, time groups, channel chunk, wavefronts
+C3_TILES = (4, 2, 16, 16, 2)    # trials per wavefront, time groups, channel chunk, wavefronts, LDS buffers
 
 
 @pytest.fixture(scope="module")
@@ -270,9 +270,9 @@ def c3_batch(spl):
         if b % 8 == 7:
             say(f"c3 blocks generated: {b + 1}")
     batch = spl.Batch([p] * C3_BEAMS, mode=spl.MODE_PERSISTENT_GRAPH)
-    dw, j, cc, nw = C3_TILES
+    dw, j, cc, nw, nbuf = C3_TILES
     for b in range(C3_BEAMS):
-        batch.set_tiles(b, dw, j, cc, waves=nw)
+        batch.set_tiles(b, dw, j, cc, waves=nw, buffers=nbuf)
     cands = spl.new_candidates(1 << 20)
     cands, stats = batch.run(dev, cands)
     torch.cuda.synchronize()
@@ -339,8 +339,8 @@ def c4_batch(spl):
         _, x = W.c2_like_block_torch(pd, p.info["n_in"], 4, b, 10, dm_max_pulse=0.9 * W.dm_max(pd), zero_dm_rate=0.2)
         dev.append(x)
     batch = spl.Batch(plans, mode=spl.MODE_PERSISTENT_GRAPH, hit_capacity=1 << 28)
-    batch.set_tiles(0, 2, 2, 16, waves=16)
-    batch.set_tiles(1, 4, 2, 32, waves=16)
+    batch.set_tiles(0, 2, 2, 8, waves=16, buffers=2)
+    batch.set_tiles(1, 4, 2, 16, waves=16, buffers=2)
     cands = spl.new_candidates(1 << 22)
     cands, stats = batch.run(dev, cands)
     torch.cuda.synchronize()
@@ -380,8 +380,9 @@ def test_c4_batch_full_size(spl, c4_batch, group):
 @pytest.mark.parametrize("band", ["300-500", "300-500-fine", "550-750"])
 @pytest.mark.parametrize("nch", [512, 37])
 def test_tile_shapes_give_identical_results(spl, nch, band):
-    """Every compiled tile shape and staging depth the plan admits gives the oracle's
-    results (37 channels: odd chunks, padded with the zero row).  The 300-500 MHz plan
+    """Every compiled tile shape, staging depth and LDS buffer count the plan admits gives
+    the oracle's results (37 channels: odd chunks, padded with the zero row; with two
+    buffers and 4-channel chunks, ten chunks alternate between the buffers).  The 300-500 MHz plan
     (3 pc cm^-3 steps, ~67 samples of extra delay per trial at the lowest channel)
     admits only 16-trial tiles; with the 2048-channel band's sampling and trial step
     (~44 samples per trial) 32-trial tiles stage rows of 1-2 KB (two 16-byte vectors
@@ -403,20 +404,22 @@ def test_tile_shapes_give_identical_results(spl, nch, band):
               (8, 2, 4), (8, 1, 8), (16, 1, 4), (4, 1, 16), (4, 2, 16), (2, 2, 16))
     ran = set()
     for dw, j, nw in shapes:
-        for cc in (0, 1, 4, 32):
-            try:
-                batch.set_tiles(0, dw, j, cc, waves=nw)
-            except spl.SplError:
-                continue
-            say("tiles", dw, j, cc, batch.tiles(0))
-            g = gpu_run(spl, [p], [x], batch=batch)
-            compare(g, ref, rc)
-            ran.add((dw, j, nw))
+        for nbuf in ((1, 2) if nw == 16 else (1,)):
+            for cc in (0, 1, 4, 16, 32):
+                try:
+                    batch.set_tiles(0, dw, j, cc, waves=nw, buffers=nbuf)
+                except spl.SplError:
+                    continue
+                say("tiles", dw, j, cc, nbuf, batch.tiles(0))
+                g = gpu_run(spl, [p], [x], batch=batch)
+                compare(g, ref, rc)
+                ran.add((dw, j, nw, nbuf))
     say("shapes checked", sorted(ran))
     if band == "550-750":
-        assert {(4, 2, 8), (4, 2, 16), (4, 1, 16), (8, 1, 8), (2, 2, 16)} <= ran, ran
+        assert {(4, 2, 8, 1), (4, 2, 16, 1), (4, 1, 16, 1), (8, 1, 8, 1), (2, 2, 16, 1),
+                (4, 2, 16, 2), (4, 1, 16, 2), (2, 2, 16, 2)} <= ran, ran
     elif band == "300-500-fine":
-        assert {(4, 2, 8), (2, 2, 16)} <= ran, ran
+        assert {(4, 2, 8, 1), (2, 2, 16, 1), (2, 2, 16, 2)} <= ran, ran
     else:
         assert ran
 
