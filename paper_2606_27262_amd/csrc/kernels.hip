@@ -245,12 +245,19 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
         // the chunk's channel pairs (an odd chunk ends with the zero row).  Software
         // pipeline: while pair k is summed, the samples of pair k+1 and the offsets of
         // pair k+2 are in flight (ping-pong buffers, branch-free steady state).
-        auto sum_chunk = [&](const int cc) {
+        // da, db: the samples of a chunk's last channel pair.  sum_chunk reads them but
+        // leaves their adds to the caller: with two buffers they are added after the
+        // chunk's barrier, while the next chunk's first offsets are in flight (the reads
+        // completed before the barrier, so the buffer may be restaged meanwhile); every
+        // 256 channels, and at the end, they are added before the 16-bit fields widen.
+        uint32_t da[DW][J], db[DW][J];
+        auto sum_chunk = [&](const int cc, const bool have_def) {
             const int np = (cc + 1) >> 1;
             int32_t ta[DW], tb[DW];
             uint32_t la[DW][J], lb[DW][J], na[DW][J], nb[DW][J];
             read_tab(0, ta);
             read_tab(1, tb);
+            if (have_def) add_rows(da, db);
             load_row(ta, la);
             load_row(tb, lb);
             read_tab(2, ta);
@@ -272,9 +279,15 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
                 load_row(ta, na);
                 load_row(tb, nb);
                 add_rows(la, lb);
-                add_rows(na, nb);
+#pragma unroll
+                for (int i = 0; i < DW; ++i)
+#pragma unroll
+                    for (int j = 0; j < J; ++j) { da[i][j] = na[i][j]; db[i][j] = nb[i][j]; }
             } else {
-                add_rows(la, lb);
+#pragma unroll
+                for (int i = 0; i < DW; ++i)
+#pragma unroll
+                    for (int j = 0; j < J; ++j) { da[i][j] = la[i][j]; db[i][j] = lb[i][j]; }
             }
         };
         // widen the 16-bit fields every 256 channels (chan_chunk is a power of two <= 256)
@@ -301,7 +314,8 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
                 store_chunk(c0, 0);
                 if (c0 + cchunk < nch) load_chunk(c0 + cchunk);
                 __syncthreads();          // the chunk is staged
-                sum_chunk(cc);
+                sum_chunk(cc, false);
+                add_rows(da, db);          // one buffer: no deferral (no VGPRs to spare)
                 widen(c0 + cc);
             }
         } else {
@@ -311,6 +325,7 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
             __syncthreads();              // the first chunk is staged
             const bool stage_first = ((wave >> 2) & 1) != 0;
             int buf = 0;
+            bool have_def = false;
             for (int c0 = 0; c0 < nch; c0 += cchunk, buf ^= 1) {
                 const int cc = min(cchunk, nch - c0);
                 const bool more = c0 + cchunk < nch;
@@ -322,10 +337,13 @@ __global__ __launch_bounds__(64 * NW) void k_dedisp(const DevBeam *__restrict__ 
                 };
                 wtab = (const int32_t *)((const uint8_t *)wtab0 + buf * buf_bytes);
                 if (more && stage_first) stage_next();
-                sum_chunk(cc);
+                sum_chunk(cc, have_def);
                 if (more && !stage_first) stage_next();
                 __syncthreads();          // the next chunk is staged, this one no longer read
-                widen(c0 + cc);
+                const int c_end = c0 + cc;
+                have_def = !((c_end & 255) == 0 || c_end >= nch);
+                if (!have_def) add_rows(da, db);
+                widen(c_end);
             }
         }
 
