@@ -207,7 +207,10 @@ typedef struct spl_run_stats {
     int64_t n_hits;                          /* boxcar hits above threshold (true count) */
     int64_t n_candidates;                    /* candidates after the peak filters (true count) */
     int64_t n_after_stencil[SPL_MAX_STENCILS];
-    int32_t hit_overflow;                    /* 1: n_hits exceeded the hit capacity */
+    int32_t hit_overflow;                    /* 1: n_hits exceeded the hit capacity; 2: the
+                                                ordered hit compaction gave up waiting for a
+                                                chunk's predecessors (not expected: the hit
+                                                list and candidates are then invalid) */
     int32_t cand_overflow;                   /* 1: n_candidates exceeded the caller's capacity */
 } spl_run_stats;
 

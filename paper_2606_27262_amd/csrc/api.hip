@@ -276,7 +276,7 @@ struct spl_batch {
     size_t off_beams = 0, off_items = 0;
     std::vector<size_t> off_X, off_S, off_mu, off_sigma, off_T;   // per beam
     size_t off_S_all = 0, bytes_S_all = 0;
-    size_t off_counts = 0, off_chunk_off = 0, off_block_sums = 0, off_row_start = 0;
+    size_t off_chunk_off = 0, off_block_sums = 0, off_row_start = 0, off_box_status = 0;
     size_t off_hits = 0, off_alive0 = 0, off_alive1 = 0, off_pos = 0, off_run = 0;
     size_t off_nms_blk = 0;   // block index of the hit rows [n_rows][nms_nblk] int32
     size_t off_hit_t = 0;     // the hits' times, packed int32 [hit_cap]
@@ -544,9 +544,9 @@ static spl_status build_layout(spl_batch *B) {
         B->off_sigma[b] = take((size_t)p.ndm * p.nseg * sizeof(double));
         B->off_T[b] = take((size_t)p.ndm * p.nseg * p.widths.size() * sizeof(int32_t));
     }
-    B->off_counts = take((size_t)B->n_chunks * sizeof(int32_t));
     B->off_chunk_off = take((size_t)B->n_chunks * sizeof(int64_t));
-    B->n_block_sums = std::max(scan_blocks(B->n_chunks), scan_blocks(B->hit_cap)) + 1;
+    B->off_box_status = take(((size_t)B->n_chunks + 1) * sizeof(uint64_t));
+    B->n_block_sums = scan_blocks(B->hit_cap) + 1;
     B->off_block_sums = take((size_t)B->n_block_sums * sizeof(int64_t));
     B->off_row_start = take((size_t)(B->n_rows + 1) * sizeof(int64_t));
     {
@@ -801,9 +801,9 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
     DevRun *run = (DevRun *)(B->ws + B->off_run);
     const int row_lo = B->row_base[b_lo], row_hi = B->row_base[b_hi];
     const int chunk_lo = B->chunk_base[b_lo], chunk_hi = B->chunk_base[b_hi];
-    int32_t *counts = (int32_t *)(B->ws + B->off_counts) + chunk_lo;
     int64_t *chunk_off = (int64_t *)(B->ws + B->off_chunk_off) + chunk_lo;
     int64_t *block_sums = (int64_t *)(B->ws + B->off_block_sums);
+    uint64_t *box_status = (uint64_t *)(B->ws + B->off_box_status) + chunk_lo;
     int64_t *row_start = (int64_t *)(B->ws + B->off_row_start) + row_lo;
     Hit *hits = (Hit *)(B->ws + B->off_hits);
     uint8_t *alive[2] = {(uint8_t *)(B->ws + B->off_alive0), (uint8_t *)(B->ws + B->off_alive1)};
@@ -836,7 +836,7 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
     StageTimer t_th(B, s, SPL_STAGE_THRESHOLDS);
     HIP_TRY(launch_thresholds(beams, b_lo, b_hi, row_lo, row_hi, s));
     HIP_TRY(t_th.stop());
-    // 3. boxcar hits: count, scan, emit in (row, t) order
+    // 3. boxcar hits in (row, t) order, each chunk's offset by look-back over the earlier chunks
     int w_max = 1;
     int max_nst = 0;
     for (int b = b_lo; b < b_hi; ++b) {
@@ -844,11 +844,10 @@ static spl_status enqueue_range(spl_batch *B, int b_lo, int b_hi, bool persisten
         max_nst = std::max(max_nst, B->plans[b]->nst);
     }
     StageTimer t_bc(B, s, SPL_STAGE_BOXCAR);
-    HIP_TRY(launch_boxcar(false, beams, b_lo, b_hi, chunk_lo, chunk_hi, w_max, counts, nullptr, nullptr, 0, s));
-    HIP_TRY(launch_scan_i32(counts, nullptr, chunk_hi - chunk_lo, block_sums, chunk_off, &run->n_hits, s));
+    HIP_TRY(launch_boxcar_one_pass(beams, b_lo, b_hi, chunk_lo, chunk_hi, w_max, box_status, chunk_off, hits, cap,
+                                   &run->n_hits, &run->box_stall, s));
     HIP_TRY(launch_row_start(beams, b_lo, b_hi, row_lo, row_hi, chunk_lo, chunk_off, &run->n_hits, cap, row_start,
                              s));
-    HIP_TRY(launch_boxcar(true, beams, b_lo, b_hi, chunk_lo, chunk_hi, w_max, counts, chunk_off, hits, cap, s));
     HIP_TRY(t_bc.stop());
     // 4. peak filters, then ordered compaction into candidate records
     StageTimer t_pk(B, s, SPL_STAGE_PEAKS);

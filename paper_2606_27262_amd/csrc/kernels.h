@@ -20,12 +20,13 @@ hipError_t launch_dedisp(int dw, int j, int nw, int sv, int nbuf, const DevBeam 
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_thresholds(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, int row_hi,
                              hipStream_t s);
-hipError_t launch_boxcar(bool emit, const DevBeam *beams, int beam_lo, int beam_hi, int chunk_lo, int chunk_hi,
-                         int w_max, int32_t *counts, const int64_t *offsets, Hit *hits, int64_t cap,
-                         hipStream_t s);
+// Boxcar hits of chunks [chunk_lo, chunk_hi) in one launch (decoupled look-back): status
+// holds chunk_hi - chunk_lo + 1 words (cleared here), offsets gets each chunk's first hit
+// index, *n_total the range's hit count; *stall is set if a look-back gave up.
+hipError_t launch_boxcar_one_pass(const DevBeam *beams, int beam_lo, int beam_hi, int chunk_lo, int chunk_hi,
+                                  int w_max, uint64_t *status, int64_t *offsets, Hit *hits, int64_t cap,
+                                  int64_t *n_total, int32_t *stall, hipStream_t s);
 int scan_blocks(int64_t n_max);
-hipError_t launch_scan_i32(const int32_t *in, const int64_t *n_dev, int64_t n_max, int64_t *block_sums,
-                           int64_t *out, int64_t *total, hipStream_t s);
 hipError_t launch_scan_u8(const uint8_t *in, const int64_t *n_dev, int64_t n_max, int64_t *block_sums,
                           int64_t *out, int64_t *total, hipStream_t s);
 hipError_t launch_row_start(const DevBeam *beams, int beam_lo, int beam_hi, int row_lo, int row_hi, int chunk_lo,

@@ -5,7 +5,8 @@
 //  k_thresholds  exact moments, mean / sigma per (DM row, segment) and the smallest
 //                boxcar sum reaching the S/N threshold per width (single pulse search)
 //  k_boxcar      boxcar filters via wrapping 32-bit prefix sums, threshold test, best
-//                width; counts hits per tile, then emits them in (row, t) order
+//                width; writes the hits in (row, t) order, each tile's offset found by
+//                decoupled look-back over the tiles before it
 //  k_nms         peak filter over the sorted hit list (3x3, then 11x11 windows)
 //  k_scan_*      device-wide exclusive scans used for ordered compaction
 //  k_scatter     candidate records from the peak-filter survivors
@@ -447,21 +448,79 @@ __global__ __launch_bounds__(kThreads) void k_thresholds(const DevBeam *__restri
 // Thread k evaluates the 4 consecutive samples 4k + 1024q + {0..3} of each quarter q, so
 // its LDS reads are 16-byte vectors at consecutive addresses across lanes.  Hits of a
 // sample form a bitmask over the widths; only samples with hits evaluate the binary64
-// S/N to pick the best width.  EMIT = false counts hits per chunk; EMIT = true writes them
-// at the chunk's offset (in t order) and skips chunks without hits.
+// S/N to pick the best width.  One launch counts and writes the hits in (row, t) order:
+// workgroups take chunks in order from a ticket counter, publish their hit count, find
+// their offset by looking back over the counts and prefixes their predecessors
+// published (decoupled look-back), and write their hits from registers.
 __device__ __forceinline__ uint32_t lds_u32(const uint32_t *S, int i) { return S[i]; }
 
-template <bool EMIT>
+// Look-back status words: flag in the top two bits, value below.
+constexpr uint64_t kStatAggregate = 1ull << 62;   // the chunk's own hit count
+constexpr uint64_t kStatInclusive = 2ull << 62;   // hits of every chunk up to and including it
+constexpr uint64_t kStatValue = (1ull << 62) - 1;
+constexpr int kLookbackPolls = 1 << 16;           // gives up (and reports it) after this many polls:
+                                                  // over 60 ms, against ~25 us per chunk
+
+// Run by one wavefront of the workgroup holding chunk idx with tot hits: publishes tot,
+// then sums the published values of the predecessors, nearest first, 64 at a time, up to
+// the nearest one that has published its inclusive prefix; publishes its own inclusive
+// prefix and returns the exclusive one.  A predecessor took its ticket earlier, so it
+// runs and publishes without waiting on this workgroup; the poll limit only guards
+// against a broken invariant (*stall is set and the offset is wrong).
+__device__ int64_t box_lookback(uint64_t *status, int idx, int64_t tot, int32_t *stall) {
+    const int lane = lane_id();
+    if (lane == 0)
+        __hip_atomic_store(&status[idx], (idx == 0 ? kStatInclusive : kStatAggregate) | (uint64_t)tot,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int64_t excl = 0;
+    int j = idx - 1;   // the nearest predecessor not summed yet
+    int polls = 0;
+    while (j >= 0) {
+        const int k = j - lane;
+        // before chunk 0 reads as an inclusive prefix of 0
+        const uint64_t v = k >= 0 ? __hip_atomic_load(&status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                  : kStatInclusive;
+        const uint64_t flag = v >> 62;
+        const uint64_t waiting = __ballot(flag == 0);
+        const uint64_t inclusive = __ballot(flag == 2);
+        const int first = inclusive ? __builtin_ctzll(inclusive) : 64;
+        const uint64_t need = first >= 63 ? ~0ull : (2ull << first) - 1;   // lanes 0 .. first
+        if (waiting & need) {
+            if (++polls > kLookbackPolls) {
+                if (lane == 0) atomicOr(stall, 1);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += wave_sum<int64_t>(lane <= first ? (int64_t)(v & kStatValue) : 0);
+        if (first < 64) break;
+        j -= 64;
+    }
+    if (lane == 0 && idx > 0)
+        __hip_atomic_store(&status[idx], kStatInclusive | (uint64_t)(excl + tot), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
+}
+
+// status: n_chunks + 1 zeroed words (the last is the ticket counter); offsets gets each
+// chunk's first hit index, n_total the range's hit count and stall the look-back's
+// give-up flag.
 __global__ __launch_bounds__(kThreads) void k_boxcar(const DevBeam *__restrict__ beams, int beam_lo,
-                                                     int beam_hi, int chunk_lo, int32_t *counts,
-                                                     const int64_t *offsets, Hit *hits, int64_t cap) {
+                                                     int beam_hi, int chunk_lo, int n_chunks, int64_t *offsets,
+                                                     Hit *hits, int64_t cap, uint64_t *status, int64_t *n_total,
+                                                     int32_t *stall) {
     extern __shared__ __align__(16) uint32_t S[];
     __shared__ uint32_t sh32[2][kThreads / 64];
     __shared__ int64_t sh64[kThreads / 64];
+    __shared__ int64_t s_base;
+    __shared__ int s_idx;
     constexpr int kQ = kBoxTile / 1024;   // quarters of 1024 samples
     const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-    if (EMIT && counts[blockIdx.x] == 0) return;   // uniform: no hits in this chunk
-    const int g = chunk_lo + blockIdx.x;
+    if (tid == 0) s_idx = (int)atomicAdd((unsigned long long *)&status[n_chunks], 1ull);
+    __syncthreads();
+    const int idx = s_idx;   // tickets follow the order in which workgroups start
+    const int g = chunk_lo + idx;
     const DevBeam &B = beams[beam_of_chunk(beams, beam_lo, beam_hi, g)];
     const int local = g - B.chunk_base;
     const int d = local / B.nchunk_t;
@@ -523,7 +582,6 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const DevBeam *__restrict__
 
     const int nw = B.nw, L = B.L, nseg = B.nseg;
     const int tend = min(t0 + kBoxTile, B.n_out);   // owned samples of this chunk: [t0, tend)
-    int cnt = 0;
     uint32_t mask[kQ][4];
 #pragma unroll
     for (int q = 0; q < kQ; ++q)
@@ -565,17 +623,6 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const DevBeam *__restrict__
             }
         }
     }
-#pragma unroll
-    for (int q = 0; q < kQ; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) cnt += mask[q][e] ? 1 : 0;
-
-    if (!EMIT) {
-        int64_t tot;
-        (void)block_exclusive_scan<int64_t>(cnt, &tot, sh64);
-        if (tid == 0) counts[blockIdx.x] = (int32_t)tot;
-        return;
-    }
     // hits are emitted in t order: quarter by quarter, thread by thread within a quarter.
     // The four per-quarter counts (<= 1024 each) are scanned together in 16-bit fields.
     uint64_t packed = 0;
@@ -589,7 +636,19 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const DevBeam *__restrict__
     uint64_t ptot;
     const uint64_t pex = block_exclusive_scan<uint64_t>(packed, &ptot, (uint64_t *)sh64);
     const int row = B.row_base + d;
-    int64_t qbase = offsets[blockIdx.x];
+    int64_t tot = 0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) tot += (int64_t)((ptot >> (16 * q)) & 0xFFFFu);
+    if (wave == 0) {
+        const int64_t excl = box_lookback(status, idx, tot, stall);
+        if (lane == 0) {
+            s_base = excl;
+            offsets[idx] = excl;
+            if (idx == n_chunks - 1) *n_total = excl + tot;
+        }
+    }
+    __syncthreads();
+    int64_t qbase = s_base;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         int64_t pos = qbase + (int64_t)((pex >> (16 * q)) & 0xFFFFu);
@@ -910,7 +969,8 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const DevBeam *__restrict_
 __global__ void k_pass_end(DevRun *run, spl_run_stats *stats, int64_t hit_cap, int nst) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     stats->n_hits += run->n_hits;
-    if (run->n_hits > hit_cap) stats->hit_overflow = 1;
+    if (run->n_hits > hit_cap && stats->hit_overflow == 0) stats->hit_overflow = 1;
+    if (run->box_stall) stats->hit_overflow = 2;
     for (int k = 0; k < nst; ++k) {
         stats->n_after_stencil[k] += run->n_alive[k];
         run->n_alive[k] = 0;
@@ -1024,20 +1084,18 @@ hipError_t launch_thresholds(const DevBeam *beams, int beam_lo, int beam_hi, int
     return hipSuccess;
 }
 
-hipError_t launch_boxcar(bool emit, const DevBeam *beams, int beam_lo, int beam_hi, int chunk_lo, int chunk_hi,
-                         int w_max, int32_t *counts, const int64_t *offsets, Hit *hits, int64_t cap,
-                         hipStream_t s) {
+hipError_t launch_boxcar_one_pass(const DevBeam *beams, int beam_lo, int beam_hi, int chunk_lo, int chunk_hi,
+                                  int w_max, uint64_t *status, int64_t *offsets, Hit *hits, int64_t cap,
+                                  int64_t *n_total, int32_t *stall, hipStream_t s) {
     const int n = chunk_hi - chunk_lo;
-    if (n <= 0) return hipSuccess;
-    // both passes read the per-chunk counts; the emitting pass also needs offsets and hits
-    if (!counts || (emit && (!offsets || !hits))) return hipErrorInvalidValue;
+    if (!status || !offsets || !hits || !n_total || !stall) return hipErrorInvalidValue;
+    if (n <= 0) return launch_fill_u64((uint64_t *)n_total, 1, 0, s);
+    // the look-back words of the range and its ticket counter start at zero
+    hipError_t e = launch_fill_u64(status, (int64_t)n + 1, 0, s);
+    if (e != hipSuccess) return e;
     const size_t lds = (size_t)(kBoxTile + w_max + 8) * sizeof(uint32_t);
-    if (emit)
-        hipLaunchKernelGGL(k_boxcar<true>, dim3(n), dim3(kThreads), lds, s, beams, beam_lo, beam_hi, chunk_lo,
-                           counts, offsets, hits, cap);
-    else
-        hipLaunchKernelGGL(k_boxcar<false>, dim3(n), dim3(kThreads), lds, s, beams, beam_lo, beam_hi, chunk_lo,
-                           counts, offsets, hits, cap);
+    hipLaunchKernelGGL(k_boxcar, dim3(n), dim3(kThreads), lds, s, beams, beam_lo, beam_hi, chunk_lo, n, offsets,
+                       hits, cap, status, n_total, stall);
     SPL_HIP_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1058,10 +1116,6 @@ static hipError_t launch_scan_t(const T *in, const int64_t *n_dev, int64_t n_max
     return hipSuccess;
 }
 
-hipError_t launch_scan_i32(const int32_t *in, const int64_t *n_dev, int64_t n_max, int64_t *block_sums,
-                           int64_t *out, int64_t *total, hipStream_t s) {
-    return launch_scan_t<int32_t>(in, n_dev, n_max, block_sums, out, total, s);
-}
 hipError_t launch_scan_u8(const uint8_t *in, const int64_t *n_dev, int64_t n_max, int64_t *block_sums,
                           int64_t *out, int64_t *total, hipStream_t s) {
     return launch_scan_t<uint8_t>(in, n_dev, n_max, block_sums, out, total, s);

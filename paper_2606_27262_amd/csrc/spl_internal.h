@@ -76,7 +76,7 @@ struct DevRun {
     int64_t n_surv;        // survivors of the first peak filter (the compacted list's length)
     int32_t hit_overflow;
     int32_t queue[kMaxShapeGroups];  // persistent-kernel work counters
-    int32_t pad;
+    int32_t box_stall;     // 1: a boxcar look-back gave up waiting (hit offsets invalid)
 };
 
 }  // namespace spl
