@@ -461,17 +461,21 @@ constexpr uint64_t kStatValue = (1ull << 62) - 1;
 constexpr int kLookbackPolls = 1 << 16;           // gives up (and reports it) after this many polls:
                                                   // over 60 ms, against ~25 us per chunk
 
-// Run by one wavefront of the workgroup holding chunk idx with tot hits: publishes tot,
-// then sums the published values of the predecessors, nearest first, 64 at a time, up to
-// the nearest one that has published its inclusive prefix; publishes its own inclusive
+// The hit count tot of chunk idx, published as soon as it is known (chunk 0's count is
+// its inclusive prefix).
+__device__ __forceinline__ void box_publish_count(uint64_t *status, int idx, int64_t tot) {
+    __hip_atomic_store(&status[idx], (idx == 0 ? kStatInclusive : kStatAggregate) | (uint64_t)tot,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Run by one wavefront of the workgroup holding chunk idx (count tot, already published):
+// sums the published values of the predecessors, nearest first, 64 at a time, up to the
+// nearest one that has published its inclusive prefix; publishes its own inclusive
 // prefix and returns the exclusive one.  A predecessor took its ticket earlier, so it
 // runs and publishes without waiting on this workgroup; the poll limit only guards
 // against a broken invariant (*stall is set and the offset is wrong).
 __device__ int64_t box_lookback(uint64_t *status, int idx, int64_t tot, int32_t *stall) {
     const int lane = lane_id();
-    if (lane == 0)
-        __hip_atomic_store(&status[idx], (idx == 0 ? kStatInclusive : kStatAggregate) | (uint64_t)tot,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int64_t excl = 0;
     int j = idx - 1;   // the nearest predecessor not summed yet
     int polls = 0;
@@ -639,6 +643,36 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const DevBeam *__restrict__
     int64_t tot = 0;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) tot += (int64_t)((ptot >> (16 * q)) & 0xFFFFu);
+    if (tid == 0) box_publish_count(status, idx, tot);
+
+    // best width of every hit (widths in ascending order; an equal S/N keeps the smaller
+    // width) while the earlier chunks finish: its mask keeps only that width's bit
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            uint32_t m = mask[q][e];
+            if (!m || (m & (m - 1)) == 0) continue;   // no hit, or a single width
+            const int li = 1024 * q + 4 * tid + e, t = t0 + li;
+            const size_t ms = (size_t)d * nseg + t / L;
+            const double mu = B.mu[ms], sigma = B.sigma[ms];
+            const uint32_t lo = S[li];
+            double best = 0.0;
+            int bj = -1;
+            while (m) {
+                const int j = __builtin_ctz(m);
+                m &= m - 1;
+                const int w = B.widths[j];
+                const double sn = snr_of((int32_t)(S[li + w] - lo), w, mu, sigma);
+                if (bj < 0 || sn > best) {
+                    best = sn;
+                    bj = j;
+                }
+            }
+            mask[q][e] = 1u << bj;
+        }
+    }
+
     if (wave == 0) {
         const int64_t excl = box_lookback(status, idx, tot, stall);
         if (lane == 0) {
@@ -655,33 +689,19 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const DevBeam *__restrict__
         qbase += (int64_t)((ptot >> (16 * q)) & 0xFFFFu);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            uint32_t m = mask[q][e];
+            const uint32_t m = mask[q][e];   // the best width's bit only
             if (!m) continue;
-            const int li = 1024 * q + 4 * tid + e, t = t0 + li;
-            const size_t idx = (size_t)d * nseg + t / L;
-            const double mu = B.mu[idx], sigma = B.sigma[idx];
-            const uint32_t lo = S[li];
-            double best = 0.0;
-            int bw = 0, bB = 0;
-            while (m) {   // widths in ascending order; an equal S/N keeps the smaller width
-                const int j = __builtin_ctz(m);
-                m &= m - 1;
-                const int w = B.widths[j];
-                const int32_t Bw = (int32_t)(S[li + w] - lo);
-                const double sn = snr_of(Bw, w, mu, sigma);
-                if (bw == 0 || sn > best) {
-                    best = sn;
-                    bw = w;
-                    bB = Bw;
-                }
-            }
             if (pos < cap) {
+                const int li = 1024 * q + 4 * tid + e, t = t0 + li;
+                const size_t ms = (size_t)d * nseg + t / L;
+                const int w = B.widths[__builtin_ctz(m)];
+                const int32_t Bw = (int32_t)(S[li + w] - S[li]);
                 Hit h;
                 h.row = row;
                 h.t = t;
-                h.w = bw;
-                h.B = bB;
-                h.snr = best;
+                h.w = w;
+                h.B = Bw;
+                h.snr = snr_of(Bw, w, B.mu[ms], B.sigma[ms]);   // the same binary64 value as above
                 hits[pos] = h;
             }
             ++pos;
