@@ -1140,11 +1140,21 @@ std::vector<std::pair<std::string, TuneEntry>> read_cache(const char *path) {
     if (!path) return out;
     FILE *f = fopen(path, "r");
     if (!f) return out;
-    char line[512], sig[256], extra[2];
+    char line[512], sig[256];
     while (fgets(line, sizeof line, f)) {
+        // exactly seven whitespace-separated fields, the six numbers integers but the last
+        int fields = 0;
+        for (const char *c = line; *c;) {
+            while (*c == ' ' || *c == '\t' || *c == '\n' || *c == '\r') ++c;
+            if (!*c) break;
+            ++fields;
+            while (*c && *c != ' ' && *c != '\t' && *c != '\n' && *c != '\r') ++c;
+        }
         TuneEntry e;
-        if (sscanf(line, "%255s %d %d %d %d %d %lf %1s", sig, &e.t.dw, &e.t.j, &e.t.nw, &e.t.nb, &e.t.cc, &e.ms,
-                   extra) == 7)
+        int used = 0;
+        if (fields == 7 && sscanf(line, "%255s %d %d %d %d %d %lf%n", sig, &e.t.dw, &e.t.j, &e.t.nw, &e.t.nb,
+                                  &e.t.cc, &e.ms, &used) == 7 &&
+            strspn(line + used, " \t\r\n") == strlen(line + used))
             out.emplace_back(sig, e);
     }
     fclose(f);

@@ -498,6 +498,24 @@ def test_autotune_keeps_results_and_caches(spl, tmp_path):
     # a second batch reuses the cached choice
     b2 = spl.Batch([p])
     assert b2.autotune([tb[0]], cache_path=str(cache))[0] == tiles[0]
+    # the cache line holds trials/wave, time groups, waves, LDS buffers, channel chunk, ms
+    sig, *fields = cache.read_text().split()
+    t = tiles[0]
+    assert [int(v) for v in fields[:5]] == [t["dm_per_wave"], t["time_groups"], t["waves"], t["buffers"],
+                                            t["chan_chunk"]]
+    # a line of six fields (no buffer count) is dropped and the plan tuned again: the
+    # batch's tiles then come from this tuning (timing decides between close shapes), and
+    # the file holds one seven-field line that names them
+    old = tmp_path / "old.txt"
+    old.write_text(f"{sig} 8 1 8 16 1.0\n")
+    b3 = spl.Batch([p])
+    t3 = b3.autotune([tb[0]], cache_path=str(old))[0]
+    lines = old.read_text().splitlines()
+    assert len(lines) == 1, lines
+    f3 = lines[0].split()
+    assert len(f3) == 7 and f3[0] == sig, lines
+    assert [int(v) for v in f3[1:6]] == [t3["dm_per_wave"], t3["time_groups"], t3["waves"], t3["buffers"],
+                                         t3["chan_chunk"]]
 
 
 def test_graph_batch_follows_new_block_pointers(spl):
