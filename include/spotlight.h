@@ -293,7 +293,8 @@ spl_status spl_batch_moments(const spl_batch *batch, int32_t beam, const int64_t
 /* Dedispersion tiling of one beam: a workgroup of `waves` wavefronts sums a tile of
  * waves*dm_per_wave DM trials by time_groups*256 samples; chan_chunk channels are staged
  * in LDS per step (a power of two in [2, 2*waves] with one buffer, [2, waves] with two;
- * 0: the largest that fits a 64 KiB budget).  With two LDS buffers (16-wavefront tiles
+ * 0: the largest that fits the LDS budget, 64 KiB for 4 and 8 wavefronts, which share a
+ * CU with other workgroups, and the whole LDS for 16).  With two LDS buffers (16-wavefront tiles
  * only) the next chunk is staged while the current one is summed.  The compiled shapes
  * (dm_per_wave, time_groups, waves[, buffers]): (2,2,8) (4,1,4) (4,2,4) (4,1,8) (4,2,8)
  * (8,1,4) (8,1,8), and (4,1,16) (4,2,16) (2,2,16) with one or two buffers. */

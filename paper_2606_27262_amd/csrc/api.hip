@@ -399,9 +399,9 @@ static void choose_chunk(PlanLayout &L, size_t lds_budget) {
     const int rmax = *std::max_element(L.row_bytes.begin(), L.row_bytes.end());
     int cc = L.tiles.cc;
     if (cc <= 0) {
+        const int tab_rows = dedisp_stage_rows(L.tiles.nb) * L.tiles.nw + 4;   // as the kernel sizes it
         cc = dedisp_stage_rows(L.tiles.nb) * L.tiles.nw;
-        while (cc > 2 &&
-               L.tiles.nb * ((size_t)4 * (cc + 1) * rmax + (size_t)(cc + 4) * 4 * L.td) > lds_budget)
+        while (cc > 2 && L.tiles.nb * ((size_t)4 * (cc + 1) * rmax + (size_t)tab_rows * 4 * L.td) > lds_budget)
             cc >>= 1;
     }
     int p2 = 2;   // at least 2: an odd last chunk is padded with a zero row
@@ -434,7 +434,8 @@ static spl_status build_layout(spl_batch *B) {
     for (auto &L : B->layouts) {
         spl_status st = layout_plan(L);
         if (st != SPL_OK) return st;
-        choose_chunk(L, 64 * 1024);
+        // 4- and 8-wavefront workgroups share a CU (64 KiB each); a 16-wavefront one holds it
+        choose_chunk(L, L.tiles.nw >= 16 ? 160 * 1024 - 256 : 64 * 1024);
     }
     const int nb = B->nb;
     B->row_base.assign(nb + 1, 0);

@@ -118,6 +118,13 @@ def test_batch_layout_host_only():
     assert b.tiles(1)["buffers"] == 2 and b.tiles(0)["chan_chunk"] == 8   # refusals keep the tiling
     b.set_tiles(1, 4, 2, 32, waves=16)
     assert b.tiles(1)["buffers"] == 1 and b.tiles(1)["chan_chunk"] == 32
+    # chan_chunk 0: the largest that fits; a 16-wavefront workgroup has the whole LDS
+    b.set_tiles(1, 4, 2, 0, waves=16)
+    assert b.tiles(1)["chan_chunk"] == 32
+    b.set_tiles(1, 4, 2, 0, waves=16, buffers=2)
+    assert b.tiles(1)["chan_chunk"] == 16
+    b.set_tiles(0, 2, 2, 0, waves=16, buffers=2)   # rows of ~1.9 KB: two buffers of 8 channels
+    assert b.tiles(0)["chan_chunk"] == 8
 
 
 def _rand_cands(rng, n_beams, per_beam, clustered=True):
