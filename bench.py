@@ -710,8 +710,8 @@ def main():
                     help="per-band logit thresholds of the ranker path (JSON written by train_ranker)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs each GPU's share of beams "
-              "independently and has no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: each GPU searches its own share of beams "
+              "independently and there is no multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -42,7 +42,7 @@ typedef int32_t spl_status;
 #define SPL_E_HIP 2          /* a HIP runtime call failed                      */
 #define SPL_E_OOM 3          /* host allocation failed or workspace too small  */
 #define SPL_E_CAPACITY 4     /* a result exceeded the capacity given           */
-#define SPL_E_UNSUPPORTED 5  /* valid input this build cannot process exactly  */
+#define SPL_E_UNSUPPORTED 5  /* valid input the library cannot process exactly */
 #define SPL_E_NO_WEIGHTS 6   /* the ranker has no weights: use the plain path  */
 #define SPL_E_INTERNAL 7
 
