@@ -235,7 +235,7 @@ def make_block_torch(spec: BlockSpec, seed: int, beam: int = 0, widths=(1, 2, 4,
 
 
 # --------------------------------------------------------------------------
-# Workload recipes (the five workloads of the build: stand-ins for uGMRT data)
+# Workload recipes (the benchmark and test workloads: stand-ins for uGMRT data)
 # --------------------------------------------------------------------------
 def pulses_evenly(rng: np.random.Generator, n: int, n_out: int, dm_lo: float, dm_hi: float,
                   fwhm_lo: float, fwhm_hi: float, snr_lo: float, snr_hi: float):

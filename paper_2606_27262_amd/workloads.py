@@ -1,4 +1,4 @@
-"""The five workloads of the build, as plan parameters plus a seeded input recipe.
+"""The benchmark and test workloads, as plan parameters plus a seeded input recipe.
 
 Shapes follow the paper's setting (8-bit samples, uGMRT Band 3 300-500 MHz and
 Band 4 550-750 MHz, 1.31072 ms sampling, DM up to 2000 and beyond, boxcar
